@@ -1,0 +1,198 @@
+"""Seeded synthetic inputs for the TC2 / TC2-CPSCF response solver.
+
+This module only *draws* inputs: atom positions, a block-sparse Hamiltonian H
+in an orthonormal basis, the electric-field perturbation H1 (position
+operator), and the occupation count.  It holds none of the method's
+arithmetic, so that both the CPU oracle and the GPU path can be fed the very
+same matrices.
+
+Recipe (stand-in for the paper's FHI-aims Hamiltonians of H(C2H4)nH chains
+and molecules, Sec. 3, which are not available):
+
+* atoms on a 1D chain or a simple-cubic lattice with spacing ``a``;
+* ``b`` orbitals per atom; the onsite block is diagonal, -1 for the first
+  ``occ_per_atom`` orbitals and +1 for the rest;
+* for every unordered atom pair I < J with distance r <= cutoff, an off-site
+  block with entries U(-amp, amp) * exp(-r / decay) is drawn (pairs in
+  row-major (I, J) order, entries row-major), and H_JI = H_IJ^T;
+* H1_d = blockdiag((x_{I,d} - mean_d) * 1_b), the position operator of the
+  homogeneous field (Sec. 2.1) in the point-atom approximation, centred.
+
+Random numbers come from ``numpy.random.default_rng(seed)`` (PCG64).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "BSR", "System", "chain_positions", "cubic_positions", "make_system",
+    "config_system", "batch_systems", "CONFIGS",
+]
+
+
+@dataclass
+class BSR:
+    """Square block-sparse matrix with uniform b x b blocks.
+
+    ``row_ptr`` (int64, nb+1), ``col`` (int32, nnzb, strictly increasing per
+    row) and ``val`` (float64, nnzb x b x b, each block row-major).  The
+    pattern is the full (both triangles) pattern.
+    """
+    nb: int
+    b: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+    @property
+    def nnzb(self) -> int:
+        return int(self.row_ptr[-1])
+
+    @property
+    def n(self) -> int:
+        return self.nb * self.b
+
+
+@dataclass
+class System:
+    H: BSR
+    H1: List[BSR]
+    n_occ: int
+    xyz: np.ndarray            # (nb, 3) atom positions
+    eps: float = 1e-6          # block drop threshold
+    tol: float = 1e-9          # convergence tolerance
+    max_iter: int = 100
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+
+def chain_positions(n_atoms: int, spacing: float = 1.0) -> np.ndarray:
+    xyz = np.zeros((n_atoms, 3))
+    xyz[:, 0] = spacing * np.arange(n_atoms)
+    return xyz
+
+
+def cubic_positions(L: int, spacing: float = 2.5, n_first: Optional[int] = None) -> np.ndarray:
+    """Sites of an L x L x L simple-cubic lattice in row-major (x slowest)
+    order; optionally only the first ``n_first`` of them."""
+    g = np.arange(L, dtype=np.float64) * spacing
+    x, y, z = np.meshgrid(g, g, g, indexing="ij")
+    xyz = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    if n_first is not None:
+        xyz = xyz[:n_first]
+    return np.ascontiguousarray(xyz)
+
+
+def _pairs_within(xyz: np.ndarray, cutoff: float) -> np.ndarray:
+    """All (I, J) with I < J and |x_I - x_J| <= cutoff, row-major order."""
+    from scipy.spatial import cKDTree
+    tree = cKDTree(xyz)
+    # a tiny slack so that exact lattice distances equal to the cutoff count
+    pairs = tree.query_pairs(cutoff * (1.0 + 1e-12), output_type="ndarray")
+    if len(pairs) == 0:
+        return np.zeros((0, 2), dtype=np.int64)
+    pairs = np.sort(pairs, axis=1)
+    order = np.lexsort((pairs[:, 1], pairs[:, 0]))
+    return pairs[order].astype(np.int64)
+
+
+def _assemble(nb: int, b: int, pairs: np.ndarray, offblocks: np.ndarray,
+              diagblocks: np.ndarray) -> BSR:
+    """Full symmetric-pattern BSR from diagonal blocks and upper off-site
+    blocks (the lower ones are their transposes)."""
+    npair = len(pairs)
+    rows = np.concatenate([np.arange(nb), pairs[:, 0], pairs[:, 1]])
+    cols = np.concatenate([np.arange(nb), pairs[:, 1], pairs[:, 0]])
+    vals = np.concatenate([diagblocks, offblocks,
+                           np.transpose(offblocks, (0, 2, 1))]) if npair else diagblocks
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    row_ptr = np.zeros(nb + 1, dtype=np.int64)
+    np.add.at(row_ptr, rows + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    return BSR(nb, b, row_ptr, cols.astype(np.int32),
+               np.ascontiguousarray(vals, dtype=np.float64))
+
+
+def make_system(xyz: np.ndarray, b: int, occ_per_atom: int, cutoff: float,
+                seed: int, n_dir: int = 1, amp: float = 0.3,
+                decay: float = 1.5, eps: float = 1e-6, tol: float = 1e-9,
+                max_iter: int = 100, name: str = "") -> System:
+    xyz = np.asarray(xyz, dtype=np.float64)
+    nb = len(xyz)
+    rng = np.random.default_rng(seed)
+    pairs = _pairs_within(xyz, cutoff)
+    r = np.linalg.norm(xyz[pairs[:, 0]] - xyz[pairs[:, 1]], axis=1) if len(pairs) else np.zeros(0)
+    off = rng.uniform(-amp, amp, size=(len(pairs), b, b))
+    off *= np.exp(-r / decay)[:, None, None]
+    onsite = np.diag(np.concatenate([-np.ones(occ_per_atom), np.ones(b - occ_per_atom)]))
+    diag = np.broadcast_to(onsite, (nb, b, b)).copy()
+    H = _assemble(nb, b, pairs, off, diag)
+    H1 = []
+    centre = xyz.mean(axis=0)
+    eye = np.eye(b)
+    for d in range(n_dir):
+        x = xyz[:, d] - centre[d]
+        blocks = x[:, None, None] * eye[None, :, :]
+        H1.append(BSR(nb, b, np.arange(nb + 1, dtype=np.int64),
+                      np.arange(nb, dtype=np.int32), np.ascontiguousarray(blocks)))
+    return System(H=H, H1=H1, n_occ=occ_per_atom * nb, xyz=xyz, eps=eps,
+                  tol=tol, max_iter=max_iter, name=name,
+                  meta=dict(b=b, occ_per_atom=occ_per_atom, cutoff=cutoff,
+                            seed=seed, amp=amp, decay=decay))
+
+
+# Named workloads.  Readings of what the paper leaves open (lattice spacing,
+# occupation for b = 13, tolerances) are fixed here and listed in the design
+# notes.
+CONFIGS = {
+    # 64-atom chain, b = 8, N = 512, one direction
+    "chain64": dict(kind="chain", n=64, spacing=1.0, b=8, occ=4, cutoff=4.0,
+                    n_dir=1, eps=1e-7, tol=1e-9, seed=1),
+    # 10^3 cube, b = 13, N = 13000, one direction
+    "cube10": dict(kind="cube", L=10, spacing=2.5, b=13, occ=4, cutoff=3.0,
+                   n_dir=1, eps=1e-6, tol=1e-9, seed=2),
+    # 20^3 cube, N = 104000, three directions
+    "cube20": dict(kind="cube", L=20, spacing=2.5, b=13, occ=4, cutoff=3.0,
+                   n_dir=3, eps=1e-6, tol=1e-9, seed=3),
+    # 30^3 cube, N = 351000, three directions
+    "cube30": dict(kind="cube", L=30, spacing=2.5, b=13, occ=4, cutoff=3.0,
+                   n_dir=3, eps=1e-5, tol=1e-9, seed=5),
+}
+
+
+def config_system(name: str, **override) -> System:
+    """Build a named workload; keyword overrides (e.g. ``L=4``) shrink it."""
+    c = dict(CONFIGS[name])
+    c.update(override)
+    if c["kind"] == "chain":
+        xyz = chain_positions(c["n"], c["spacing"])
+    else:
+        xyz = cubic_positions(c["L"], c["spacing"], c.get("n_first"))
+    return make_system(xyz, c["b"], c["occ"], c["cutoff"], c["seed"],
+                       n_dir=c["n_dir"], eps=c["eps"], tol=c["tol"],
+                       name=name)
+
+
+def batch_systems(n_sys: int = 32, lo: int = 200, hi: int = 4000, seed: int = 4,
+                  b: int = 13, n_dir: int = 3, eps: float = 1e-6,
+                  tol: float = 1e-9, spacing: float = 2.5,
+                  sizes: Optional[Sequence[int]] = None) -> List[System]:
+    """Independent systems of uneven size: n_k atoms drawn uniformly in
+    [lo, hi]; system k is the first n_k sites (row-major) of the smallest
+    cube holding them, with its own seed 1000*seed + k."""
+    if sizes is None:
+        sizes = np.random.default_rng(seed).integers(lo, hi + 1, n_sys)
+    out = []
+    for k, n in enumerate(sizes):
+        n = int(n)
+        L = int(np.ceil(n ** (1.0 / 3.0) - 1e-9))
+        while L ** 3 < n:
+            L += 1
+        xyz = cubic_positions(L, spacing, n_first=n)
+        out.append(make_system(xyz, b, 4, 3.0, 1000 * seed + k, n_dir=n_dir,
+                               eps=eps, tol=tol, name=f"batch{k}"))
+    return out
