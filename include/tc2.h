@@ -1,0 +1,142 @@
+/*
+ * tc2.h - C ABI of the MI355X (gfx950) TC2 / TC2-CPSCF response solver.
+ *
+ * The library purifies the zero-order density matrix X0 of a Hamiltonian H
+ * given in an orthonormal atom-block basis with the second-order
+ * trace-correcting recursion (Sec. 2.3, Eq. TC2), and, coupled with it, the
+ * first-order response X1 to a homogeneous electric field (Sec. 2.3,
+ * Eq. TC2-CPSCF):
+ *
+ *   X0 <- (emax*I - H)/(emax - emin),  X1_d <- -H1_d/(emax - emin)
+ *   repeat:  if Tr X0 >= Nocc:  X0 <- X0 X0,        X1_d <- X1_d X0 + X0 X1_d
+ *            else:              X0 <- 2X0 - X0 X0,  X1_d <- 2X1_d - X1_d X0 - X0 X1_d
+ *            drop every off-diagonal atom block whose Frobenius norm is < eps
+ *                                     (filter of Sec. 2.4, made block-wise)
+ *   until the band energies Tr(X0 H), Tr(X1_d H) and the traces
+ *   Tr(X1_d H1_d) change by less than tol (tolerance of Sec. 2.4).
+ *
+ * emin/emax are Gershgorin bounds of H (Sec. 2.3).  Each iteration is a
+ * truncated block-sparse product (symbolic pattern, numeric block products
+ * X0X0, X0X1, X1X0 on MFMA, norm drop, trace reduction choosing the next
+ * branch), all in HIP kernels on one GPU.  Several independent systems can be
+ * solved in one call (one merged launch per iteration step).
+ *
+ * Conventions
+ *  - Matrices are square, block-sparse (BSR) with uniform b x b blocks,
+ *    1 <= b <= 16.  row_ptr has nb+1 int64 entries, col has nnzb int32
+ *    entries strictly increasing within each row, val has nnzb*b*b doubles,
+ *    each block row-major.  The FULL pattern (both triangles) is given and it
+ *    must be symmetric; values must be symmetric (H_JI = H_IJ^T), which the
+ *    library assumes and does not check beyond the pattern.
+ *  - All pointers passed to tc2_setup are HOST pointers owned by the caller;
+ *    tc2_setup copies what it needs, so they may be freed when it returns.
+ *  - Every entry point returns a status; no C++ exception crosses the ABI.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef TC2_H
+#define TC2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TC2_API __attribute__((visibility("default")))
+
+typedef enum {
+  TC2_OK = 0,
+  TC2_NOT_CONVERGED = 1,   /* max_iter reached; results are the last iterate  */
+  TC2_FLOOR_REACHED = 2,   /* stopped by the stall guard (precision floor)     */
+  TC2_EINVAL = -1,         /* malformed argument or option                     */
+  TC2_ENOMEM = -2,         /* device or host allocation failed                 */
+  TC2_EDEVICE = -3,        /* no usable gfx950 device, or a HIP call failed    */
+  TC2_ENONSYM = -4,        /* pattern not symmetric or a diagonal block missing */
+  TC2_EDEGENERATE = -5,    /* emax == emin while 0 < Nocc < N                 */
+  TC2_ENAN = -6,           /* NaN/Inf in the input or produced by an iteration */
+  TC2_EOVERFLOW = -7       /* a size exceeds the library's index range         */
+} tc2_status;
+
+typedef struct {
+  int32_t nb;              /* block rows (atoms); N = nb*b                      */
+  int32_t b;               /* block dimension, 1..16                             */
+  const int64_t *row_ptr;  /* nb+1, row_ptr[0] = 0                               */
+  const int32_t *col;      /* nnzb = row_ptr[nb]                                 */
+  const double *val;       /* nnzb*b*b                                           */
+} tc2_bsr;
+
+typedef struct {
+  tc2_bsr H;               /* ground-state Hamiltonian, orthonormal basis        */
+  int32_t n_dir;           /* number of perturbations (field directions), 0..3   */
+  tc2_bsr H1[3];           /* first-order Hamiltonians; same nb and b as H       */
+  int64_t n_occ;           /* occupied states, 0..N                              */
+  double eps_drop;         /* block drop threshold, >= 0                         */
+  double tol;              /* band-energy convergence tolerance, > 0             */
+  int32_t max_iter;        /* 1..TC2_MAX_ITER                                    */
+  const char *replay;      /* NULL, or a string of 'S'/'D' forcing each step's
+                              branch (exactly strlen(replay) steps are run)    */
+} tc2_problem;
+
+#define TC2_MAX_ITER 200
+
+enum { TC2_FP64 = 0, TC2_FP32 = 1, TC2_BF16 = 2 };
+
+typedef struct {
+  int32_t precision;       /* TC2_FP64 / TC2_FP32 / TC2_BF16 block products      */
+  int32_t closing_fp64;    /* 0, or 2: finish a reduced-precision solve with two
+                              FP64 steps of opposite branches                  */
+  int32_t skip;            /* 0: no screening (all candidate blocks computed)    */
+  int32_t device;          /* HIP device ordinal                                 */
+  int32_t export_matrices; /* 1: tc2_run copies X0/X1 back to host views         */
+  int32_t verbose;         /* 1: per-iteration log on stderr                     */
+} tc2_options;
+
+typedef struct {
+  tc2_status status;
+  int32_t iters;           /* updates performed (including closing steps)        */
+  double trace_x1h1[3];    /* Tr(X1_d H1_d), the raw polarizability trace        */
+  double tr_x0;            /* Tr X0                                              */
+  double idem_err;         /* Tr X0 - ||X0||_F^2                                 */
+  double tr_x1[3];         /* Tr X1_d                                            */
+  double e0;               /* Tr(X0 H)                                           */
+  double e1[3];            /* Tr(X1_d H)                                         */
+  double emin, emax;       /* Gershgorin bounds                                  */
+  double seconds;          /* device time of the solve                           */
+  double useful_flops;     /* 2 b^3 per block triple landing on a kept block     */
+  double executed_flops;   /* MFMA flops issued, padding included                */
+  char branches[TC2_MAX_ITER + 4]; /* 'S'/'D' per update, NUL-terminated        */
+  /* Library-owned host copies (valid until the next tc2_run or tc2_free) when
+     export_matrices = 1; same layout as the inputs.  Otherwise zeroed. */
+  tc2_bsr X0;
+  tc2_bsr X1[3];
+} tc2_result;
+
+typedef struct tc2_ctx tc2_ctx;
+
+/* Validate n_problems >= 1 problems (they must share b and n_dir), copy them
+ * to the device and prepare one solver context.  *out is NULL on failure.
+ * Errors: TC2_EINVAL (argument ranges, b mismatch, bad BSR ordering),
+ * TC2_ENONSYM, TC2_ENAN, TC2_EDEGENERATE (checked on the device once emin and
+ * emax are known, at tc2_run), TC2_EDEVICE, TC2_ENOMEM, TC2_EOVERFLOW. */
+TC2_API tc2_status tc2_setup(const tc2_problem *problems, int32_t n_problems,
+                     const tc2_options *opts, tc2_ctx **out);
+
+/* Run the solve for every problem of the context on hip_stream (a
+ * hipStream_t; NULL means the library's own stream).  res points to
+ * n_problems results.  Returns the worst status over the problems (errors
+ * before warnings).  May be called again; each call restarts from H. */
+TC2_API tc2_status tc2_run(tc2_ctx *ctx, void *hip_stream, tc2_result *res);
+
+/* Release the context and everything it owns.  NULL-safe. */
+TC2_API void tc2_free(tc2_ctx *ctx);
+
+/* Static description of a status code. */
+TC2_API const char *tc2_strerror(tc2_status s);
+
+/* Library version string. */
+TC2_API const char *tc2_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TC2_H */

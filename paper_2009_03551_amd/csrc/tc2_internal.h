@@ -1,0 +1,152 @@
+// Internal declarations shared by the TC2 runtime and its kernels.
+//
+// Device data layout (one merged block-diagonal matrix for a batch of
+// systems; every system has nb_s atom rows, all with the same block size b):
+//
+//  * pattern: int32 row pointer rp[nb+1] and sorted column indices ci[nnz]
+//    holding BOTH triangles of the symmetric pattern;
+//  * values: for entry e and matrix m (m = 0 for X0, 1..D for X1_d) one
+//    padded 16 x 16 tile at ((e*(1+D) + m) * 256), stored COLUMN-major
+//    (element (r, c) at c*16 + r) and zero outside the b x b corner.  With
+//    this layout the MFMA A and B fragments of a block product are single
+//    contiguous 64-lane loads (see the numeric kernel);
+//  * H and H1_d are stored the same way (one matrix per value array).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tc2 {
+
+constexpr int BP = 16;        // padded block dimension
+constexpr int BS = BP * BP;   // elements per padded block
+constexpr int MAXD = 3;       // field directions
+constexpr int NQ = 4 + 3 * MAXD;  // per-work-item partial sums (see Q_*)
+constexpr int CHUNK = 32;     // candidates per numeric work item
+constexpr int MAX_SYS_BITS = 1 << 19;  // atoms per system (symbolic bitmap)
+
+// partial-sum slots
+enum {
+  Q_TR0 = 0,   // Tr X0
+  Q_FRO0 = 1,  // ||X0||_F^2
+  Q_E0 = 2,    // Tr(X0 H)
+  Q_TRIP = 3,  // block triples landing on kept output blocks
+  Q_TR1 = 4,   // Tr X1_d           (4 .. 4+D-1)
+  Q_E1 = 4 + MAXD,       // Tr(X1_d H)
+  Q_AL = 4 + 2 * MAXD,   // Tr(X1_d H1_d)
+};
+
+enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
+
+struct SymArgs {
+  int nb;
+  const int* rp;        // current pattern
+  const int* ci;
+  const int* sys_of;    // row -> system
+  const int* sys_end;   // system -> one past its last row
+  const int* active;    // system -> 1 while iterating
+  const int* cand_rp;   // fill pass only
+  int* cand_cnt;        // count pass output (nb)
+  int* cand_ci;         // fill pass output
+  int max_sys_atoms;    // largest system (LDS bitmap size)
+};
+
+struct MeasArgs {
+  int nb;
+  int D;
+  const int* rp;
+  const int* ci;
+  const void* xv;
+  const int* h_rp;
+  const int* h_ci;
+  const double* h_v;
+  const int* h1_rp[MAXD];
+  const int* h1_ci[MAXD];
+  const double* h1_v[MAXD];
+  double* partial;      // nb x NQ
+};
+
+struct NumArgs {
+  int nb;
+  int D;
+  int b;
+  int ksteps;               // ceil(b/4): K-steps of 4 in the padded tile
+  const int* rp;            // current pattern
+  const int* ci;
+  const void* xv;           // current values (T)
+  const int* cand_rp;       // upper-triangle candidates
+  const int* cand_ci;
+  const int* item_row;      // work item -> row
+  const int* item_c0;       // work item -> first candidate
+  int n_items;
+  const int* sys_of;
+  const int* active;
+  const int* branch;        // system -> 1 SQUARE, 0 DOUBLE
+  const double* eps;        // system -> drop threshold
+  // H and H1 (for the band energies and alpha), FP64 padded column-major
+  const int* h_rp;
+  const int* h_ci;
+  const double* h_v;
+  const int* h1_rp[MAXD];
+  const int* h1_ci[MAXD];
+  const double* h1_v[MAXD];
+  // outputs
+  void* stage;              // kept upper blocks, row-major tiles (T)
+  int2* kept_ij;            // slot -> (I, J)
+  int* stage_count;         // atomic slot counter
+  int stage_cap;
+  int* overflow;            // set when stage_count would exceed stage_cap
+  int* bad;                 // set when a NaN/Inf is produced
+  double* partial;          // n_items x NQ
+  unsigned long long* exec_pairs;  // block triples issued (all candidates)
+};
+
+struct CompactArgs {
+  int nb;
+  int D;
+  const int* stage_count;
+  const int2* kept_ij;
+  int* rowcnt;        // nb (zeroed)
+  int* cursor;        // nb (zeroed)
+  const int* new_rp;  // nb+1
+  int* tmp_ci;
+  int* tmp_src;
+  int* new_ci;
+  int* new_src;
+  const int* sys_of;
+  const int* sys_start;
+  const int* sys_end;
+  int max_sys_atoms;
+};
+
+// kernels (launch wrappers), all asynchronous on `st`
+void launch_gershgorin(hipStream_t st, int nb, int b, const int* rp, const int* ci,
+                       const double* hv, double* rowlo, double* rowhi);
+void launch_sys_minmax(hipStream_t st, int nsys, const int* sys_start, const int* sys_end,
+                       int b, const double* rowlo, const double* rowhi, double* emin, double* emax);
+void launch_init(hipStream_t st, int prec, int nnz, int D, int b, const int* row_of,
+                 const int* ci, const int* src_h, const int* const* src_h1,
+                 const double* hv, const double* const* h1v, const int* sys_of,
+                 const double* emin, const double* emax, const int* mode, void* xv);
+void launch_symbolic(hipStream_t st, int pass, const SymArgs& a);
+void launch_scan(hipStream_t st, int n, const int* in, int* out, int* total);
+void launch_items(hipStream_t st, int nb, const int* cand_rp, const int* item_rp,
+                  int* item_row, int* item_c0);
+void launch_items_count(hipStream_t st, int nb, const int* cand_rp, int* item_cnt);
+void launch_numeric(hipStream_t st, int prec, const NumArgs& a);
+void launch_measure(hipStream_t st, int prec, const MeasArgs& a);
+void launch_compact_count(hipStream_t st, const CompactArgs& a, int n_kept);
+void launch_compact_scatter(hipStream_t st, const CompactArgs& a, int n_kept);
+void launch_row_sort(hipStream_t st, const CompactArgs& a);
+void launch_gather(hipStream_t st, int prec, int nnz, int D, const int* new_src,
+                   const void* stage, void* xv);
+void launch_reduce(hipStream_t st, int nsys, const int* sys_item_lo, const int* sys_item_hi,
+                   const double* partial, double* scal);
+void launch_sys_items(hipStream_t st, int nsys, const int* sys_start, const int* sys_end,
+                      const int* item_rp, int* lo, int* hi);
+void launch_export(hipStream_t st, int prec, int nnz, int D, int m, int b, const void* xv,
+                   double* out);
+void launch_convert(hipStream_t st, int from_prec, int to_prec, long long n, const void* in,
+                    void* out);
+void launch_fill_int(hipStream_t st, int* p, int v, long long n);
+
+}  // namespace tc2

@@ -1,0 +1,854 @@
+// Host runtime of the TC2 / TC2-CPSCF solver: the C ABI of include/tc2.h.
+//
+// tc2_setup validates and uploads the problems (a batch is merged into one
+// block-diagonal matrix with a system id per atom row); tc2_run drives the
+// recursion of Sec. 2.3 (Eq. TC2 coupled with Eq. TC2-CPSCF) on the device,
+// one merged kernel sequence per update, and applies the stopping rule of
+// Sec. 2.4 (band-energy change below the tolerance) per system.
+#include "tc2_internal.h"
+#include "../../include/tc2.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace tc2;
+
+namespace {
+
+// ------------------------------------------------------------------ device buffers
+struct DBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  // grow to at least n bytes (contents are not preserved)
+  hipError_t reserve(size_t n) {
+    if (n <= cap && p) return hipSuccess;
+    release();
+    size_t want = std::max<size_t>(n, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    cap = want;
+    return hipSuccess;
+  }
+  template <typename T> T* as() const { return (T*)p; }
+};
+
+struct HostBsr {
+  std::vector<int64_t> row_ptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+struct SysInfo {
+  int row0 = 0, nb = 0;
+  int64_t n_occ = 0;
+  double eps = 0, tol = 0;
+  int max_iter = 0;
+  std::string replay;
+  int mode = 0;  // 0 iterate, 1 trivial zero (Nocc = 0), 2 trivial identity (Nocc = N)
+};
+
+struct SysState {
+  bool active = false;
+  int k = 0;
+  double prev[1 + 2 * MAXD] = {0};
+  std::vector<double> iota;
+  std::string branches;
+  int closing_left = 0;
+  int closing_first = 1;
+  tc2_status status = TC2_OK;
+  double trip = 0;
+};
+
+}  // namespace
+
+struct tc2_ctx {
+  int device = 0;
+  hipStream_t own = nullptr;
+  int nsys = 0, D = 0, b = 0, nb = 0, prec = P_FP64, closing = 0, verbose = 0, export_m = 0;
+  int max_sys_atoms = 0;
+  std::vector<SysInfo> sys;
+  // host copies kept for export
+  std::vector<int> h_sys_of;
+  // device: systems
+  DBuf sys_of, sys_start, sys_end, active, branch, mode, eps, emin, emax, bad;
+  // device: H and H1
+  DBuf h_rp, h_ci, h_v;
+  DBuf h1_rp[MAXD], h1_ci[MAXD], h1_v[MAXD];
+  // initial pattern (union of H and H1 patterns) and its sources
+  int nnz0 = 0;
+  DBuf x0_rp, x0_ci, x0_row, src_h, src_h1[MAXD];
+  // iterate (double buffered)
+  DBuf rp[2], ci[2], xv[2];
+  int nnz[2] = {0, 0};
+  int cur = 0;
+  int cur_prec = P_FP64;
+  // work buffers
+  DBuf cand_cnt, cand_rp, cand_ci, item_cnt, item_rp, item_row, item_c0, partial;
+  DBuf stage, kept_ij, counters, exec_pairs, rowcnt, cursor, tmp_ci, tmp_src, new_src;
+  DBuf sys_lo, sys_hi, scal, rowlo, rowhi, xfer;
+  int stage_cap = 0;
+  // results
+  std::vector<HostBsr> out_x0;
+  std::vector<HostBsr> out_x1[MAXD];
+};
+
+namespace {
+
+#define HIPCHK(x)                                                        \
+  do {                                                                   \
+    hipError_t e_ = (x);                                                 \
+    if (e_ != hipSuccess) {                                              \
+      if (ctx && ctx->verbose)                                           \
+        fprintf(stderr, "tc2: %s failed: %s\n", #x, hipGetErrorString(e_)); \
+      return e_ == hipErrorOutOfMemory ? TC2_ENOMEM : TC2_EDEVICE;       \
+    }                                                                    \
+  } while (0)
+
+size_t prec_bytes(int prec) { return prec == P_FP64 ? 8 : 4; }
+
+tc2_status validate_bsr(const tc2_bsr& m, int nb, int b) {
+  if (m.nb != nb || m.b != b) return TC2_EINVAL;
+  if (!m.row_ptr || (!m.col && m.row_ptr[nb] > 0) || (!m.val && m.row_ptr[nb] > 0)) return TC2_EINVAL;
+  if (m.row_ptr[0] != 0) return TC2_EINVAL;
+  for (int i = 0; i < nb; ++i) {
+    if (m.row_ptr[i + 1] < m.row_ptr[i]) return TC2_EINVAL;
+    for (int64_t p = m.row_ptr[i]; p < m.row_ptr[i + 1]; ++p) {
+      if (m.col[p] < 0 || m.col[p] >= nb) return TC2_EINVAL;
+      if (p > m.row_ptr[i] && m.col[p] <= m.col[p - 1]) return TC2_EINVAL;
+    }
+  }
+  if (m.row_ptr[nb] > (int64_t)0x7fffffff / 2) return TC2_EOVERFLOW;
+  // symmetric pattern
+  for (int i = 0; i < nb; ++i)
+    for (int64_t p = m.row_ptr[i]; p < m.row_ptr[i + 1]; ++p) {
+      int j = m.col[p];
+      const int32_t* b0 = m.col + m.row_ptr[j];
+      const int32_t* b1 = m.col + m.row_ptr[j + 1];
+      if (!std::binary_search(b0, b1, i)) return TC2_ENONSYM;
+    }
+  int64_t nv = m.row_ptr[nb] * (int64_t)b * b;
+  for (int64_t k = 0; k < nv; ++k)
+    if (!std::isfinite(m.val[k])) return TC2_ENAN;
+  return TC2_OK;
+}
+
+bool has_diag(const tc2_bsr& m, int nb) {
+  for (int i = 0; i < nb; ++i)
+    if (!std::binary_search(m.col + m.row_ptr[i], m.col + m.row_ptr[i + 1], i)) return false;
+  return true;
+}
+
+// padded, column-major device image of a batch of BSR matrices (FP64)
+void pack_blocks(const tc2_bsr& m, int b, std::vector<double>& out) {
+  int64_t nnz = m.row_ptr[m.nb];
+  size_t off = out.size();
+  out.resize(off + (size_t)nnz * BS, 0.0);
+  for (int64_t e = 0; e < nnz; ++e)
+    for (int r = 0; r < b; ++r)
+      for (int c = 0; c < b; ++c)
+        out[off + (size_t)e * BS + c * BP + r] = m.val[(e * b + r) * b + c];
+}
+
+template <typename T>
+tc2_status upload(tc2_ctx* ctx, DBuf& d, const std::vector<T>& h) {
+  HIPCHK(d.reserve(h.size() * sizeof(T)));
+  if (!h.empty()) HIPCHK(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return TC2_OK;
+}
+
+// merged row pointer / columns (int32) of a matrix family over the batch
+void merge_pattern(const std::vector<const tc2_bsr*>& ms, const std::vector<SysInfo>& sys,
+                   std::vector<int>& rp, std::vector<int>& ci) {
+  rp.assign(1, 0);
+  ci.clear();
+  for (size_t s = 0; s < ms.size(); ++s) {
+    const tc2_bsr* m = ms[s];
+    for (int i = 0; i < m->nb; ++i) {
+      for (int64_t p = m->row_ptr[i]; p < m->row_ptr[i + 1]; ++p) ci.push_back(sys[s].row0 + m->col[p]);
+      rp.push_back((int)ci.size());
+    }
+  }
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* tc2_version(void) { return "tc2-mi355x 0.1 (gfx950)"; }
+
+const char* tc2_strerror(tc2_status s) {
+  switch (s) {
+    case TC2_OK: return "ok";
+    case TC2_NOT_CONVERGED: return "not converged within max_iter";
+    case TC2_FLOOR_REACHED: return "stopped at the precision floor (stall guard)";
+    case TC2_EINVAL: return "invalid argument";
+    case TC2_ENOMEM: return "out of memory";
+    case TC2_EDEVICE: return "device error or no gfx950 device";
+    case TC2_ENONSYM: return "pattern not symmetric or diagonal block missing";
+    case TC2_EDEGENERATE: return "degenerate spectrum bounds (emax == emin)";
+    case TC2_ENAN: return "NaN or Inf encountered";
+    case TC2_EOVERFLOW: return "size exceeds the index range";
+  }
+  return "unknown status";
+}
+
+void tc2_free(tc2_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->own) (void)hipStreamDestroy(ctx->own);
+  delete ctx;
+}
+
+static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_options* o,
+                             tc2_ctx** out) {
+  tc2_ctx* ctx = nullptr;
+  if (!out) return TC2_EINVAL;
+  *out = nullptr;
+  if (!probs || np < 1 || !o) return TC2_EINVAL;
+  if (o->precision < 0 || o->precision > 2) return TC2_EINVAL;
+  if (o->closing_fp64 != 0 && o->closing_fp64 != 2) return TC2_EINVAL;
+  if (o->skip != 0) return TC2_EINVAL;
+  if (o->precision == P_BF16) return TC2_EINVAL;  // not available yet
+  const int b = probs[0].H.b, D = probs[0].n_dir;
+  if (b < 1 || b > BP || D < 0 || D > MAXD) return TC2_EINVAL;
+  int64_t nb_tot = 0;
+  int max_atoms = 0;
+  for (int s = 0; s < np; ++s) {
+    const tc2_problem& p = probs[s];
+    if (p.H.b != b || p.n_dir != D) return TC2_EINVAL;
+    if (p.H.nb < 1) return TC2_EINVAL;
+    if (!(p.eps_drop >= 0.0) || !(p.tol > 0.0) || !std::isfinite(p.eps_drop)) return TC2_EINVAL;
+    if (p.max_iter < 1 || p.max_iter > TC2_MAX_ITER) return TC2_EINVAL;
+    int64_t N = (int64_t)p.H.nb * b;
+    if (p.n_occ < 0 || p.n_occ > N) return TC2_EINVAL;
+    if (p.replay) {
+      size_t L = strlen(p.replay);
+      if (L < 1 || L > TC2_MAX_ITER) return TC2_EINVAL;
+      for (size_t k = 0; k < L; ++k)
+        if (p.replay[k] != 'S' && p.replay[k] != 'D') return TC2_EINVAL;
+    }
+    tc2_status st = validate_bsr(p.H, p.H.nb, b);
+    if (st != TC2_OK) return st;
+    if (!has_diag(p.H, p.H.nb)) return TC2_ENONSYM;
+    for (int d = 0; d < D; ++d) {
+      st = validate_bsr(p.H1[d], p.H.nb, b);
+      if (st != TC2_OK) return st;
+    }
+    nb_tot += p.H.nb;
+    max_atoms = std::max(max_atoms, p.H.nb);
+  }
+  if (nb_tot > (1 << 26) || max_atoms > MAX_SYS_BITS) return TC2_EOVERFLOW;
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TC2_EDEVICE;
+  if (o->device < 0 || o->device >= ndev) return TC2_EDEVICE;
+  if (hipSetDevice(o->device) != hipSuccess) return TC2_EDEVICE;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, o->device) != hipSuccess) return TC2_EDEVICE;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TC2_EDEVICE;
+  }
+
+  ctx = new (std::nothrow) tc2_ctx();
+  if (!ctx) return TC2_ENOMEM;
+  ctx->device = o->device;
+  ctx->nsys = np;
+  ctx->D = D;
+  ctx->b = b;
+  ctx->nb = (int)nb_tot;
+  ctx->prec = o->precision;
+  ctx->closing = o->closing_fp64;
+  ctx->verbose = o->verbose;
+  ctx->export_m = o->export_matrices;
+  ctx->max_sys_atoms = max_atoms;
+  tc2_status st = TC2_OK;
+  auto fail = [&](tc2_status s) {
+    tc2_free(ctx);
+    return s;
+  };
+  if (hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess) return fail(TC2_EDEVICE);
+
+  // systems
+  std::vector<int> sys_of(nb_tot), sys_start(np), sys_end(np), mode(np);
+  std::vector<double> eps(np);
+  int row = 0;
+  ctx->sys.resize(np);
+  for (int s = 0; s < np; ++s) {
+    const tc2_problem& p = probs[s];
+    SysInfo& si = ctx->sys[s];
+    si.row0 = row;
+    si.nb = p.H.nb;
+    si.n_occ = p.n_occ;
+    si.eps = p.eps_drop;
+    si.tol = p.tol;
+    si.max_iter = p.max_iter;
+    if (p.replay) si.replay = p.replay;
+    int64_t N = (int64_t)p.H.nb * b;
+    si.mode = p.n_occ == 0 ? 1 : (p.n_occ == N ? 2 : 0);
+    for (int i = 0; i < p.H.nb; ++i) sys_of[row + i] = s;
+    sys_start[s] = row;
+    sys_end[s] = row + p.H.nb;
+    mode[s] = si.mode;
+    eps[s] = p.eps_drop;
+    row += p.H.nb;
+  }
+  ctx->h_sys_of = sys_of;
+  if ((st = upload(ctx, ctx->sys_of, sys_of)) != TC2_OK) return fail(st);
+  if ((st = upload(ctx, ctx->sys_start, sys_start)) != TC2_OK) return fail(st);
+  if ((st = upload(ctx, ctx->sys_end, sys_end)) != TC2_OK) return fail(st);
+  if ((st = upload(ctx, ctx->mode, mode)) != TC2_OK) return fail(st);
+  if ((st = upload(ctx, ctx->eps, eps)) != TC2_OK) return fail(st);
+  std::vector<int> zeros(np, 0);
+  if ((st = upload(ctx, ctx->active, zeros)) != TC2_OK) return fail(st);
+  if ((st = upload(ctx, ctx->branch, zeros)) != TC2_OK) return fail(st);
+  if ((st = upload(ctx, ctx->bad, zeros)) != TC2_OK) return fail(st);
+  if (ctx->emin.reserve(np * 8) || ctx->emax.reserve(np * 8)) return fail(TC2_ENOMEM);
+
+  // H, H1 merged
+  std::vector<const tc2_bsr*> hs(np);
+  for (int s = 0; s < np; ++s) hs[s] = &probs[s].H;
+  std::vector<int> rp, ci;
+  std::vector<double> vals;
+  merge_pattern(hs, ctx->sys, rp, ci);
+  for (int s = 0; s < np; ++s) pack_blocks(probs[s].H, b, vals);
+  if ((st = upload(ctx, ctx->h_rp, rp)) != TC2_OK) return fail(st);
+  if ((st = upload(ctx, ctx->h_ci, ci)) != TC2_OK) return fail(st);
+  if ((st = upload(ctx, ctx->h_v, vals)) != TC2_OK) return fail(st);
+  std::vector<int> hrp = rp, hci = ci;
+  std::vector<std::vector<int>> h1rp(D), h1ci(D);
+  for (int d = 0; d < D; ++d) {
+    std::vector<const tc2_bsr*> m1(np);
+    for (int s = 0; s < np; ++s) m1[s] = &probs[s].H1[d];
+    vals.clear();
+    merge_pattern(m1, ctx->sys, h1rp[d], h1ci[d]);
+    for (int s = 0; s < np; ++s) pack_blocks(probs[s].H1[d], b, vals);
+    if ((st = upload(ctx, ctx->h1_rp[d], h1rp[d])) != TC2_OK) return fail(st);
+    if ((st = upload(ctx, ctx->h1_ci[d], h1ci[d])) != TC2_OK) return fail(st);
+    if ((st = upload(ctx, ctx->h1_v[d], vals)) != TC2_OK) return fail(st);
+  }
+  // initial pattern: union of H and the H1_d patterns, with source entries
+  std::vector<int> xrp(1, 0), xci, xrow, sh;
+  std::vector<std::vector<int>> sh1(D);
+  for (int I = 0; I < ctx->nb; ++I) {
+    std::vector<int> cols(hci.begin() + hrp[I], hci.begin() + hrp[I + 1]);
+    for (int d = 0; d < D; ++d) cols.insert(cols.end(), h1ci[d].begin() + h1rp[d][I], h1ci[d].begin() + h1rp[d][I + 1]);
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    for (int J : cols) {
+      xci.push_back(J);
+      xrow.push_back(I);
+      auto f = std::lower_bound(hci.begin() + hrp[I], hci.begin() + hrp[I + 1], J);
+      sh.push_back((f != hci.begin() + hrp[I + 1] && *f == J) ? (int)(f - hci.begin()) : -1);
+      for (int d = 0; d < D; ++d) {
+        auto g = std::lower_bound(h1ci[d].begin() + h1rp[d][I], h1ci[d].begin() + h1rp[d][I + 1], J);
+        sh1[d].push_back((g != h1ci[d].begin() + h1rp[d][I + 1] && *g == J) ? (int)(g - h1ci[d].begin()) : -1);
+      }
+    }
+    xrp.push_back((int)xci.size());
+  }
+  ctx->nnz0 = (int)xci.size();
+  if ((st = upload(ctx, ctx->x0_rp, xrp)) != TC2_OK) return fail(st);
+  if ((st = upload(ctx, ctx->x0_ci, xci)) != TC2_OK) return fail(st);
+  if ((st = upload(ctx, ctx->x0_row, xrow)) != TC2_OK) return fail(st);
+  if ((st = upload(ctx, ctx->src_h, sh)) != TC2_OK) return fail(st);
+  for (int d = 0; d < D; ++d)
+    if ((st = upload(ctx, ctx->src_h1[d], sh1[d])) != TC2_OK) return fail(st);
+  if (ctx->rowlo.reserve((size_t)ctx->nb * b * 8) || ctx->rowhi.reserve((size_t)ctx->nb * b * 8))
+    return fail(TC2_ENOMEM);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(TC2_EDEVICE);
+  *out = ctx;
+  return TC2_OK;
+}
+
+tc2_status tc2_setup(const tc2_problem* problems, int32_t n_problems, const tc2_options* opts,
+                     tc2_ctx** out) {
+  try {
+    return setup_impl(problems, n_problems, opts, out);
+  } catch (const std::bad_alloc&) {
+    return TC2_ENOMEM;
+  } catch (...) {
+    return TC2_EINVAL;
+  }
+}
+
+}  // extern "C"
+
+// ====================================================================== solve
+namespace {
+
+// Copy the current iterate into fresh buffers of another precision.
+tc2_status convert_iterate(tc2_ctx* ctx, hipStream_t st, int to_prec) {
+  int c = ctx->cur;
+  long long n = (long long)ctx->nnz[c] * (1 + ctx->D) * BS;
+  DBuf& dst = ctx->xv[c ^ 1];
+  HIPCHK(dst.reserve((size_t)n * prec_bytes(to_prec)));
+  launch_convert(st, ctx->cur_prec, to_prec, n, ctx->xv[c].p, dst.p);
+  // move the pattern along
+  HIPCHK(ctx->rp[c ^ 1].reserve((size_t)(ctx->nb + 1) * 4));
+  HIPCHK(ctx->ci[c ^ 1].reserve((size_t)std::max(1, ctx->nnz[c]) * 4));
+  HIPCHK(hipMemcpyAsync(ctx->rp[c ^ 1].p, ctx->rp[c].p, (size_t)(ctx->nb + 1) * 4, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->ci[c ^ 1].p, ctx->ci[c].p, (size_t)ctx->nnz[c] * 4, hipMemcpyDeviceToDevice, st));
+  ctx->nnz[c ^ 1] = ctx->nnz[c];
+  ctx->cur = c ^ 1;
+  ctx->cur_prec = to_prec;
+  return TC2_OK;
+}
+
+// Scalars of the current iterate into host memory (nsys x NQ).
+tc2_status measure(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal) {
+  const int c = ctx->cur;
+  MeasArgs m{};
+  m.nb = ctx->nb;
+  m.D = ctx->D;
+  m.rp = ctx->rp[c].as<int>();
+  m.ci = ctx->ci[c].as<int>();
+  m.xv = ctx->xv[c].p;
+  m.h_rp = ctx->h_rp.as<int>();
+  m.h_ci = ctx->h_ci.as<int>();
+  m.h_v = ctx->h_v.as<double>();
+  for (int d = 0; d < ctx->D; ++d) {
+    m.h1_rp[d] = ctx->h1_rp[d].as<int>();
+    m.h1_ci[d] = ctx->h1_ci[d].as<int>();
+    m.h1_v[d] = ctx->h1_v[d].as<double>();
+  }
+  HIPCHK(ctx->partial.reserve((size_t)std::max(ctx->nb, 1) * NQ * 8));
+  m.partial = ctx->partial.as<double>();
+  launch_measure(st, ctx->cur_prec, m);
+  HIPCHK(ctx->scal.reserve((size_t)ctx->nsys * NQ * 8));
+  launch_reduce(st, ctx->nsys, ctx->sys_start.as<int>(), ctx->sys_end.as<int>(), ctx->partial.as<double>(),
+                ctx->scal.as<double>());
+  scal.resize((size_t)ctx->nsys * NQ);
+  HIPCHK(hipMemcpyAsync(scal.data(), ctx->scal.p, scal.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return TC2_OK;
+}
+
+// One update of every active system: symbolic, numeric, compaction.
+// Leaves the per-system scalars of the new iterate in `scal`.
+tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
+                unsigned long long& exec_pairs_total) {
+  const int c = ctx->cur, n = c ^ 1;
+  const int nb = ctx->nb, D = ctx->D;
+  const size_t tile = (size_t)(1 + D) * BS * prec_bytes(ctx->cur_prec);
+  int* cnt = nullptr;  // device counters: [0] total, [1] stage_count, [2] overflow
+  HIPCHK(ctx->counters.reserve(64));
+  cnt = ctx->counters.as<int>();
+  int hcnt[4];
+
+  // ---- symbolic
+  HIPCHK(ctx->cand_cnt.reserve((size_t)nb * 4));
+  HIPCHK(ctx->cand_rp.reserve((size_t)(nb + 1) * 4));
+  SymArgs sa{};
+  sa.nb = nb;
+  sa.rp = ctx->rp[c].as<int>();
+  sa.ci = ctx->ci[c].as<int>();
+  sa.sys_of = ctx->sys_of.as<int>();
+  sa.sys_end = ctx->sys_end.as<int>();
+  sa.active = ctx->active.as<int>();
+  sa.cand_cnt = ctx->cand_cnt.as<int>();
+  sa.cand_rp = ctx->cand_rp.as<int>();
+  sa.max_sys_atoms = ctx->max_sys_atoms;
+  launch_symbolic(st, 0, sa);
+  launch_scan(st, nb, ctx->cand_cnt.as<int>(), ctx->cand_rp.as<int>(), cnt);
+  HIPCHK(hipMemcpyAsync(hcnt, cnt, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const int ncand = hcnt[0];
+  HIPCHK(ctx->cand_ci.reserve((size_t)std::max(ncand, 1) * 4));
+  sa.cand_ci = ctx->cand_ci.as<int>();
+  launch_symbolic(st, 1, sa);
+
+  // ---- work items
+  HIPCHK(ctx->item_cnt.reserve((size_t)nb * 4));
+  HIPCHK(ctx->item_rp.reserve((size_t)(nb + 1) * 4));
+  launch_items_count(st, nb, ctx->cand_rp.as<int>(), ctx->item_cnt.as<int>());
+  launch_scan(st, nb, ctx->item_cnt.as<int>(), ctx->item_rp.as<int>(), cnt);
+  HIPCHK(hipMemcpyAsync(hcnt, cnt, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const int n_items = hcnt[0];
+  HIPCHK(ctx->item_row.reserve((size_t)std::max(n_items, 1) * 4));
+  HIPCHK(ctx->item_c0.reserve((size_t)std::max(n_items, 1) * 4));
+  HIPCHK(ctx->partial.reserve((size_t)std::max(n_items, nb) * NQ * 8));
+  launch_items(st, nb, ctx->cand_rp.as<int>(), ctx->item_rp.as<int>(), ctx->item_row.as<int>(),
+               ctx->item_c0.as<int>());
+  HIPCHK(ctx->sys_lo.reserve((size_t)ctx->nsys * 4));
+  HIPCHK(ctx->sys_hi.reserve((size_t)ctx->nsys * 4));
+  launch_sys_items(st, ctx->nsys, ctx->sys_start.as<int>(), ctx->sys_end.as<int>(), ctx->item_rp.as<int>(),
+                   ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>());
+
+  // ---- numeric (retried with a larger stage if it overflows)
+  if (ctx->stage_cap == 0) ctx->stage_cap = std::max(ctx->nnz[c], nb) + 1024;
+  HIPCHK(ctx->exec_pairs.reserve(8));
+  int n_kept = 0;
+  unsigned long long pairs = 0;
+  for (int attempt = 0;; ++attempt) {
+    int cap = std::min(ctx->stage_cap, ncand);
+    cap = std::max(cap, 1);
+    HIPCHK(ctx->stage.reserve((size_t)cap * tile));
+    HIPCHK(ctx->kept_ij.reserve((size_t)cap * 8));
+    launch_fill_int(st, cnt, 0, 4);
+    launch_fill_int(st, ctx->exec_pairs.as<int>(), 0, 2);
+    NumArgs na{};
+    na.nb = nb;
+    na.D = D;
+    na.b = ctx->b;
+    na.ksteps = (ctx->b + 3) / 4;
+    na.rp = ctx->rp[c].as<int>();
+    na.ci = ctx->ci[c].as<int>();
+    na.xv = ctx->xv[c].p;
+    na.cand_rp = ctx->cand_rp.as<int>();
+    na.cand_ci = ctx->cand_ci.as<int>();
+    na.item_row = ctx->item_row.as<int>();
+    na.item_c0 = ctx->item_c0.as<int>();
+    na.n_items = n_items;
+    na.sys_of = ctx->sys_of.as<int>();
+    na.active = ctx->active.as<int>();
+    na.branch = ctx->branch.as<int>();
+    na.eps = ctx->eps.as<double>();
+    na.h_rp = ctx->h_rp.as<int>();
+    na.h_ci = ctx->h_ci.as<int>();
+    na.h_v = ctx->h_v.as<double>();
+    for (int d = 0; d < D; ++d) {
+      na.h1_rp[d] = ctx->h1_rp[d].as<int>();
+      na.h1_ci[d] = ctx->h1_ci[d].as<int>();
+      na.h1_v[d] = ctx->h1_v[d].as<double>();
+    }
+    na.stage = ctx->stage.p;
+    na.kept_ij = ctx->kept_ij.as<int2>();
+    na.stage_count = cnt + 1;
+    na.stage_cap = cap;
+    na.overflow = cnt + 2;
+    na.bad = ctx->bad.as<int>();
+    na.partial = ctx->partial.as<double>();
+    na.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
+    launch_numeric(st, ctx->cur_prec, na);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(hcnt, cnt, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&pairs, ctx->exec_pairs.p, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (!hcnt[2]) {
+      n_kept = hcnt[1];
+      break;
+    }
+    // overflow: the counter still counts every kept block
+    ctx->stage_cap = (int)std::min<long long>((long long)hcnt[1] * 5 / 4 + 1024, ncand);
+    if (attempt > 3) return TC2_ENOMEM;
+  }
+  exec_pairs_total += pairs;
+  ctx->stage_cap = std::max(ctx->stage_cap, n_kept * 5 / 4 + 1024);
+
+  // ---- compaction into the new pattern
+  HIPCHK(ctx->rowcnt.reserve((size_t)nb * 4));
+  HIPCHK(ctx->cursor.reserve((size_t)nb * 4));
+  HIPCHK(ctx->rp[n].reserve((size_t)(nb + 1) * 4));
+  launch_fill_int(st, ctx->rowcnt.as<int>(), 0, nb);
+  launch_fill_int(st, ctx->cursor.as<int>(), 0, nb);
+  CompactArgs ca{};
+  ca.nb = nb;
+  ca.D = D;
+  ca.kept_ij = ctx->kept_ij.as<int2>();
+  ca.rowcnt = ctx->rowcnt.as<int>();
+  ca.cursor = ctx->cursor.as<int>();
+  ca.new_rp = ctx->rp[n].as<int>();
+  ca.sys_of = ctx->sys_of.as<int>();
+  ca.sys_start = ctx->sys_start.as<int>();
+  ca.sys_end = ctx->sys_end.as<int>();
+  ca.max_sys_atoms = ctx->max_sys_atoms;
+  launch_compact_count(st, ca, n_kept);
+  launch_scan(st, nb, ctx->rowcnt.as<int>(), ctx->rp[n].as<int>(), cnt);
+  HIPCHK(hipMemcpyAsync(hcnt, cnt, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const int nnz_new = hcnt[0];
+  HIPCHK(ctx->tmp_ci.reserve((size_t)std::max(nnz_new, 1) * 4));
+  HIPCHK(ctx->tmp_src.reserve((size_t)std::max(nnz_new, 1) * 4));
+  HIPCHK(ctx->new_src.reserve((size_t)std::max(nnz_new, 1) * 4));
+  HIPCHK(ctx->ci[n].reserve((size_t)std::max(nnz_new, 1) * 4));
+  HIPCHK(ctx->xv[n].reserve((size_t)std::max(nnz_new, 1) * tile));
+  ca.tmp_ci = ctx->tmp_ci.as<int>();
+  ca.tmp_src = ctx->tmp_src.as<int>();
+  ca.new_ci = ctx->ci[n].as<int>();
+  ca.new_src = ctx->new_src.as<int>();
+  launch_compact_scatter(st, ca, n_kept);
+  launch_row_sort(st, ca);
+  launch_gather(st, ctx->cur_prec, nnz_new, D, ctx->new_src.as<int>(), ctx->stage.p, ctx->xv[n].p);
+  ctx->nnz[n] = nnz_new;
+  ctx->cur = n;
+
+  // ---- per-system scalars of the new iterate
+  HIPCHK(ctx->scal.reserve((size_t)ctx->nsys * NQ * 8));
+  launch_reduce(st, ctx->nsys, ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>(), ctx->partial.as<double>(),
+                ctx->scal.as<double>());
+  scal.resize((size_t)ctx->nsys * NQ);
+  HIPCHK(hipMemcpyAsync(scal.data(), ctx->scal.p, scal.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  return TC2_OK;
+}
+
+// energies vector used by the stopping test: E0, E1_d, alpha_d
+void energies(const double* q, int D, double* e) {
+  e[0] = q[Q_E0];
+  for (int d = 0; d < D; ++d) {
+    e[1 + d] = q[Q_E1 + d];
+    e[1 + D + d] = q[Q_AL + d];
+  }
+}
+
+tc2_status export_results(tc2_ctx* ctx, hipStream_t st) {
+  const int c = ctx->cur, D = ctx->D, b = ctx->b, nb = ctx->nb;
+  const int nnz = ctx->nnz[c];
+  std::vector<int> rp(nb + 1), ci(std::max(nnz, 1));
+  HIPCHK(hipMemcpyAsync(rp.data(), ctx->rp[c].p, (size_t)(nb + 1) * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ci.data(), ctx->ci[c].p, (size_t)nnz * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx->xfer.reserve((size_t)std::max(nnz, 1) * b * b * 8));
+  std::vector<double> v((size_t)nnz * b * b);
+  ctx->out_x0.assign(ctx->nsys, HostBsr());
+  for (int d = 0; d < MAXD; ++d) ctx->out_x1[d].assign(d < D ? ctx->nsys : 0, HostBsr());
+  for (int m = 0; m <= D; ++m) {
+    launch_export(st, ctx->cur_prec, nnz, D, m, b, ctx->xv[c].p, ctx->xfer.as<double>());
+    HIPCHK(hipMemcpyAsync(v.data(), ctx->xfer.p, v.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int s = 0; s < ctx->nsys; ++s) {
+      const SysInfo& si = ctx->sys[s];
+      HostBsr& hb = (m == 0) ? ctx->out_x0[s] : ctx->out_x1[m - 1][s];
+      hb.row_ptr.assign(1, 0);
+      hb.col.clear();
+      hb.val.clear();
+      for (int i = 0; i < si.nb; ++i) {
+        int I = si.row0 + i;
+        for (int p = rp[I]; p < rp[I + 1]; ++p) {
+          hb.col.push_back(ci[p] - si.row0);
+          hb.val.insert(hb.val.end(), v.begin() + (size_t)p * b * b, v.begin() + (size_t)(p + 1) * b * b);
+        }
+        hb.row_ptr.push_back((int64_t)hb.col.size());
+      }
+    }
+  }
+  return TC2_OK;
+}
+
+tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
+  if (!ctx || !res) return TC2_EINVAL;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = stream ? (hipStream_t)stream : ctx->own;
+  const int nsys = ctx->nsys, D = ctx->D, b = ctx->b, nb = ctx->nb;
+  std::vector<SysState> ss(nsys);
+  hipEvent_t ev0, ev1;
+  HIPCHK(hipEventCreate(&ev0));
+  HIPCHK(hipEventCreate(&ev1));
+  HIPCHK(hipEventRecord(ev0, st));
+
+  // ---- Gershgorin bounds and the initial matrices
+  std::vector<double> emin(nsys), emax(nsys);
+  launch_gershgorin(st, nb, b, ctx->h_rp.as<int>(), ctx->h_ci.as<int>(), ctx->h_v.as<double>(),
+                    ctx->rowlo.as<double>(), ctx->rowhi.as<double>());
+  launch_sys_minmax(st, nsys, ctx->sys_start.as<int>(), ctx->sys_end.as<int>(), b, ctx->rowlo.as<double>(),
+                    ctx->rowhi.as<double>(), ctx->emin.as<double>(), ctx->emax.as<double>());
+  HIPCHK(hipMemcpyAsync(emin.data(), ctx->emin.p, nsys * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(emax.data(), ctx->emax.p, nsys * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<int> mode(nsys), active(nsys, 0), branch(nsys, 0), bad(nsys, 0);
+  for (int s = 0; s < nsys; ++s) {
+    mode[s] = ctx->sys[s].mode;
+    ss[s].status = TC2_OK;
+    if (mode[s] == 0 && !(emax[s] > emin[s])) {
+      ss[s].status = TC2_EDEGENERATE;
+      mode[s] = 1;  // placeholder result; status reports the error
+    }
+    if (mode[s] == 0) ss[s].active = true;
+  }
+  HIPCHK(hipMemcpyAsync(ctx->mode.p, mode.data(), nsys * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->bad.p, bad.data(), nsys * 4, hipMemcpyHostToDevice, st));
+  const int start_prec = ctx->prec == P_FP64 ? P_FP64 : P_FP32;
+  ctx->cur = 0;
+  ctx->cur_prec = start_prec;
+  ctx->nnz[0] = ctx->nnz0;
+  ctx->stage_cap = 0;
+  const size_t tile = (size_t)(1 + D) * BS * prec_bytes(start_prec);
+  HIPCHK(ctx->rp[0].reserve((size_t)(nb + 1) * 4));
+  HIPCHK(ctx->ci[0].reserve((size_t)std::max(ctx->nnz0, 1) * 4));
+  HIPCHK(ctx->xv[0].reserve((size_t)std::max(ctx->nnz0, 1) * tile));
+  HIPCHK(hipMemcpyAsync(ctx->rp[0].p, ctx->x0_rp.p, (size_t)(nb + 1) * 4, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->ci[0].p, ctx->x0_ci.p, (size_t)ctx->nnz0 * 4, hipMemcpyDeviceToDevice, st));
+  {
+    const int* src1[MAXD] = {nullptr, nullptr, nullptr};
+    const double* h1v[MAXD] = {nullptr, nullptr, nullptr};
+    for (int d = 0; d < D; ++d) {
+      src1[d] = ctx->src_h1[d].as<int>();
+      h1v[d] = ctx->h1_v[d].as<double>();
+    }
+    launch_init(st, start_prec, ctx->nnz0, D, b, ctx->x0_row.as<int>(), ctx->x0_ci.as<int>(),
+                ctx->src_h.as<int>(), src1, ctx->h_v.as<double>(), h1v, ctx->sys_of.as<int>(),
+                ctx->emin.as<double>(), ctx->emax.as<double>(), ctx->mode.as<int>(), ctx->xv[0].p);
+  }
+  std::vector<double> scal;
+  tc2_status st0 = measure(ctx, st, scal);
+  if (st0 != TC2_OK) return st0;
+  for (int s = 0; s < nsys; ++s) {
+    energies(&scal[(size_t)s * NQ], D, ss[s].prev);
+    branch[s] = scal[(size_t)s * NQ + Q_TR0] >= (double)ctx->sys[s].n_occ ? 1 : 0;
+  }
+
+  // ---- iterate.  phase 0: working precision; phase 1: closing FP64 pair
+  unsigned long long exec_pairs = 0;
+  const bool reduced = ctx->prec != P_FP64;
+  int phase = 0;
+  for (;;) {
+    bool any = false;
+    for (int s = 0; s < nsys; ++s) {
+      active[s] = ss[s].active ? 1 : 0;
+      any |= ss[s].active;
+      if (ss[s].active) {
+        const std::string& rep = ctx->sys[s].replay;
+        if (phase == 0 && !rep.empty()) branch[s] = rep[ss[s].k] == 'S' ? 1 : 0;
+        ss[s].branches.push_back(branch[s] ? 'S' : 'D');
+      }
+    }
+    if (!any) {
+      if (phase == 0 && reduced && ctx->closing == 2) {
+        // closing pair in FP64: trace rule, then the opposite branch
+        tc2_status cs = convert_iterate(ctx, st, P_FP64);
+        if (cs != TC2_OK) return cs;
+        phase = 1;
+        for (int s = 0; s < nsys; ++s)
+          if (mode[s] == 0 && ss[s].status >= 0) {
+            ss[s].active = true;
+            ss[s].closing_left = 2;
+            ss[s].closing_first = branch[s];
+          }
+        continue;
+      }
+      break;
+    }
+    HIPCHK(hipMemcpyAsync(ctx->active.p, active.data(), nsys * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctx->branch.p, branch.data(), nsys * 4, hipMemcpyHostToDevice, st));
+    tc2_status r = step(ctx, st, scal, exec_pairs);
+    if (r != TC2_OK) return r;
+    HIPCHK(hipMemcpyAsync(bad.data(), ctx->bad.p, nsys * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int s = 0; s < nsys; ++s) {
+      if (!ss[s].active) continue;
+      SysState& S = ss[s];
+      const SysInfo& si = ctx->sys[s];
+      const double* q = &scal[(size_t)s * NQ];
+      S.k++;
+      S.trip += q[Q_TRIP];
+      double cur[1 + 2 * MAXD];
+      energies(q, D, cur);
+      const double iota = q[Q_TR0] - q[Q_FRO0];
+      S.iota.push_back(iota);
+      double dmax = 0.0;
+      for (int k = 0; k < 1 + 2 * D; ++k) dmax = std::max(dmax, std::fabs(cur[k] - S.prev[k]));
+      std::copy(cur, cur + 1 + 2 * D, S.prev);
+      if (ctx->verbose)
+        fprintf(stderr, "tc2 sys %d it %d %c tr-nocc %.3e iota %.3e E0 %.12f dmax %.3e\n", s, S.k,
+                S.branches.back(), q[Q_TR0] - (double)si.n_occ, iota, cur[0], dmax);
+      if (bad[s]) {
+        S.status = TC2_ENAN;
+        S.active = false;
+        continue;
+      }
+      if (phase == 1) {
+        // closing pair: the second step takes the branch opposite to the first
+        if (--S.closing_left == 0) S.active = false;
+        else branch[s] = S.closing_first ? 0 : 1;
+        continue;
+      }
+      const double tol = reduced ? std::max(si.tol, ctx->prec == P_FP32 ? 1e-6 : 1e-3) : si.tol;
+      bool stop = false;
+      if (!si.replay.empty()) {
+        if (S.k == (int)si.replay.size()) {
+          stop = true;
+          S.status = TC2_OK;
+        }
+      } else if (S.k >= 2 && dmax < tol) {
+        stop = true;
+        S.status = TC2_OK;
+      } else if (S.k >= 3 && std::fabs(iota) < 1.0 &&
+                 std::fabs(iota) >= std::fabs(S.iota[S.iota.size() - 3])) {
+        stop = true;
+        S.status = TC2_FLOOR_REACHED;
+      } else if (S.k >= si.max_iter) {
+        stop = true;
+        S.status = TC2_NOT_CONVERGED;
+      }
+      if (stop) S.active = false;
+      branch[s] = q[Q_TR0] >= (double)si.n_occ ? 1 : 0;
+    }
+  }
+  HIPCHK(hipEventRecord(ev1, st));
+  HIPCHK(hipEventSynchronize(ev1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+
+  // final scalars straight from the stored iterate
+  st0 = measure(ctx, st, scal);
+  if (st0 != TC2_OK) return st0;
+  if (ctx->export_m) {
+    st0 = export_results(ctx, st);
+    if (st0 != TC2_OK) return st0;
+  }
+  tc2_status worst = TC2_OK;
+  const double b3 = 2.0 * b * b * b;
+  const double kst = (double)((b + 3) / 4) * 4;
+  for (int s = 0; s < nsys; ++s) {
+    tc2_result& R = res[s];
+    memset(&R, 0, sizeof(R));
+    const double* q = &scal[(size_t)s * NQ];
+    R.status = ss[s].status;
+    R.iters = ss[s].k;
+    R.tr_x0 = q[Q_TR0];
+    R.idem_err = q[Q_TR0] - q[Q_FRO0];
+    R.e0 = q[Q_E0];
+    for (int d = 0; d < D; ++d) {
+      R.trace_x1h1[d] = q[Q_AL + d];
+      R.tr_x1[d] = q[Q_TR1 + d];
+      R.e1[d] = q[Q_E1 + d];
+    }
+    R.emin = emin[s];
+    R.emax = emax[s];
+    R.seconds = ms * 1e-3;
+    R.useful_flops = ss[s].trip * b3 * (1 + 2 * D);
+    R.executed_flops = (s == 0) ? (double)exec_pairs * (1 + 2 * D) * 2.0 * BP * BP * kst : 0.0;
+    strncpy(R.branches, ss[s].branches.c_str(), TC2_MAX_ITER + 3);
+    if (ctx->export_m) {
+      HostBsr& x0 = ctx->out_x0[s];
+      R.X0 = tc2_bsr{ctx->sys[s].nb, b, x0.row_ptr.data(), x0.col.data(), x0.val.data()};
+      for (int d = 0; d < D; ++d) {
+        HostBsr& x1 = ctx->out_x1[d][s];
+        R.X1[d] = tc2_bsr{ctx->sys[s].nb, b, x1.row_ptr.data(), x1.col.data(), x1.val.data()};
+      }
+    }
+    if (R.status < 0 && (worst >= 0 || R.status < worst)) worst = R.status;
+    else if (worst >= 0 && R.status > worst) worst = R.status;
+  }
+  return worst;
+}
+
+}  // namespace
+
+extern "C" tc2_status tc2_run(tc2_ctx* ctx, void* hip_stream, tc2_result* res) {
+  try {
+    return run_impl(ctx, hip_stream, res);
+  } catch (const std::bad_alloc&) {
+    return TC2_ENOMEM;
+  } catch (...) {
+    return TC2_EDEVICE;
+  }
+}

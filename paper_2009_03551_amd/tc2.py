@@ -1,0 +1,214 @@
+"""ctypes binding of the C ABI in include/tc2.h (argument marshalling only).
+
+Every step of the solve runs in the HIP kernels of ``libtc2.so``; this module
+only converts numpy arrays to the C structs and back.  It raises when the
+library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Union
+
+import numpy as np
+
+from .workloads import BSR, System
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtc2.so")
+
+TC2_MAX_ITER = 200
+STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "FLOOR_REACHED", -1: "EINVAL", -2: "ENOMEM",
+          -3: "EDEVICE", -4: "ENONSYM", -5: "EDEGENERATE", -6: "ENAN", -7: "EOVERFLOW"}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+
+class tc2_bsr(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("b", C.c_int32), ("row_ptr", C.POINTER(C.c_int64)),
+                ("col", C.POINTER(C.c_int32)), ("val", C.POINTER(C.c_double))]
+
+
+class tc2_problem(C.Structure):
+    _fields_ = [("H", tc2_bsr), ("n_dir", C.c_int32), ("H1", tc2_bsr * 3),
+                ("n_occ", C.c_int64), ("eps_drop", C.c_double), ("tol", C.c_double),
+                ("max_iter", C.c_int32), ("replay", C.c_char_p)]
+
+
+class tc2_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("closing_fp64", C.c_int32), ("skip", C.c_int32),
+                ("device", C.c_int32), ("export_matrices", C.c_int32), ("verbose", C.c_int32)]
+
+
+class tc2_result(C.Structure):
+    _fields_ = [("status", C.c_int), ("iters", C.c_int32), ("trace_x1h1", C.c_double * 3),
+                ("tr_x0", C.c_double), ("idem_err", C.c_double), ("tr_x1", C.c_double * 3),
+                ("e0", C.c_double), ("e1", C.c_double * 3), ("emin", C.c_double),
+                ("emax", C.c_double), ("seconds", C.c_double), ("useful_flops", C.c_double),
+                ("executed_flops", C.c_double), ("branches", C.c_char * (TC2_MAX_ITER + 4)),
+                ("X0", tc2_bsr), ("X1", tc2_bsr * 3)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libtc2.so (built in-tree by ``build()``); raise if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "paper_2009_03551_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        L.tc2_setup.restype = C.c_int
+        L.tc2_setup.argtypes = [C.POINTER(tc2_problem), C.c_int32, C.POINTER(tc2_options),
+                                C.POINTER(C.c_void_p)]
+        L.tc2_run.restype = C.c_int
+        L.tc2_run.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(tc2_result)]
+        L.tc2_free.restype = None
+        L.tc2_free.argtypes = [C.c_void_p]
+        L.tc2_strerror.restype = C.c_char_p
+        L.tc2_strerror.argtypes = [C.c_int]
+        L.tc2_version.restype = C.c_char_p
+        L.tc2_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("tc2_setup", "tc2_run", "tc2_free", "tc2_strerror", "tc2_version")
+
+
+class TC2Error(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lib().tc2_strerror(status).decode()
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({msg})")
+        self.status = status
+
+
+@dataclass
+class Result:
+    status: int
+    iters: int
+    branches: str
+    alpha: List[float]
+    tr_x0: float
+    idem_err: float
+    tr_x1: List[float]
+    e0: float
+    e1: List[float]
+    emin: float
+    emax: float
+    seconds: float
+    useful_flops: float
+    executed_flops: float
+    X0: Optional[BSR] = None
+    X1: List[BSR] = field(default_factory=list)
+
+    @property
+    def status_name(self) -> str:
+        return STATUS.get(self.status, str(self.status))
+
+
+def _c_bsr(m: BSR, keep: list) -> tc2_bsr:
+    rp = np.ascontiguousarray(m.row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(m.col, dtype=np.int32)
+    va = np.ascontiguousarray(m.val, dtype=np.float64)
+    keep += [rp, ci, va]
+    return tc2_bsr(m.nb, m.b, rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                   ci.ctypes.data_as(C.POINTER(C.c_int32)),
+                   va.ctypes.data_as(C.POINTER(C.c_double)))
+
+
+def _py_bsr(m: tc2_bsr) -> BSR:
+    nb, b = m.nb, m.b
+    rp = np.ctypeslib.as_array(m.row_ptr, shape=(nb + 1,)).copy()
+    nnz = int(rp[-1])
+    ci = np.ctypeslib.as_array(m.col, shape=(max(nnz, 1),))[:nnz].copy()
+    va = np.ctypeslib.as_array(m.val, shape=(max(nnz * b * b, 1),))[:nnz * b * b].copy()
+    return BSR(nb, b, rp, ci, va.reshape(nnz, b, b))
+
+
+class Solver:
+    """A prepared context (``tc2_setup``) that can be run repeatedly."""
+
+    def __init__(self, systems: Union[System, Sequence[System]], precision: str = "fp64",
+                 closing_fp64: int = 0, export: bool = True, device: int = 0,
+                 replay: Optional[Sequence[Optional[str]]] = None, verbose: bool = False):
+        if isinstance(systems, System):
+            systems = [systems]
+        self.systems = list(systems)
+        self._keep: list = []
+        n = len(self.systems)
+        probs = (tc2_problem * n)()
+        for k, s in enumerate(self.systems):
+            p = probs[k]
+            p.H = _c_bsr(s.H, self._keep)
+            p.n_dir = len(s.H1)
+            for d, h1 in enumerate(s.H1):
+                p.H1[d] = _c_bsr(h1, self._keep)
+            p.n_occ = int(s.n_occ)
+            p.eps_drop = float(s.eps)
+            p.tol = float(s.tol)
+            p.max_iter = int(s.max_iter)
+            rep = replay[k] if replay is not None else None
+            if rep:
+                rb = rep.encode()
+                self._keep.append(rb)
+                p.replay = rb
+            else:
+                p.replay = None
+        self.n_dir = len(self.systems[0].H1)
+        opts = tc2_options(PRECISION[precision], int(closing_fp64), 0, int(device),
+                           1 if export else 0, 1 if verbose else 0)
+        self._ctx = C.c_void_p()
+        st = lib().tc2_setup(probs, n, C.byref(opts), C.byref(self._ctx))
+        if st != 0:
+            raise TC2Error(st, "tc2_setup")
+
+    def run(self, stream: Optional[int] = None, check: bool = True) -> List[Result]:
+        n = len(self.systems)
+        res = (tc2_result * n)()
+        st = lib().tc2_run(self._ctx, C.c_void_p(stream) if stream else None, res)
+        if check and st < 0:
+            raise TC2Error(st, "tc2_run")
+        out = []
+        D = self.n_dir
+        for r in res:
+            x0 = _py_bsr(r.X0) if r.X0.row_ptr else None
+            x1 = [_py_bsr(r.X1[d]) for d in range(D)] if r.X0.row_ptr else []
+            out.append(Result(r.status, r.iters, r.branches.decode(), list(r.trace_x1h1[:D]),
+                              r.tr_x0, r.idem_err, list(r.tr_x1[:D]), r.e0, list(r.e1[:D]),
+                              r.emin, r.emax, r.seconds, r.useful_flops, r.executed_flops,
+                              x0, x1))
+        return out
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().tc2_free(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(systems, **kw) -> List[Result]:
+    """One-shot setup + run + free."""
+    s = Solver(systems, **kw)
+    try:
+        return s.run()
+    finally:
+        s.close()
+
+
+def bsr_dense(m: BSR) -> np.ndarray:
+    """Dense copy of a BSR result (for tests and checks)."""
+    A = np.zeros((m.nb * m.b, m.nb * m.b))
+    b = m.b
+    for I in range(m.nb):
+        for p in range(int(m.row_ptr[I]), int(m.row_ptr[I + 1])):
+            J = int(m.col[p])
+            A[I * b:(I + 1) * b, J * b:(J + 1) * b] = m.val[p]
+    return A

@@ -1,0 +1,121 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and rejects malformed input on the host before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2009_03551_amd import tc2 as T
+from paper_2009_03551_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "tc2.h")).read()
+    return sorted(set(re.findall(r"TC2_API\s+[\w\s\*]+?\b(tc2_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = T.lib()
+    syms = declared_symbols()
+    assert set(syms) >= {"tc2_setup", "tc2_run", "tc2_free"}
+    out = subprocess.run(["nm", "-D", "--defined-only", T.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (tc2_\w+)", out))
+    for s in syms:
+        assert s in exported, s
+        getattr(lib, s)
+    assert set(T.EXPORTED) == set(syms)
+
+
+def test_strerror_and_version():
+    lib = T.lib()
+    assert b"gfx950" in lib.tc2_version()
+    for code in T.STATUS:
+        assert lib.tc2_strerror(code)
+    lib.tc2_free(None)  # NULL-safe
+
+
+def _setup_status(sys_list, **kw):
+    try:
+        T.Solver(sys_list, **kw).close()
+        return 0
+    except T.TC2Error as e:
+        return e.status
+
+
+def small():
+    return W.config_system("chain64", n=6)
+
+
+def test_rejects_bad_nocc():
+    s = small()
+    s.n_occ = s.H.n + 1
+    assert _setup_status(s) == -1
+    s.n_occ = -1
+    assert _setup_status(s) == -1
+
+
+def test_rejects_bad_eps_tol_iters():
+    for attr, val in (("eps", -1.0), ("tol", 0.0), ("max_iter", 0), ("max_iter", 10**6)):
+        s = small()
+        setattr(s, attr, val)
+        assert _setup_status(s) == -1, attr
+
+
+def test_rejects_unsorted_columns():
+    s = small()
+    s.H.col = s.H.col.copy()
+    r0, r1 = int(s.H.row_ptr[2]), int(s.H.row_ptr[3])
+    s.H.col[r0:r1] = s.H.col[r0:r1][::-1]
+    assert _setup_status(s) == -1
+
+
+def test_rejects_nonsymmetric_pattern():
+    s = small()
+    # drop the (1, 0) entry only
+    rp, ci, va = s.H.row_ptr.copy(), s.H.col.copy(), s.H.val.copy()
+    p = int(rp[1]) + list(ci[rp[1]:rp[2]]).index(0)
+    ci = np.delete(ci, p)
+    va = np.delete(va, p, axis=0)
+    rp[2:] -= 1
+    s.H = W.BSR(s.H.nb, s.H.b, rp, ci, va)
+    assert _setup_status(s) == -4
+
+
+def test_rejects_missing_diagonal():
+    s = W.config_system("chain64", n=3, cutoff=0.5)
+    H = s.H
+    keep = np.array([not (i == 1) for i in range(H.nnzb)])
+    rp = np.array([0, 1, 1, 2], dtype=np.int64)
+    s.H = W.BSR(3, H.b, rp, H.col[keep], H.val[keep])
+    assert _setup_status(s) == -4
+
+
+def test_rejects_nan():
+    s = small()
+    s.H.val = s.H.val.copy()
+    s.H.val[0, 0, 0] = np.nan
+    assert _setup_status(s) == -6
+
+
+def test_rejects_mismatched_batch():
+    a = small()
+    b = W.config_system("chain64", n=6, b=5)
+    assert _setup_status([a, b]) == -1
+
+
+def test_rejects_bad_options():
+    assert _setup_status(small(), closing_fp64=1) == -1
+    assert _setup_status(small(), replay=["SX"]) == -1
+
+
+def test_valid_problem_needs_a_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert _setup_status(small()) == -3

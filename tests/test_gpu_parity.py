@@ -1,0 +1,130 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Both sides run the same recursion in FP64 with different summation orders,
+so iterates agree to rounding (~1e-13) unless a block norm lies within
+rounding of eps; the bar is the stated one, max|dX1| < 1e-6 and
+rel|d alpha| < 1e-6, and the FP64 cases are held to 1e-9 / 1e-10 here.
+"""
+import numpy as np
+import pytest
+
+from oracle import tc2_oracle as O
+from paper_2009_03551_amd import tc2 as T
+from paper_2009_03551_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_X = 1e-9
+FP64_A = 1e-10
+
+
+def compare(sys, g, o, tol_x=FP64_X, tol_a=FP64_A, branches=True):
+    print(f"  {sys.name}: gpu {g.status_name} it={g.iters} {g.branches} | "
+          f"oracle st={o.status} it={o.iters} {o.branches}", flush=True)
+    if branches:
+        assert g.branches == o.branches
+    dx0 = np.abs(T.bsr_dense(g.X0) - o.X0).max()
+    assert dx0 < tol_x, dx0
+    for d in range(len(sys.H1)):
+        dx1 = np.abs(T.bsr_dense(g.X1[d]) - o.X1[d]).max()
+        dal = abs(g.alpha[d] - o.alpha[d]) / max(abs(o.alpha[d]), 1e-300)
+        print(f"    dir {d}: max|dX1|={dx1:.2e} rel|dalpha|={dal:.2e} alpha={g.alpha[d]:.10f}",
+              flush=True)
+        assert dx1 < tol_x, dx1
+        assert dal < tol_a, dal
+    assert abs(g.tr_x0 - np.trace(o.X0)) < 1e-8
+
+
+def run_both(sys, **kw):
+    g = T.solve(sys, **kw)[0]
+    o = O.solve_system(sys)
+    return g, o
+
+
+def test_chain64_fp64():
+    s = W.config_system("chain64")
+    g, o = run_both(s)
+    assert g.status == o.status == 0
+    compare(s, g, o)
+
+
+def test_chain_ragged_block():
+    # b = 5 (one K-step of the padded tile is ragged), 37 atoms
+    s = W.config_system("chain64", n=37, b=5, occ=2, eps=1e-6, seed=17)
+    g, o = run_both(s)
+    compare(s, g, o)
+
+
+def test_cube_b13_fp64():
+    s = W.config_system("cube10", L=4)
+    g, o = run_both(s)
+    compare(s, g, o)
+
+
+def test_cube_three_directions():
+    s = W.config_system("cube20", L=3, eps=1e-6)
+    g, o = run_both(s)
+    compare(s, g, o)
+
+
+def test_batch_uneven_systems():
+    sys_list = W.batch_systems(sizes=[20, 64, 9, 41], n_dir=2)
+    gs = T.solve(sys_list)
+    for s, g in zip(sys_list, gs):
+        compare(s, g, O.solve_system(s))
+
+
+def test_replay_branches():
+    s = W.config_system("chain64", n=20)
+    o = O.solve_system(s)
+    rep = o.branches[:-3] + ("S" if o.branches[-3] == "D" else "D") + o.branches[-2:]
+    g = T.solve(s, replay=[rep])[0]
+    o2 = O.solve_system(s, replay=rep)
+    assert g.branches == rep
+    compare(s, g, o2)
+
+
+@pytest.mark.parametrize("which", ["none", "all"])
+def test_nocc_edges(which):
+    s = W.config_system("chain64", n=5)
+    s.n_occ = 0 if which == "none" else s.H.n
+    g = T.solve(s)[0]
+    X0 = T.bsr_dense(g.X0)
+    assert g.status == 0 and g.iters == 0
+    assert np.array_equal(X0, np.zeros_like(X0) if which == "none" else np.eye(X0.shape[0]))
+    assert not np.any(T.bsr_dense(g.X1[0]))
+
+
+def test_single_atom():
+    s = W.config_system("chain64", n=1)
+    g, o = run_both(s)
+    compare(s, g, o)
+
+
+def test_degenerate_spectrum():
+    s = W.config_system("chain64", n=4, cutoff=0.5)
+    s.H.val = np.broadcast_to(np.eye(8) * 0.3, s.H.val.shape).copy()
+    with pytest.raises(T.TC2Error) as e:
+        T.solve(s)
+    assert e.value.status == -5
+
+
+def test_max_iter_not_converged():
+    s = W.config_system("chain64", n=16)
+    s.max_iter = 3
+    g = T.solve(s)[0]
+    assert g.status == 1 and g.iters == 3
+    o = O.solve_system(s, max_iter=3)
+    compare(s, g, o)
+
+
+def test_repeat_run_is_bitwise_identical():
+    s = W.config_system("cube10", L=3)
+    solver = T.Solver(s)
+    a = solver.run()[0]
+    b = solver.run()[0]
+    solver.close()
+    assert a.branches == b.branches
+    assert np.array_equal(a.X1[0].val, b.X1[0].val)
+    assert np.array_equal(a.X0.col, b.X0.col)
