@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark of the TC2 + response solve on one MI355X.
+
+One step = one complete solve (``tc2_run``): Gershgorin bounds, initial
+matrices, every TC2 / TC2-CPSCF update (symbolic pattern, MFMA block
+products, drop, reductions, branch) until the stopping rule, with the inputs
+already resident in HBM (uploaded by ``tc2_setup`` before timing).
+
+Prints one JSON line.  ``value`` is useful GFLOP/s of the chosen precision
+variant (2 b^3 per block triple landing on a kept output block, times the
+1 + 2D block products of an update); ``ms_per_step`` is seconds per solve in
+ms.  The plain FP64 path is run too and the chosen variant is gated against
+it (max |dX1| < 1e-6, relative |d alpha| < 1e-6).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sysm, gpu_iters: int, useful_flops: float, iters_sample: int = 1) -> dict:
+    """The FP64 oracle on the host cores: ``iters_sample`` full-size TC2 updates
+    (dense products, block drop, band energies) timed, scaled to a whole solve
+    by the GPU's update count."""
+    import numpy as np
+    from oracle import tc2_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()
+                       if p.get("user_api") == "blas"] or [os.cpu_count() or 1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    H = O.bsr_to_dense(sysm.H.nb, sysm.H.b, sysm.H.row_ptr, sysm.H.col, sysm.H.val)
+    H1s = [O.bsr_to_dense(h.nb, h.b, h.row_ptr, h.col, h.val) for h in sysm.H1]
+    emin, emax = O.gershgorin(H)
+    X0, X1s = O.tc2_init(H, H1s, emin, emax)
+    b = sysm.H.b
+    t0 = time.perf_counter()
+    for _ in range(iters_sample):
+        sq = np.trace(X0) >= sysm.n_occ
+        X0, X1s = O.tc2_step(X0, X1s, sq)
+        X0 = O.block_drop(X0, b, sysm.eps)
+        X1s = [O.block_drop(X, b, sysm.eps) for X in X1s]
+        O.band_energies(X0, X1s, H, H1s)
+    dt = (time.perf_counter() - t0) / iters_sample
+    solve_s = dt * gpu_iters
+    return {"value": round(useful_flops / solve_s / 1e9, 3), "unit": "GFLOP/s",
+            "cores": int(threads), "kind": "oracle",
+            "s_per_solve": round(solve_s, 2),
+            "sample": f"{iters_sample} dense FP64 oracle update(s) at full size "
+                      f"(N={sysm.H.n}), {dt:.1f} s each, scaled by {gpu_iters} updates"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cube10")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has "
+              "no multi-GPU path", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2009_03551_amd import tc2 as T
+    from paper_2009_03551_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    sysm = W.config_system(args.workload)
+    log(f"workload {args.workload}: atoms={sysm.H.nb} b={sysm.H.b} N={sysm.H.n} "
+        f"nnzb(H)={sysm.H.nnzb} dirs={len(sysm.H1)} eps={sysm.eps} tol={sysm.tol}")
+
+    # plain FP64 path: reference for the gate, and its own timing
+    ref_solver = T.Solver(sysm, precision="fp64", export=True, profile=True)
+    ref = ref_solver.run(stream=stream)[0]
+    torch.cuda.synchronize()
+    log(f"fp64 reference: {ref.status_name} iters={ref.iters} {ref.branches} "
+        f"alpha={ref.alpha} kept={ref.kept_blocks} {ref.seconds:.3f}s")
+
+    chosen = args.precision
+    closing = 0 if chosen == "fp64" else 2
+    solver = T.Solver(sysm, precision=chosen, closing_fp64=closing, export=False, profile=True)
+    for _ in range(args.warmup):
+        solver.run(stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(args.steps):
+        results.append(solver.run(stream=stream)[0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+    r = results[-1]
+    value = r.useful_flops / (ms_per_step * 1e-3) / 1e9
+    ms_num = sum(x.ms_numeric for x in results) / len(results)
+    launches = results[-1].numeric_launches
+    achieved = r.useful_flops / (ms_num * 1e-3) / 1e12
+    peak = PEAK_TFLOPS["fp64" if chosen == "fp64" else ("fp32" if chosen == "fp32" else "bf16")]
+    log(f"{chosen}: {ms_per_step:.1f} ms/solve, numeric {ms_num:.1f} ms in {launches} launches, "
+        f"symbolic {r.ms_symbolic:.1f} ms, compact {r.ms_compact:.1f} ms, "
+        f"useful {r.useful_flops / 1e12:.3f} TF, executed {r.executed_flops / 1e12:.3f} TF")
+
+    # gate of the chosen variant against the plain FP64 path
+    if chosen == "fp64":
+        gate = {"max_abs_dX1": 0.0, "rel_dalpha": 0.0, "pass": True}
+    else:
+        g = T.Solver(sysm, precision=chosen, closing_fp64=closing, export=True).run(stream=stream)[0]
+        dx1 = max(float(np.abs(T.bsr_dense(a) - T.bsr_dense(b)).max())
+                  for a, b in zip(g.X1, ref.X1))
+        dal = max(abs(x - y) / abs(y) for x, y in zip(g.alpha, ref.alpha))
+        gate = {"max_abs_dX1": dx1, "rel_dalpha": dal, "pass": bool(dx1 < 1e-6 and dal < 1e-6)}
+
+    out = {
+        "metric": "TC2+response s/solve & useful GFLOP/s, chosen vs plain FP64 at max|dX1|<1e-6",
+        "value": round(value, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "s_per_solve": round(ms_per_step * 1e-3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[chosen],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "atoms": sysm.H.nb, "b": sysm.H.b,
+                   "N": sysm.H.n, "directions": len(sysm.H1), "eps": sysm.eps,
+                   "tol": sysm.tol, "precision": chosen, "closing_fp64": closing,
+                   "iters": r.iters, "status": r.status_name},
+        "plain_fp64": {"s_per_solve": round(ref.seconds, 4),
+                       "useful_gflops": round(ref.useful_flops / ref.seconds / 1e9, 3)},
+        "speedup_vs_plain_fp64": round(ref.seconds / (ms_per_step * 1e-3), 3),
+        "gate": gate,
+        "useful_tflop_per_solve": round(r.useful_flops / 1e12, 4),
+        "executed_tflop_per_solve": round(r.executed_flops / 1e12, 4),
+        "roofline": {"bound": "mfma", "kernel": "k_numeric", "achieved": round(achieved, 3),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": None,
+                     "executed_frac": round(r.executed_flops / (ms_num * 1e-3) / 1e12 / peak, 4),
+                     "launches_per_solve": launches,
+                     "avg_launch_ms": round(ms_num / max(launches, 1), 4)},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(sysm, r.iters, r.useful_flops, args.cpu_sample_iters)
+    print(json.dumps(out), flush=True)
+    solver.close()
+    ref_solver.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

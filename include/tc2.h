@@ -89,6 +89,7 @@ typedef struct {
   int32_t device;          /* HIP device ordinal                                 */
   int32_t export_matrices; /* 1: tc2_run copies X0/X1 back to host views         */
   int32_t verbose;         /* 1: per-iteration log on stderr                     */
+  int32_t profile;         /* 1: time each phase with HIP events on the stream   */
 } tc2_options;
 
 typedef struct {
@@ -104,6 +105,10 @@ typedef struct {
   double seconds;          /* device time of the solve                           */
   double useful_flops;     /* 2 b^3 per block triple landing on a kept block     */
   double executed_flops;   /* MFMA flops issued, padding included                */
+  int64_t kept_blocks;     /* stored blocks of the final X pattern (both halves) */
+  /* phase times in ms, summed over the updates (profile = 1 only) */
+  double ms_symbolic, ms_numeric, ms_compact;
+  int32_t numeric_launches;
   char branches[TC2_MAX_ITER + 4]; /* 'S'/'D' per update, NUL-terminated        */
   /* Library-owned host copies (valid until the next tc2_run or tc2_free) when
      export_matrices = 1; same layout as the inputs.  Otherwise zeroed. */

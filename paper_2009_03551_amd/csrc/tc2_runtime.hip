@@ -79,6 +79,10 @@ struct tc2_ctx {
   int device = 0;
   hipStream_t own = nullptr;
   int nsys = 0, D = 0, b = 0, nb = 0, prec = P_FP64, closing = 0, verbose = 0, export_m = 0;
+  int profile = 0;
+  hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};
+  double ms_sym = 0, ms_num = 0, ms_cmp = 0;
+  int num_launches = 0;
   int max_sys_atoms = 0;
   std::vector<SysInfo> sys;
   // host copies kept for export
@@ -211,6 +215,8 @@ void tc2_free(tc2_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
+  for (hipEvent_t& e : ctx->pev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -276,12 +282,16 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   ctx->verbose = o->verbose;
   ctx->export_m = o->export_matrices;
   ctx->max_sys_atoms = max_atoms;
+  ctx->profile = o->profile;
   tc2_status st = TC2_OK;
   auto fail = [&](tc2_status s) {
     tc2_free(ctx);
     return s;
   };
   if (hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess) return fail(TC2_EDEVICE);
+  if (ctx->profile)
+    for (hipEvent_t& e : ctx->pev)
+      if (hipEventCreate(&e) != hipSuccess) return fail(TC2_EDEVICE);
 
   // systems
   std::vector<int> sys_of(nb_tot), sys_start(np), sys_end(np), mode(np);
@@ -451,6 +461,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   int hcnt[4];
 
   // ---- symbolic
+  if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[0], st));
   HIPCHK(ctx->cand_cnt.reserve((size_t)nb * 4));
   HIPCHK(ctx->cand_rp.reserve((size_t)(nb + 1) * 4));
   SymArgs sa{};
@@ -471,6 +482,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   HIPCHK(ctx->cand_ci.reserve((size_t)std::max(ncand, 1) * 4));
   sa.cand_ci = ctx->cand_ci.as<int>();
   launch_symbolic(st, 1, sa);
+  if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[1], st));
 
   // ---- work items
   HIPCHK(ctx->item_cnt.reserve((size_t)nb * 4));
@@ -490,8 +502,19 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   launch_sys_items(st, ctx->nsys, ctx->sys_start.as<int>(), ctx->sys_end.as<int>(), ctx->item_rp.as<int>(),
                    ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>());
 
-  // ---- numeric (retried with a larger stage if it overflows)
-  if (ctx->stage_cap == 0) ctx->stage_cap = std::max(ctx->nnz[c], nb) + 1024;
+  // ---- numeric (retried with a larger stage if it overflows).  The stage
+  // holds every candidate when that fits a modest budget, else an estimate.
+  {
+    const size_t budget = (size_t)16 << 30;
+    if ((size_t)ncand * tile <= budget) ctx->stage_cap = std::max(ctx->stage_cap, ncand);
+    else if (ctx->stage_cap == 0) ctx->stage_cap = std::max(ctx->nnz[c], nb) + 1024;
+  }
+  if (ctx->profile) {
+    HIPCHK(hipEventSynchronize(ctx->pev[1]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->pev[0], ctx->pev[1]));
+    ctx->ms_sym += ms;
+  }
   HIPCHK(ctx->exec_pairs.reserve(8));
   int n_kept = 0;
   unsigned long long pairs = 0;
@@ -535,11 +558,19 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     na.bad = ctx->bad.as<int>();
     na.partial = ctx->partial.as<double>();
     na.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
+    if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[2], st));
     launch_numeric(st, ctx->cur_prec, na);
     HIPCHK(hipGetLastError());
+    if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[3], st));
     HIPCHK(hipMemcpyAsync(hcnt, cnt, 16, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&pairs, ctx->exec_pairs.p, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (ctx->profile) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ctx->pev[2], ctx->pev[3]));
+      ctx->ms_num += ms;
+      ctx->num_launches++;
+    }
     if (!hcnt[2]) {
       n_kept = hcnt[1];
       break;
@@ -552,6 +583,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   ctx->stage_cap = std::max(ctx->stage_cap, n_kept * 5 / 4 + 1024);
 
   // ---- compaction into the new pattern
+  if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[0], st));
   HIPCHK(ctx->rowcnt.reserve((size_t)nb * 4));
   HIPCHK(ctx->cursor.reserve((size_t)nb * 4));
   HIPCHK(ctx->rp[n].reserve((size_t)(nb + 1) * 4));
@@ -587,6 +619,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   launch_gather(st, ctx->cur_prec, nnz_new, D, ctx->new_src.as<int>(), ctx->stage.p, ctx->xv[n].p);
   ctx->nnz[n] = nnz_new;
   ctx->cur = n;
+  if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[1], st));
 
   // ---- per-system scalars of the new iterate
   HIPCHK(ctx->scal.reserve((size_t)ctx->nsys * NQ * 8));
@@ -596,6 +629,11 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   HIPCHK(hipMemcpyAsync(scal.data(), ctx->scal.p, scal.size() * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
+  if (ctx->profile) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->pev[0], ctx->pev[1]));
+    ctx->ms_cmp += ms;
+  }
   return TC2_OK;
 }
 
@@ -647,6 +685,8 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
   hipStream_t st = stream ? (hipStream_t)stream : ctx->own;
   const int nsys = ctx->nsys, D = ctx->D, b = ctx->b, nb = ctx->nb;
   std::vector<SysState> ss(nsys);
+  ctx->ms_sym = ctx->ms_num = ctx->ms_cmp = 0.0;
+  ctx->num_launches = 0;
   hipEvent_t ev0, ev1;
   HIPCHK(hipEventCreate(&ev0));
   HIPCHK(hipEventCreate(&ev1));
@@ -804,6 +844,10 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
     st0 = export_results(ctx, st);
     if (st0 != TC2_OK) return st0;
   }
+  std::vector<int> final_rp(nb + 1);
+  HIPCHK(hipMemcpyAsync(final_rp.data(), ctx->rp[ctx->cur].p, (size_t)(nb + 1) * 4,
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
   tc2_status worst = TC2_OK;
   const double b3 = 2.0 * b * b * b;
   const double kst = (double)((b + 3) / 4) * 4;
@@ -827,6 +871,11 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
     R.useful_flops = ss[s].trip * b3 * (1 + 2 * D);
     R.executed_flops = (s == 0) ? (double)exec_pairs * (1 + 2 * D) * 2.0 * BP * BP * kst : 0.0;
     strncpy(R.branches, ss[s].branches.c_str(), TC2_MAX_ITER + 3);
+    R.ms_symbolic = ctx->ms_sym;
+    R.ms_numeric = ctx->ms_num;
+    R.ms_compact = ctx->ms_cmp;
+    R.numeric_launches = ctx->num_launches;
+    R.kept_blocks = final_rp[ctx->sys[s].row0 + ctx->sys[s].nb] - final_rp[ctx->sys[s].row0];
     if (ctx->export_m) {
       HostBsr& x0 = ctx->out_x0[s];
       R.X0 = tc2_bsr{ctx->sys[s].nb, b, x0.row_ptr.data(), x0.col.data(), x0.val.data()};

@@ -37,7 +37,8 @@ class tc2_problem(C.Structure):
 
 class tc2_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("closing_fp64", C.c_int32), ("skip", C.c_int32),
-                ("device", C.c_int32), ("export_matrices", C.c_int32), ("verbose", C.c_int32)]
+                ("device", C.c_int32), ("export_matrices", C.c_int32), ("verbose", C.c_int32),
+                ("profile", C.c_int32)]
 
 
 class tc2_result(C.Structure):
@@ -45,7 +46,10 @@ class tc2_result(C.Structure):
                 ("tr_x0", C.c_double), ("idem_err", C.c_double), ("tr_x1", C.c_double * 3),
                 ("e0", C.c_double), ("e1", C.c_double * 3), ("emin", C.c_double),
                 ("emax", C.c_double), ("seconds", C.c_double), ("useful_flops", C.c_double),
-                ("executed_flops", C.c_double), ("branches", C.c_char * (TC2_MAX_ITER + 4)),
+                ("executed_flops", C.c_double), ("kept_blocks", C.c_int64),
+                ("ms_symbolic", C.c_double), ("ms_numeric", C.c_double),
+                ("ms_compact", C.c_double), ("numeric_launches", C.c_int32),
+                ("branches", C.c_char * (TC2_MAX_ITER + 4)),
                 ("X0", tc2_bsr), ("X1", tc2_bsr * 3)]
 
 
@@ -101,6 +105,11 @@ class Result:
     seconds: float
     useful_flops: float
     executed_flops: float
+    kept_blocks: int = 0
+    ms_symbolic: float = 0.0
+    ms_numeric: float = 0.0
+    ms_compact: float = 0.0
+    numeric_launches: int = 0
     X0: Optional[BSR] = None
     X1: List[BSR] = field(default_factory=list)
 
@@ -133,7 +142,8 @@ class Solver:
 
     def __init__(self, systems: Union[System, Sequence[System]], precision: str = "fp64",
                  closing_fp64: int = 0, export: bool = True, device: int = 0,
-                 replay: Optional[Sequence[Optional[str]]] = None, verbose: bool = False):
+                 replay: Optional[Sequence[Optional[str]]] = None, verbose: bool = False,
+                 profile: bool = False):
         if isinstance(systems, System):
             systems = [systems]
         self.systems = list(systems)
@@ -159,7 +169,7 @@ class Solver:
                 p.replay = None
         self.n_dir = len(self.systems[0].H1)
         opts = tc2_options(PRECISION[precision], int(closing_fp64), 0, int(device),
-                           1 if export else 0, 1 if verbose else 0)
+                           1 if export else 0, 1 if verbose else 0, 1 if profile else 0)
         self._ctx = C.c_void_p()
         st = lib().tc2_setup(probs, n, C.byref(opts), C.byref(self._ctx))
         if st != 0:
@@ -179,7 +189,8 @@ class Solver:
             out.append(Result(r.status, r.iters, r.branches.decode(), list(r.trace_x1h1[:D]),
                               r.tr_x0, r.idem_err, list(r.tr_x1[:D]), r.e0, list(r.e1[:D]),
                               r.emin, r.emax, r.seconds, r.useful_flops, r.executed_flops,
-                              x0, x1))
+                              r.kept_blocks, r.ms_symbolic, r.ms_numeric, r.ms_compact,
+                              r.numeric_launches, x0, x1))
         return out
 
     def close(self):
