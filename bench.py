@@ -71,6 +71,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cube10")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--kernel", default="tile", choices=["tile", "block"])
+    ap.add_argument("--skip", default="none", choices=["none", "bound"])
+    ap.add_argument("--fp64-first", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=1)
     args = ap.parse_args()
@@ -95,7 +98,7 @@ def main() -> int:
         f"nnzb(H)={sysm.H.nnzb} dirs={len(sysm.H1)} eps={sysm.eps} tol={sysm.tol}")
 
     # plain FP64 path: reference for the gate, and its own timing
-    ref_solver = T.Solver(sysm, precision="fp64", export=True, profile=True)
+    ref_solver = T.Solver(sysm, precision="fp64", export=True, profile=True, kernel=args.kernel)
     ref = ref_solver.run(stream=stream)[0]
     torch.cuda.synchronize()
     log(f"fp64 reference: {ref.status_name} iters={ref.iters} {ref.branches} "
@@ -103,7 +106,9 @@ def main() -> int:
 
     chosen = args.precision
     closing = 0 if chosen == "fp64" else 2
-    solver = T.Solver(sysm, precision=chosen, closing_fp64=closing, export=False, profile=True)
+    variant = dict(precision=chosen, closing_fp64=closing, kernel=args.kernel, skip=args.skip,
+                   fp64_first=args.fp64_first if chosen != "fp64" else 0)
+    solver = T.Solver(sysm, export=False, profile=True, **variant)
     for _ in range(args.warmup):
         solver.run(stream=stream)
     torch.cuda.synchronize()
@@ -128,7 +133,7 @@ def main() -> int:
     if chosen == "fp64":
         gate = {"max_abs_dX1": 0.0, "rel_dalpha": 0.0, "pass": True}
     else:
-        g = T.Solver(sysm, precision=chosen, closing_fp64=closing, export=True).run(stream=stream)[0]
+        g = T.Solver(sysm, export=True, **variant).run(stream=stream)[0]
         dx1 = max(float(np.abs(T.bsr_dense(a) - T.bsr_dense(b)).max())
                   for a, b in zip(g.X1, ref.X1))
         dal = max(abs(x - y) / abs(y) for x, y in zip(g.alpha, ref.alpha))
@@ -151,14 +156,17 @@ def main() -> int:
         "config": {"workload": args.workload, "atoms": sysm.H.nb, "b": sysm.H.b,
                    "N": sysm.H.n, "directions": len(sysm.H1), "eps": sysm.eps,
                    "tol": sysm.tol, "precision": chosen, "closing_fp64": closing,
-                   "iters": r.iters, "status": r.status_name},
+                   "iters": r.iters, "status": r.status_name, "kernel": args.kernel,
+                   "skip": args.skip, "fp64_first": variant["fp64_first"],
+                   "screened_blocks": r.screened_blocks},
         "plain_fp64": {"s_per_solve": round(ref.seconds, 4),
                        "useful_gflops": round(ref.useful_flops / ref.seconds / 1e9, 3)},
         "speedup_vs_plain_fp64": round(ref.seconds / (ms_per_step * 1e-3), 3),
         "gate": gate,
         "useful_tflop_per_solve": round(r.useful_flops / 1e12, 4),
         "executed_tflop_per_solve": round(r.executed_flops / 1e12, 4),
-        "roofline": {"bound": "mfma", "kernel": "k_numeric", "achieved": round(achieved, 3),
+        "roofline": {"bound": "mfma",
+                     "kernel": "k_tile_numeric" if args.kernel == "tile" else "k_numeric", "achieved": round(achieved, 3),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": None,
                      "executed_frac": round(r.executed_flops / (ms_num * 1e-3) / 1e12 / peak, 4),

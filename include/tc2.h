@@ -75,6 +75,8 @@ typedef struct {
   int32_t max_iter;        /* 1..TC2_MAX_ITER                                    */
   const char *replay;      /* NULL, or a string of 'S'/'D' forcing each step's
                               branch (exactly strlen(replay) steps are run)    */
+  const double *xyz;       /* NULL, or nb x 3 atom positions: used only to group
+                              nearby atoms into clusters for the tiled kernel  */
 } tc2_problem;
 
 #define TC2_MAX_ITER 200
@@ -82,14 +84,23 @@ typedef struct {
 enum { TC2_FP64 = 0, TC2_FP32 = 1, TC2_BF16 = 2 };
 
 typedef struct {
-  int32_t precision;       /* TC2_FP64 / TC2_FP32 / TC2_BF16 block products      */
+  int32_t precision;       /* TC2_FP64 / TC2_FP32 / TC2_BF16 block products.  FP32
+                              and BF16 keep X in FP32 with FP32 accumulation;
+                              BF16 rounds the MFMA operands to bfloat16; traces,
+                              branch and stopping tests stay in FP64           */
   int32_t closing_fp64;    /* 0, or 2: finish a reduced-precision solve with two
                               FP64 steps of opposite branches                  */
-  int32_t skip;            /* 0: no screening (all candidate blocks computed)    */
+  int32_t skip;            /* 0: every candidate block is computed; 1: exact
+                              norm-bound screen (skips blocks that are certainly
+                              dropped; results unchanged); tiled kernel only   */
   int32_t device;          /* HIP device ordinal                                 */
   int32_t export_matrices; /* 1: tc2_run copies X0/X1 back to host views         */
   int32_t verbose;         /* 1: per-iteration log on stderr                     */
   int32_t profile;         /* 1: time each phase with HIP events on the stream   */
+  int32_t numeric_kernel;  /* 0: clustered output tiles (default); 1: one wave per
+                              output block (reference kernel; FP64/FP32 only)  */
+  int32_t fp64_first;      /* reduced precision only: number of leading updates
+                              run in FP64 before switching (0..TC2_MAX_ITER)   */
 } tc2_options;
 
 typedef struct {
@@ -106,6 +117,8 @@ typedef struct {
   double useful_flops;     /* 2 b^3 per block triple landing on a kept block     */
   double executed_flops;   /* MFMA flops issued, padding included                */
   int64_t kept_blocks;     /* stored blocks of the final X pattern (both halves) */
+  int64_t screened_blocks; /* output blocks skipped by the screen, all updates
+                              (batch total, reported on the first problem)    */
   /* phase times in ms, summed over the updates (profile = 1 only) */
   double ms_symbolic, ms_numeric, ms_compact;
   int32_t numeric_launches;

@@ -23,6 +23,7 @@ constexpr int MAXD = 3;       // field directions
 constexpr int NQ = 4 + 3 * MAXD;  // per-work-item partial sums (see Q_*)
 constexpr int CHUNK = 32;     // candidates per numeric work item
 constexpr int MAX_SYS_BITS = 1 << 19;  // atoms per system (symbolic bitmap)
+constexpr int CS = 8;         // atoms per cluster (tiled numeric kernel)
 
 // partial-sum slots
 enum {
@@ -100,6 +101,88 @@ struct NumArgs {
   unsigned long long* exec_pairs;  // block triples issued (all candidates)
 };
 
+// Cluster row panels: for cluster P the sorted union of the columns K of its
+// atoms' rows, with the entry index of (I_s, K) for each member s (-1 absent).
+struct PanelArgs {
+  int nc;
+  const int* rp;
+  const int* ci;
+  const int* clus_atom;   // nc x CS, -1 padded
+  const int* clus_sys;    // cluster -> system
+  const int* sys_start;
+  const int* sys_end;
+  const int* csys_start;  // system -> first cluster
+  const int* csys_end;
+  const int* atom_clus;   // atom -> cluster
+  const int* active;
+  int max_sys_atoms;
+  int max_sys_clusters;
+  // panels
+  int* panel_cnt;         // nc
+  const int* panel_rp;    // nc+1
+  int* panel_k;
+  int* panel_e;           // 8 per panel entry
+  // tiles
+  int* tile_cnt;          // nc
+  long long* tile_pairs;  // nc: upper bound of output pairs of the tiles of P
+  const int* tile_rp;     // nc+1
+  int* tile_p;
+  int* tile_q;
+};
+
+struct TileArgs {
+  int D;
+  int bf16;               // FP32 values, MFMA operands rounded to bfloat16
+  int skip;               // 0 none, 1 exact norm-bound screen
+  const float* bn;        // block norms (nnz x (1+D)) when skip != 0
+  unsigned long long* screened;  // outputs skipped by the screen
+  int ksteps;
+  int n_tiles;
+  const int* rp;
+  const int* ci;
+  const void* xv;
+  const int* tile_p;
+  const int* tile_q;
+  const int* clus_atom;
+  const int* clus_sys;
+  const int* panel_rp;
+  const int* panel_k;
+  const int* panel_e;
+  const int* branch;
+  const double* eps;
+  const int* h_rp;
+  const int* h_ci;
+  const double* h_v;
+  const int* h1_rp[MAXD];
+  const int* h1_ci[MAXD];
+  const double* h1_v[MAXD];
+  void* stage;
+  int2* kept_ij;
+  int* stage_count;
+  int stage_cap;
+  int* overflow;
+  int* bad;
+  double* partial;        // n_tiles x NQ
+  unsigned long long* exec_pairs;
+};
+
+// Rows of systems that stopped iterating: their upper blocks go to the stage
+// unchanged.
+struct CopyArgs {
+  int nb;
+  int D;
+  const int* rp;
+  const int* ci;
+  const void* xv;
+  const int* sys_of;
+  const int* active;
+  void* stage;
+  int2* kept_ij;
+  int* stage_count;
+  int stage_cap;
+  int* overflow;
+};
+
 struct CompactArgs {
   int nb;
   int D;
@@ -134,6 +217,12 @@ void launch_items(hipStream_t st, int nb, const int* cand_rp, const int* item_rp
 void launch_items_count(hipStream_t st, int nb, const int* cand_rp, int* item_cnt);
 void launch_numeric(hipStream_t st, int prec, const NumArgs& a);
 void launch_measure(hipStream_t st, int prec, const MeasArgs& a);
+void launch_panels(hipStream_t st, int pass, const PanelArgs& a);
+void launch_tiles(hipStream_t st, int pass, const PanelArgs& a);
+void launch_tile_numeric(hipStream_t st, int prec, const TileArgs& a);
+int tile_split(int prec, int D);  // blocks per tile of the tiled kernel
+void launch_copy_through(hipStream_t st, int prec, const CopyArgs& a, int nnz);
+void launch_block_norms(hipStream_t st, int prec, long long nnz, int D, const void* xv, float* bn);
 void launch_compact_count(hipStream_t st, const CompactArgs& a, int n_kept);
 void launch_compact_scatter(hipStream_t st, const CompactArgs& a, int n_kept);
 void launch_row_sort(hipStream_t st, const CompactArgs& a);
@@ -141,7 +230,7 @@ void launch_gather(hipStream_t st, int prec, int nnz, int D, const int* new_src,
                    const void* stage, void* xv);
 void launch_reduce(hipStream_t st, int nsys, const int* sys_item_lo, const int* sys_item_hi,
                    const double* partial, double* scal);
-void launch_sys_items(hipStream_t st, int nsys, const int* sys_start, const int* sys_end,
+void launch_sys_items(hipStream_t st, int nsys, int mult, const int* sys_start, const int* sys_end,
                       const int* item_rp, int* lo, int* hi);
 void launch_export(hipStream_t st, int prec, int nnz, int D, int m, int b, const void* xv,
                    double* out);

@@ -11,56 +11,9 @@
 //               block Frobenius norms, drop (filter of Sec. 2.4), traces and
 //               band-energy partial sums;
 //   compact   : kept upper blocks -> new sorted symmetric pattern + values.
-#include "tc2_internal.h"
-
-#include <hip/hip_bf16.h>
+#include "tc2_device.h"
 
 namespace tc2 {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef short s4 __attribute__((ext_vector_type(4)));
-
-// ------------------------------------------------------------------ helpers
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-
-// first index p in [0, n) with a[p] == key, or -1 (a sorted ascending)
-__device__ __forceinline__ int bsearch_eq(const int* a, int n, int key) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    int v = a[mid];
-    if (v < key) lo = mid + 1; else hi = mid;
-  }
-  return (lo < n && a[lo] == key) ? lo : -1;
-}
-
-// Accumulator of one 16 x 16 output tile.  The MFMA result layout differs
-// between the f64 and f32 instructions (checked on the device):
-//   f64 16x16x4: lane l, register j holds row l/16 + 4j, column l%16;
-//   f32 16x16x4: lane l, register j holds row 4(l/16) + j, column l%16.
-template <typename T> struct Acc;
-template <> struct Acc<double> {
-  d4 v;
-  __device__ static int row(int l, int j) { return (l >> 4) + 4 * j; }
-};
-template <> struct Acc<float> {
-  f4 v;
-  __device__ static int row(int l, int j) { return 4 * (l >> 4) + j; }
-};
-
-__device__ __forceinline__ void mfma(Acc<double>& c, double a, double b) {
-  c.v = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c.v, 0, 0, 0);
-}
-__device__ __forceinline__ void mfma(Acc<float>& c, float a, float b) {
-  c.v = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c.v, 0, 0, 0);
-}
 
 // ------------------------------------------------------------------ Gershgorin
 // Bounds of the spectrum of H (Sec. 2.3): per scalar row i, H_ii -+ sum_{j!=i} |H_ij|.
@@ -153,8 +106,7 @@ __global__ void k_init(long long n, int D, int b, const int* row_of, const int* 
 // ------------------------------------------------------------------ symbolic
 // Upper-triangle candidate pattern of the product: for row I the union over
 // K in row(I) of {J in row(K) : J >= I}.  Pass 0 counts, pass 1 writes the
-// sorted columns.  Rows of systems that no longer iterate keep their own
-// upper pattern (copy-through).
+// sorted columns.
 __global__ __launch_bounds__(256) void k_symbolic(int pass, SymArgs a) {
   extern __shared__ unsigned sbits[];
   __shared__ int sscan[256];
@@ -164,23 +116,8 @@ __global__ __launch_bounds__(256) void k_symbolic(int pass, SymArgs a) {
   const int nwords = (nbits + 31) >> 5;
   const int t = threadIdx.x;
   const int r0 = a.rp[I], r1 = a.rp[I + 1];
-  if (!a.active[s]) {
-    // copy-through: own upper entries
-    if (pass == 0) {
-      int cnt = 0;
-      for (int e = r0 + t; e < r1; e += blockDim.x) cnt += a.ci[e] >= I;
-      sscan[t] = cnt;
-      __syncthreads();
-      for (int o = 128; o > 0; o >>= 1) {
-        if (t < o) sscan[t] += sscan[t + o];
-        __syncthreads();
-      }
-      if (t == 0) a.cand_cnt[I] = sscan[0];
-    } else if (t == 0) {
-      int base = a.cand_rp[I];
-      for (int e = r0; e < r1; ++e)
-        if (a.ci[e] >= I) a.cand_ci[base++] = a.ci[e];
-    }
+  if (!a.active[s]) {  // stopped systems are carried by the copy-through kernel
+    if (pass == 0 && t == 0) a.cand_cnt[I] = 0;
     return;
   }
   for (int w = t; w < nwords; w += blockDim.x) sbits[w] = 0u;
@@ -278,12 +215,12 @@ __global__ void k_items(int nb, const int* cand_rp, const int* item_rp, int* ite
   }
 }
 
-__global__ void k_sys_items(int nsys, const int* sys_start, const int* sys_end,
+__global__ void k_sys_items(int nsys, int mult, const int* sys_start, const int* sys_end,
                             const int* item_rp, int* lo, int* hi) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsys) return;
-  lo[s] = item_rp[sys_start[s]];
-  hi[s] = item_rp[sys_end[s]];
+  lo[s] = mult * item_rp[sys_start[s]];
+  hi[s] = mult * item_rp[sys_end[s]];
 }
 
 // ------------------------------------------------------------------ numeric
@@ -300,7 +237,6 @@ __global__ __launch_bounds__(256) void k_numeric(NumArgs a) {
   const int r0 = a.rp[I], mI = a.rp[I + 1] - r0;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int s = a.sys_of[I];
-  const bool active = a.active[s] != 0;
   const bool square = a.branch[s] != 0;
   const double eps = a.eps[s];
   const int* rowI = a.ci + r0;
@@ -312,6 +248,9 @@ __global__ __launch_bounds__(256) void k_numeric(NumArgs a) {
 
   const T* X = (const T*)a.xv;
   const size_t stride = (size_t)(1 + D) * BS;
+  EpiCtx E{a.xv, stride, a.h_rp, a.h_ci, a.h_v, {a.h1_rp[0], a.h1_rp[1], a.h1_rp[2]},
+           {a.h1_ci[0], a.h1_ci[1], a.h1_ci[2]}, {a.h1_v[0], a.h1_v[1], a.h1_v[2]}, a.stage,
+           a.kept_ij, a.stage_count, a.stage_cap, a.overflow, a.bad};
   double q[NQ];
 #pragma unroll
   for (int k = 0; k < NQ; ++k) q[k] = 0.0;
@@ -319,151 +258,46 @@ __global__ __launch_bounds__(256) void k_numeric(NumArgs a) {
 
   for (int c = c0 + wave; c < c1; c += 4) {
     const int J = a.cand_ci[c];
-    const bool diag = (J == I);
-    Acc<T> acc0;
-    Acc<T> acc1[D > 0 ? D : 1];
+    Acc<T> acc[1 + D];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc0.v[j] = 0;
+    for (int m = 0; m <= D; ++m)
 #pragma unroll
-    for (int d = 0; d < (D > 0 ? D : 1); ++d)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc1[d].v[j] = 0;
+      for (int j = 0; j < 4; ++j) acc[m].v[j] = 0;
     int npairs = 0;
-    if (active) {
-      const int f0 = a.rp[J], f1 = a.rp[J + 1];
-      for (int base = f0; base < f1; base += 64) {
-        const int f = base + lane;
-        int pos = -1;
-        if (f < f1) pos = bsearch_eq(rowI, mI, a.ci[f]);
-        const bool found = pos >= 0;
-        const unsigned long long mask = __ballot(found);
-        const int n = __popcll(mask);
-        if (n == 0) continue;
-        const int my = __popcll(mask & ((1ull << lane) - 1ull));
-        const int dst = found ? my : n + (lane - my);
-        const int vI = __builtin_amdgcn_ds_permute(dst << 2, r0 + pos);
-        const int vJ = __builtin_amdgcn_ds_permute(dst << 2, f);
-        npairs += n;
-        for (int i = 0; i < n; ++i) {
-          const int pI = __builtin_amdgcn_readlane(vI, i);
-          const int pJ = __builtin_amdgcn_readlane(vJ, i);
-          const T* xa = X + (size_t)pI * stride + lane;
-          const T* xb = X + (size_t)pJ * stride + lane;
-          for (int kk = 0; kk < a.ksteps; ++kk) {
-            const T a0 = xa[kk * 64], b0 = xb[kk * 64];
-            mfma(acc0, a0, b0);
+    const int f0 = a.rp[J], f1 = a.rp[J + 1];
+    for (int base = f0; base < f1; base += 64) {
+      const int f = base + lane;
+      int pos = -1;
+      if (f < f1) pos = bsearch_eq(rowI, mI, a.ci[f]);
+      const bool found = pos >= 0;
+      const unsigned long long mask = __ballot(found);
+      const int n = __popcll(mask);
+      if (n == 0) continue;
+      const int my = __popcll(mask & ((1ull << lane) - 1ull));
+      const int dst = found ? my : n + (lane - my);
+      const int vI = __builtin_amdgcn_ds_permute(dst << 2, r0 + pos);
+      const int vJ = __builtin_amdgcn_ds_permute(dst << 2, f);
+      npairs += n;
+      for (int i = 0; i < n; ++i) {
+        const int pI = __builtin_amdgcn_readlane(vI, i);
+        const int pJ = __builtin_amdgcn_readlane(vJ, i);
+        const T* xa = X + (size_t)pI * stride + lane;
+        const T* xb = X + (size_t)pJ * stride + lane;
+        for (int kk = 0; kk < a.ksteps; ++kk) {
+          const T a0 = xa[kk * 64], b0 = xb[kk * 64];
+          mfma(acc[0], a0, b0);
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-              const T a1 = xa[(1 + d) * BS + kk * 64], b1 = xb[(1 + d) * BS + kk * 64];
-              mfma(acc1[d], a0, b1);
-              mfma(acc1[d], a1, b0);
-            }
+          for (int d = 0; d < D; ++d) {
+            const T a1 = xa[(1 + d) * BS + kk * 64], b1 = xb[(1 + d) * BS + kk * 64];
+            mfma(acc[1 + d], a0, b1);
+            mfma(acc[1 + d], a1, b0);
           }
         }
       }
-      issued += npairs;
     }
-
-    // ---- epilogue: combine with the branch, norms, drop, partial sums
-    const int pIJ = bsearch_eq(rowI, mI, J);  // old block (I, J), -1 if absent
-    const int col = lane & 15;
-    double v[1 + D][4];
-#pragma unroll
-    for (int m = 0; m <= D; ++m) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = Acc<T>::row(lane, j);
-        double old = 0.0;
-        if (pIJ >= 0) old = (double)X[(size_t)(r0 + pIJ) * stride + m * BS + col * BP + r];
-        double cval = (m == 0) ? (double)acc0.v[j] : (double)acc1[m > 0 ? m - 1 : 0].v[j];
-        double x;
-        if (!active) x = old;
-        else if (square) x = cval;
-        else x = 2.0 * old - cval;
-        v[m][j] = (T)x;  // the new iterate lives in working precision
-      }
-    }
-    double nrm2[1 + D];
-    bool keep[1 + D];
-    bool any = false;
-    bool bad = false;
-#pragma unroll
-    for (int m = 0; m <= D; ++m) {
-      double ss = 0.0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        ss += v[m][j] * v[m][j];
-        bad |= !isfinite(v[m][j]);
-      }
-      nrm2[m] = wave_sum(ss);
-      keep[m] = diag || !active || !(sqrt(nrm2[m]) < eps);
-      any |= keep[m];
-    }
-    if (__ballot(bad) != 0ull && lane == 0) atomicOr(&a.bad[s], 1);
-    if (any) {
-      int slot = 0;
-      if (lane == 0) slot = atomicAdd(a.stage_count, 1);
-      slot = __builtin_amdgcn_readfirstlane(slot);
-      if (slot < a.stage_cap) {
-        T* st = (T*)a.stage + (size_t)slot * stride;
-#pragma unroll
-        for (int m = 0; m <= D; ++m)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int r = Acc<T>::row(lane, j);
-            st[m * BS + r * BP + col] = keep[m] ? (T)v[m][j] : (T)0;
-          }
-        if (lane == 0) a.kept_ij[slot] = make_int2(I, J);
-      } else if (lane == 0) {
-        atomicOr(a.overflow, 1);
-      }
-    }
-    if (active) {
-      const double w = diag ? 1.0 : 2.0;
-      if (any) q[Q_TRIP] += (double)npairs;
-      if (diag) {
-#pragma unroll
-        for (int m = 0; m <= D; ++m) {
-          double tr = 0.0;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) tr += (Acc<T>::row(lane, j) == col) ? v[m][j] : 0.0;
-          tr = wave_sum(tr);
-          if (m == 0) q[Q_TR0] += tr; else q[Q_TR1 + m - 1] += tr;
-        }
-      }
-      if (keep[0]) q[Q_FRO0] += w * nrm2[0];
-      // band energies over the pattern of H, alpha over the pattern of H1_d
-      int eh = -1;
-      for (int e = a.h_rp[I]; e < a.h_rp[I + 1]; ++e)
-        if (a.h_ci[e] == J) { eh = e; break; }
-      if (eh >= 0) {
-        const double* hb = a.h_v + (size_t)eh * BS;
-#pragma unroll
-        for (int m = 0; m <= D; ++m) {
-          if (!keep[m]) continue;
-          double dot = 0.0;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) dot += v[m][j] * hb[col * BP + Acc<T>::row(lane, j)];
-          dot = wave_sum(dot);
-          if (m == 0) q[Q_E0] += w * dot; else q[Q_E1 + m - 1] += w * dot;
-        }
-      }
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        if (!keep[1 + d]) continue;
-        int e1 = -1;
-        for (int e = a.h1_rp[d][I]; e < a.h1_rp[d][I + 1]; ++e)
-          if (a.h1_ci[d][e] == J) { e1 = e; break; }
-        if (e1 >= 0) {
-          const double* hb = a.h1_v[d] + (size_t)e1 * BS;
-          double dot = 0.0;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) dot += v[1 + d][j] * hb[col * BP + Acc<T>::row(lane, j)];
-          dot = wave_sum(dot);
-          q[Q_AL + d] += w * dot;
-        }
-      }
-    }
+    issued += npairs;
+    const int pIJ = bsearch_eq(rowI, mI, J);
+    epilogue<T, D>(E, acc, I, J, pIJ >= 0 ? r0 + pIJ : -1, square, eps, npairs, s, q);
   }
   if (lane == 0) {
 #pragma unroll
@@ -726,9 +560,9 @@ void launch_items(hipStream_t st, int nb, const int* cand_rp, const int* item_rp
                      item_row, item_c0);
 }
 
-void launch_sys_items(hipStream_t st, int nsys, const int* sys_start, const int* sys_end,
-                      const int* item_rp, int* lo, int* hi) {
-  hipLaunchKernelGGL(k_sys_items, dim3(nblk(nsys, 64)), dim3(64), 0, st, nsys, sys_start,
+void launch_sys_items(hipStream_t st, int nsys, int mult, const int* sys_start,
+                      const int* sys_end, const int* item_rp, int* lo, int* hi) {
+  hipLaunchKernelGGL(k_sys_items, dim3(nblk(nsys, 64)), dim3(64), 0, st, nsys, mult, sys_start,
                      sys_end, item_rp, lo, hi);
 }
 

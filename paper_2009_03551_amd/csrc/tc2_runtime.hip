@@ -104,7 +104,18 @@ struct tc2_ctx {
   DBuf cand_cnt, cand_rp, cand_ci, item_cnt, item_rp, item_row, item_c0, partial;
   DBuf stage, kept_ij, counters, exec_pairs, rowcnt, cursor, tmp_ci, tmp_src, new_src;
   DBuf sys_lo, sys_hi, scal, rowlo, rowhi, xfer;
-  int stage_cap = 0;
+  long long stage_cap = 0;
+  int kernel = 0;                 // 0 tiled, 1 one wave per block
+  int fp64_first = 0;             // leading FP64 updates of a reduced-precision solve
+  int op_bf16 = 0;                // current stage rounds MFMA operands to bfloat16
+  int skip = 0;                   // 1: exact norm-bound screen in the tiled kernel
+  DBuf bn, screened;              // block norms, screened-output counter
+  unsigned long long screened_total = 0;
+  std::vector<int> h_active;      // host copy of the active flags
+  // clusters
+  int nc = 0, max_sys_clusters = 0;
+  DBuf clus_atom, clus_sys, atom_clus, csys_start, csys_end;
+  DBuf panel_cnt, panel_rp, panel_k, panel_e, tile_cnt, tile_rp, tile_pairs, tile_p, tile_q;
   // results
   std::vector<HostBsr> out_x0;
   std::vector<HostBsr> out_x1[MAXD];
@@ -228,8 +239,11 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   if (!probs || np < 1 || !o) return TC2_EINVAL;
   if (o->precision < 0 || o->precision > 2) return TC2_EINVAL;
   if (o->closing_fp64 != 0 && o->closing_fp64 != 2) return TC2_EINVAL;
-  if (o->skip != 0) return TC2_EINVAL;
-  if (o->precision == P_BF16) return TC2_EINVAL;  // not available yet
+  if (o->skip < 0 || o->skip > 1) return TC2_EINVAL;
+  if (o->skip != 0 && o->numeric_kernel != 0) return TC2_EINVAL;
+  if (o->numeric_kernel < 0 || o->numeric_kernel > 1) return TC2_EINVAL;
+  if (o->precision == P_BF16 && o->numeric_kernel != 0) return TC2_EINVAL;
+  if (o->fp64_first < 0 || o->fp64_first > TC2_MAX_ITER) return TC2_EINVAL;
   const int b = probs[0].H.b, D = probs[0].n_dir;
   if (b < 1 || b > BP || D < 0 || D > MAXD) return TC2_EINVAL;
   int64_t nb_tot = 0;
@@ -283,6 +297,9 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   ctx->export_m = o->export_matrices;
   ctx->max_sys_atoms = max_atoms;
   ctx->profile = o->profile;
+  ctx->kernel = o->numeric_kernel;
+  ctx->fp64_first = o->fp64_first;
+  ctx->skip = o->skip;
   tc2_status st = TC2_OK;
   auto fail = [&](tc2_status s) {
     tc2_free(ctx);
@@ -378,6 +395,68 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   if ((st = upload(ctx, ctx->src_h, sh)) != TC2_OK) return fail(st);
   for (int d = 0; d < D; ++d)
     if ((st = upload(ctx, ctx->src_h1[d], sh1[d])) != TC2_OK) return fail(st);
+  // clusters of up to CS nearby atoms for the tiled kernel: atoms in Morton
+  // order of their positions (grid step = shortest distance between two atoms
+  // coupled in H), or in index order without positions, cut into runs of CS
+  {
+    std::vector<int> clus_atom, clus_sys, atom_clus(nb_tot), csys_start(np), csys_end(np);
+    int maxc = 0;
+    for (int s = 0; s < np; ++s) {
+      const tc2_problem& p = probs[s];
+      const int n = p.H.nb, row0 = ctx->sys[s].row0;
+      std::vector<int> order(n);
+      for (int i = 0; i < n; ++i) order[i] = i;
+      if (p.xyz) {
+        for (int i = 0; i < 3 * n; ++i)
+          if (!std::isfinite(p.xyz[i])) return fail(TC2_ENAN);
+        double h = 0.0;
+        for (int i = 0; i < n; ++i)
+          for (int64_t e = p.H.row_ptr[i]; e < p.H.row_ptr[i + 1]; ++e) {
+            const int j = p.H.col[e];
+            if (j == i) continue;
+            double d2 = 0.0;
+            for (int k = 0; k < 3; ++k) d2 += (p.xyz[3 * i + k] - p.xyz[3 * j + k]) * (p.xyz[3 * i + k] - p.xyz[3 * j + k]);
+            const double d = std::sqrt(d2);
+            if (d > 0.0 && (h == 0.0 || d < h)) h = d;
+          }
+        if (!(h > 0.0)) h = 1.0;
+        double lo3[3] = {INFINITY, INFINITY, INFINITY};
+        for (int i = 0; i < n; ++i)
+          for (int k = 0; k < 3; ++k) lo3[k] = std::min(lo3[k], p.xyz[3 * i + k]);
+        std::vector<uint64_t> key(n);
+        for (int i = 0; i < n; ++i) {
+          uint64_t code = 0;
+          uint64_t q[3];
+          for (int k = 0; k < 3; ++k) {
+            double v = std::floor((p.xyz[3 * i + k] - lo3[k]) / h + 0.5);
+            q[k] = (uint64_t)std::min(std::max(v, 0.0), 2097151.0);
+          }
+          for (int bit = 20; bit >= 0; --bit)
+            for (int k = 0; k < 3; ++k) code = (code << 1) | ((q[k] >> bit) & 1u);
+          key[i] = code;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key[x] < key[y]; });
+      }
+      csys_start[s] = (int)clus_sys.size();
+      for (int k = 0; k < n; k += CS) {
+        std::vector<int> mem(order.begin() + k, order.begin() + std::min(n, k + CS));
+        std::sort(mem.begin(), mem.end());
+        const int cidx = (int)clus_sys.size();
+        clus_sys.push_back(s);
+        for (int j = 0; j < CS; ++j) clus_atom.push_back(j < (int)mem.size() ? row0 + mem[j] : -1);
+        for (int m : mem) atom_clus[row0 + m] = cidx;
+      }
+      csys_end[s] = (int)clus_sys.size();
+      maxc = std::max(maxc, csys_end[s] - csys_start[s]);
+    }
+    ctx->nc = (int)clus_sys.size();
+    ctx->max_sys_clusters = maxc;
+    if ((st = upload(ctx, ctx->clus_atom, clus_atom)) != TC2_OK) return fail(st);
+    if ((st = upload(ctx, ctx->clus_sys, clus_sys)) != TC2_OK) return fail(st);
+    if ((st = upload(ctx, ctx->atom_clus, atom_clus)) != TC2_OK) return fail(st);
+    if ((st = upload(ctx, ctx->csys_start, csys_start)) != TC2_OK) return fail(st);
+    if ((st = upload(ctx, ctx->csys_end, csys_end)) != TC2_OK) return fail(st);
+  }
   if (ctx->rowlo.reserve((size_t)ctx->nb * b * 8) || ctx->rowhi.reserve((size_t)ctx->nb * b * 8))
     return fail(TC2_ENOMEM);
   if (hipDeviceSynchronize() != hipSuccess) return fail(TC2_EDEVICE);
@@ -448,65 +527,129 @@ tc2_status measure(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal) {
   return TC2_OK;
 }
 
-// One update of every active system: symbolic, numeric, compaction.
-// Leaves the per-system scalars of the new iterate in `scal`.
+// One update of every active system: candidates (atom-level symbolic product
+// or cluster panels + tiles), numeric products with the fused epilogue,
+// copy-through of stopped systems, compaction into the next pattern.  Leaves
+// the per-system scalars of the new iterate in `scal`.
 tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
                 unsigned long long& exec_pairs_total) {
   const int c = ctx->cur, n = c ^ 1;
   const int nb = ctx->nb, D = ctx->D;
   const size_t tile = (size_t)(1 + D) * BS * prec_bytes(ctx->cur_prec);
-  int* cnt = nullptr;  // device counters: [0] total, [1] stage_count, [2] overflow
   HIPCHK(ctx->counters.reserve(64));
-  cnt = ctx->counters.as<int>();
+  int* cnt = ctx->counters.as<int>();  // [0] scan total, [1] stage count, [2] overflow
   int hcnt[4];
+  const bool tiled = ctx->kernel == 0;
+  bool any_stopped = false;
+  for (int s = 0; s < ctx->nsys; ++s) any_stopped |= !ctx->h_active[s];
 
-  // ---- symbolic
   if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[0], st));
-  HIPCHK(ctx->cand_cnt.reserve((size_t)nb * 4));
-  HIPCHK(ctx->cand_rp.reserve((size_t)(nb + 1) * 4));
-  SymArgs sa{};
-  sa.nb = nb;
-  sa.rp = ctx->rp[c].as<int>();
-  sa.ci = ctx->ci[c].as<int>();
-  sa.sys_of = ctx->sys_of.as<int>();
-  sa.sys_end = ctx->sys_end.as<int>();
-  sa.active = ctx->active.as<int>();
-  sa.cand_cnt = ctx->cand_cnt.as<int>();
-  sa.cand_rp = ctx->cand_rp.as<int>();
-  sa.max_sys_atoms = ctx->max_sys_atoms;
-  launch_symbolic(st, 0, sa);
-  launch_scan(st, nb, ctx->cand_cnt.as<int>(), ctx->cand_rp.as<int>(), cnt);
-  HIPCHK(hipMemcpyAsync(hcnt, cnt, 4, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  const int ncand = hcnt[0];
-  HIPCHK(ctx->cand_ci.reserve((size_t)std::max(ncand, 1) * 4));
-  sa.cand_ci = ctx->cand_ci.as<int>();
-  launch_symbolic(st, 1, sa);
+  int n_work = 0;          // work items (atom path) or tile blocks (tiled path)
+  long long out_bound = 0; // upper bound of computed output blocks
+  const int mult = tiled ? tile_split(ctx->cur_prec, D) : 1;
+  if (!tiled) {
+    // ---- atom-level symbolic product and work items
+    HIPCHK(ctx->cand_cnt.reserve((size_t)nb * 4));
+    HIPCHK(ctx->cand_rp.reserve((size_t)(nb + 1) * 4));
+    SymArgs sa{};
+    sa.nb = nb;
+    sa.rp = ctx->rp[c].as<int>();
+    sa.ci = ctx->ci[c].as<int>();
+    sa.sys_of = ctx->sys_of.as<int>();
+    sa.sys_end = ctx->sys_end.as<int>();
+    sa.active = ctx->active.as<int>();
+    sa.cand_cnt = ctx->cand_cnt.as<int>();
+    sa.cand_rp = ctx->cand_rp.as<int>();
+    sa.max_sys_atoms = ctx->max_sys_atoms;
+    launch_symbolic(st, 0, sa);
+    launch_scan(st, nb, ctx->cand_cnt.as<int>(), ctx->cand_rp.as<int>(), cnt);
+    HIPCHK(hipMemcpyAsync(hcnt, cnt, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int ncand = hcnt[0];
+    out_bound = ncand;
+    HIPCHK(ctx->cand_ci.reserve((size_t)std::max(ncand, 1) * 4));
+    sa.cand_ci = ctx->cand_ci.as<int>();
+    launch_symbolic(st, 1, sa);
+    HIPCHK(ctx->item_cnt.reserve((size_t)nb * 4));
+    HIPCHK(ctx->item_rp.reserve((size_t)(nb + 1) * 4));
+    launch_items_count(st, nb, ctx->cand_rp.as<int>(), ctx->item_cnt.as<int>());
+    launch_scan(st, nb, ctx->item_cnt.as<int>(), ctx->item_rp.as<int>(), cnt);
+    HIPCHK(hipMemcpyAsync(hcnt, cnt, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    n_work = hcnt[0];
+    HIPCHK(ctx->item_row.reserve((size_t)std::max(n_work, 1) * 4));
+    HIPCHK(ctx->item_c0.reserve((size_t)std::max(n_work, 1) * 4));
+    launch_items(st, nb, ctx->cand_rp.as<int>(), ctx->item_rp.as<int>(), ctx->item_row.as<int>(),
+                 ctx->item_c0.as<int>());
+    HIPCHK(ctx->sys_lo.reserve((size_t)ctx->nsys * 4));
+    HIPCHK(ctx->sys_hi.reserve((size_t)ctx->nsys * 4));
+    launch_sys_items(st, ctx->nsys, 1, ctx->sys_start.as<int>(), ctx->sys_end.as<int>(),
+                     ctx->item_rp.as<int>(), ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>());
+  } else {
+    // ---- cluster panels and tiles
+    const int nc = ctx->nc;
+    HIPCHK(ctx->panel_cnt.reserve((size_t)nc * 4));
+    HIPCHK(ctx->panel_rp.reserve((size_t)(nc + 1) * 4));
+    HIPCHK(ctx->tile_cnt.reserve((size_t)nc * 4));
+    HIPCHK(ctx->tile_rp.reserve((size_t)(nc + 1) * 4));
+    HIPCHK(ctx->tile_pairs.reserve((size_t)nc * 8));
+    PanelArgs pa{};
+    pa.nc = nc;
+    pa.rp = ctx->rp[c].as<int>();
+    pa.ci = ctx->ci[c].as<int>();
+    pa.clus_atom = ctx->clus_atom.as<int>();
+    pa.clus_sys = ctx->clus_sys.as<int>();
+    pa.sys_start = ctx->sys_start.as<int>();
+    pa.sys_end = ctx->sys_end.as<int>();
+    pa.csys_start = ctx->csys_start.as<int>();
+    pa.csys_end = ctx->csys_end.as<int>();
+    pa.atom_clus = ctx->atom_clus.as<int>();
+    pa.active = ctx->active.as<int>();
+    pa.max_sys_atoms = ctx->max_sys_atoms;
+    pa.max_sys_clusters = ctx->max_sys_clusters;
+    pa.panel_cnt = ctx->panel_cnt.as<int>();
+    pa.panel_rp = ctx->panel_rp.as<int>();
+    pa.tile_cnt = ctx->tile_cnt.as<int>();
+    pa.tile_pairs = ctx->tile_pairs.as<long long>();
+    pa.tile_rp = ctx->tile_rp.as<int>();
+    launch_panels(st, 0, pa);
+    launch_scan(st, nc, ctx->panel_cnt.as<int>(), ctx->panel_rp.as<int>(), cnt);
+    HIPCHK(hipMemcpyAsync(hcnt, cnt, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int npanel = hcnt[0];
+    HIPCHK(ctx->panel_k.reserve((size_t)std::max(npanel, 1) * 4));
+    HIPCHK(ctx->panel_e.reserve((size_t)std::max(npanel, 1) * CS * 4));
+    pa.panel_k = ctx->panel_k.as<int>();
+    pa.panel_e = ctx->panel_e.as<int>();
+    launch_panels(st, 1, pa);
+    launch_tiles(st, 0, pa);
+    launch_scan(st, nc, ctx->tile_cnt.as<int>(), ctx->tile_rp.as<int>(), cnt);
+    std::vector<long long> pairs(nc);
+    HIPCHK(hipMemcpyAsync(hcnt, cnt, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pairs.data(), ctx->tile_pairs.p, (size_t)nc * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int ntiles = hcnt[0];
+    for (long long v : pairs) out_bound += v;
+    HIPCHK(ctx->tile_p.reserve((size_t)std::max(ntiles, 1) * 4));
+    HIPCHK(ctx->tile_q.reserve((size_t)std::max(ntiles, 1) * 4));
+    pa.tile_p = ctx->tile_p.as<int>();
+    pa.tile_q = ctx->tile_q.as<int>();
+    launch_tiles(st, 1, pa);
+    n_work = ntiles;
+    HIPCHK(ctx->sys_lo.reserve((size_t)ctx->nsys * 4));
+    HIPCHK(ctx->sys_hi.reserve((size_t)ctx->nsys * 4));
+    launch_sys_items(st, ctx->nsys, mult, ctx->csys_start.as<int>(), ctx->csys_end.as<int>(),
+                     ctx->tile_rp.as<int>(), ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>());
+  }
+  HIPCHK(ctx->partial.reserve((size_t)std::max((long long)n_work * mult, (long long)nb) * NQ * 8));
   if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[1], st));
 
-  // ---- work items
-  HIPCHK(ctx->item_cnt.reserve((size_t)nb * 4));
-  HIPCHK(ctx->item_rp.reserve((size_t)(nb + 1) * 4));
-  launch_items_count(st, nb, ctx->cand_rp.as<int>(), ctx->item_cnt.as<int>());
-  launch_scan(st, nb, ctx->item_cnt.as<int>(), ctx->item_rp.as<int>(), cnt);
-  HIPCHK(hipMemcpyAsync(hcnt, cnt, 4, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  const int n_items = hcnt[0];
-  HIPCHK(ctx->item_row.reserve((size_t)std::max(n_items, 1) * 4));
-  HIPCHK(ctx->item_c0.reserve((size_t)std::max(n_items, 1) * 4));
-  HIPCHK(ctx->partial.reserve((size_t)std::max(n_items, nb) * NQ * 8));
-  launch_items(st, nb, ctx->cand_rp.as<int>(), ctx->item_rp.as<int>(), ctx->item_row.as<int>(),
-               ctx->item_c0.as<int>());
-  HIPCHK(ctx->sys_lo.reserve((size_t)ctx->nsys * 4));
-  HIPCHK(ctx->sys_hi.reserve((size_t)ctx->nsys * 4));
-  launch_sys_items(st, ctx->nsys, ctx->sys_start.as<int>(), ctx->sys_end.as<int>(), ctx->item_rp.as<int>(),
-                   ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>());
-
   // ---- numeric (retried with a larger stage if it overflows).  The stage
-  // holds every candidate when that fits a modest budget, else an estimate.
+  // holds every possible output block when that fits a modest budget.
+  if (any_stopped) out_bound += ctx->nnz[c];
   {
     const size_t budget = (size_t)16 << 30;
-    if ((size_t)ncand * tile <= budget) ctx->stage_cap = std::max(ctx->stage_cap, ncand);
+    if ((size_t)out_bound * tile <= budget) ctx->stage_cap = std::max<long long>(ctx->stage_cap, out_bound);
     else if (ctx->stage_cap == 0) ctx->stage_cap = std::max(ctx->nnz[c], nb) + 1024;
   }
   if (ctx->profile) {
@@ -516,52 +659,115 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     ctx->ms_sym += ms;
   }
   HIPCHK(ctx->exec_pairs.reserve(8));
+  const bool screen = tiled && ctx->skip != 0;
+  if (screen) {
+    HIPCHK(ctx->bn.reserve((size_t)std::max(ctx->nnz[c], 1) * (1 + D) * 4));
+    HIPCHK(ctx->screened.reserve(8));
+    launch_block_norms(st, ctx->cur_prec, ctx->nnz[c], D, ctx->xv[c].p, ctx->bn.as<float>());
+  }
   int n_kept = 0;
   unsigned long long pairs = 0;
   for (int attempt = 0;; ++attempt) {
-    int cap = std::min(ctx->stage_cap, ncand);
-    cap = std::max(cap, 1);
+    int cap = (int)std::min<long long>(std::max<long long>(ctx->stage_cap, 1), out_bound > 0 ? out_bound : 1);
     HIPCHK(ctx->stage.reserve((size_t)cap * tile));
     HIPCHK(ctx->kept_ij.reserve((size_t)cap * 8));
     launch_fill_int(st, cnt, 0, 4);
     launch_fill_int(st, ctx->exec_pairs.as<int>(), 0, 2);
-    NumArgs na{};
-    na.nb = nb;
-    na.D = D;
-    na.b = ctx->b;
-    na.ksteps = (ctx->b + 3) / 4;
-    na.rp = ctx->rp[c].as<int>();
-    na.ci = ctx->ci[c].as<int>();
-    na.xv = ctx->xv[c].p;
-    na.cand_rp = ctx->cand_rp.as<int>();
-    na.cand_ci = ctx->cand_ci.as<int>();
-    na.item_row = ctx->item_row.as<int>();
-    na.item_c0 = ctx->item_c0.as<int>();
-    na.n_items = n_items;
-    na.sys_of = ctx->sys_of.as<int>();
-    na.active = ctx->active.as<int>();
-    na.branch = ctx->branch.as<int>();
-    na.eps = ctx->eps.as<double>();
-    na.h_rp = ctx->h_rp.as<int>();
-    na.h_ci = ctx->h_ci.as<int>();
-    na.h_v = ctx->h_v.as<double>();
-    for (int d = 0; d < D; ++d) {
-      na.h1_rp[d] = ctx->h1_rp[d].as<int>();
-      na.h1_ci[d] = ctx->h1_ci[d].as<int>();
-      na.h1_v[d] = ctx->h1_v[d].as<double>();
-    }
-    na.stage = ctx->stage.p;
-    na.kept_ij = ctx->kept_ij.as<int2>();
-    na.stage_count = cnt + 1;
-    na.stage_cap = cap;
-    na.overflow = cnt + 2;
-    na.bad = ctx->bad.as<int>();
-    na.partial = ctx->partial.as<double>();
-    na.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
     if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[2], st));
-    launch_numeric(st, ctx->cur_prec, na);
+    if (!tiled) {
+      NumArgs na{};
+      na.nb = nb;
+      na.D = D;
+      na.b = ctx->b;
+      na.ksteps = (ctx->b + 3) / 4;
+      na.rp = ctx->rp[c].as<int>();
+      na.ci = ctx->ci[c].as<int>();
+      na.xv = ctx->xv[c].p;
+      na.cand_rp = ctx->cand_rp.as<int>();
+      na.cand_ci = ctx->cand_ci.as<int>();
+      na.item_row = ctx->item_row.as<int>();
+      na.item_c0 = ctx->item_c0.as<int>();
+      na.n_items = n_work;
+      na.sys_of = ctx->sys_of.as<int>();
+      na.active = ctx->active.as<int>();
+      na.branch = ctx->branch.as<int>();
+      na.eps = ctx->eps.as<double>();
+      na.h_rp = ctx->h_rp.as<int>();
+      na.h_ci = ctx->h_ci.as<int>();
+      na.h_v = ctx->h_v.as<double>();
+      for (int d = 0; d < D; ++d) {
+        na.h1_rp[d] = ctx->h1_rp[d].as<int>();
+        na.h1_ci[d] = ctx->h1_ci[d].as<int>();
+        na.h1_v[d] = ctx->h1_v[d].as<double>();
+      }
+      na.stage = ctx->stage.p;
+      na.kept_ij = ctx->kept_ij.as<int2>();
+      na.stage_count = cnt + 1;
+      na.stage_cap = cap;
+      na.overflow = cnt + 2;
+      na.bad = ctx->bad.as<int>();
+      na.partial = ctx->partial.as<double>();
+      na.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
+      launch_numeric(st, ctx->cur_prec, na);
+    } else {
+      TileArgs ta{};
+      ta.D = D;
+      ta.ksteps = (ctx->b + 3) / 4;
+      ta.n_tiles = n_work;
+      ta.rp = ctx->rp[c].as<int>();
+      ta.ci = ctx->ci[c].as<int>();
+      ta.xv = ctx->xv[c].p;
+      ta.tile_p = ctx->tile_p.as<int>();
+      ta.tile_q = ctx->tile_q.as<int>();
+      ta.clus_atom = ctx->clus_atom.as<int>();
+      ta.clus_sys = ctx->clus_sys.as<int>();
+      ta.panel_rp = ctx->panel_rp.as<int>();
+      ta.panel_k = ctx->panel_k.as<int>();
+      ta.panel_e = ctx->panel_e.as<int>();
+      ta.branch = ctx->branch.as<int>();
+      ta.eps = ctx->eps.as<double>();
+      ta.h_rp = ctx->h_rp.as<int>();
+      ta.h_ci = ctx->h_ci.as<int>();
+      ta.h_v = ctx->h_v.as<double>();
+      for (int d = 0; d < D; ++d) {
+        ta.h1_rp[d] = ctx->h1_rp[d].as<int>();
+        ta.h1_ci[d] = ctx->h1_ci[d].as<int>();
+        ta.h1_v[d] = ctx->h1_v[d].as<double>();
+      }
+      ta.stage = ctx->stage.p;
+      ta.kept_ij = ctx->kept_ij.as<int2>();
+      ta.stage_count = cnt + 1;
+      ta.stage_cap = cap;
+      ta.overflow = cnt + 2;
+      ta.bad = ctx->bad.as<int>();
+      ta.partial = ctx->partial.as<double>();
+      ta.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
+      ta.bf16 = (ctx->op_bf16 && ctx->cur_prec == P_FP32) ? 1 : 0;
+      ta.skip = screen ? 1 : 0;
+      ta.bn = screen ? ctx->bn.as<float>() : nullptr;
+      ta.screened = screen ? ctx->screened.as<unsigned long long>() : nullptr;
+      if (screen) launch_fill_int(st, ctx->screened.as<int>(), 0, 2);
+      launch_tile_numeric(st, ctx->cur_prec, ta);
+    }
     HIPCHK(hipGetLastError());
     if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[3], st));
+    if (any_stopped) {
+      CopyArgs ca{};
+      ca.nb = nb;
+      ca.D = D;
+      ca.rp = ctx->rp[c].as<int>();
+      ca.ci = ctx->ci[c].as<int>();
+      ca.xv = ctx->xv[c].p;
+      ca.sys_of = ctx->sys_of.as<int>();
+      ca.active = ctx->active.as<int>();
+      ca.stage = ctx->stage.p;
+      ca.kept_ij = ctx->kept_ij.as<int2>();
+      ca.stage_count = cnt + 1;
+      ca.stage_cap = cap;
+      ca.overflow = cnt + 2;
+      launch_copy_through(st, ctx->cur_prec, ca, ctx->nnz[c]);
+      HIPCHK(hipGetLastError());
+    }
     HIPCHK(hipMemcpyAsync(hcnt, cnt, 16, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&pairs, ctx->exec_pairs.p, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -576,11 +782,23 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       break;
     }
     // overflow: the counter still counts every kept block
-    ctx->stage_cap = (int)std::min<long long>((long long)hcnt[1] * 5 / 4 + 1024, ncand);
+    ctx->stage_cap = (int)std::min<long long>((long long)hcnt[1] * 5 / 4 + 1024, out_bound);
     if (attempt > 3) return TC2_ENOMEM;
   }
   exec_pairs_total += pairs;
-  ctx->stage_cap = std::max(ctx->stage_cap, n_kept * 5 / 4 + 1024);
+  if (screen) {
+    unsigned long long sc = 0;
+    HIPCHK(hipMemcpyAsync(&sc, ctx->screened.p, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ctx->screened_total += sc;
+  }
+  if (ctx->verbose) {
+    float ms = 0.f;
+    if (ctx->profile) (void)hipEventElapsedTime(&ms, ctx->pev[2], ctx->pev[3]);
+    fprintf(stderr, "tc2 step: %s work=%d (x%d) out_bound=%lld kept=%d pairs=%llu numeric %.3f ms\n",
+            tiled ? "tiles" : "items", n_work, mult, out_bound, n_kept, pairs, ms);
+  }
+  ctx->stage_cap = std::max(ctx->stage_cap, (long long)n_kept * 5 / 4 + 1024);
 
   // ---- compaction into the new pattern
   if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[0], st));
@@ -686,6 +904,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
   const int nsys = ctx->nsys, D = ctx->D, b = ctx->b, nb = ctx->nb;
   std::vector<SysState> ss(nsys);
   ctx->ms_sym = ctx->ms_num = ctx->ms_cmp = 0.0;
+  ctx->screened_total = 0;
   ctx->num_launches = 0;
   hipEvent_t ev0, ev1;
   HIPCHK(hipEventCreate(&ev0));
@@ -713,7 +932,9 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
   }
   HIPCHK(hipMemcpyAsync(ctx->mode.p, mode.data(), nsys * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(ctx->bad.p, bad.data(), nsys * 4, hipMemcpyHostToDevice, st));
-  const int start_prec = ctx->prec == P_FP64 ? P_FP64 : P_FP32;
+  // reduced precision keeps FP32 values; BF16 rounds the MFMA operands only.
+  // fp64_first leading updates run in FP64 before the switch.
+  const int start_prec = (ctx->prec == P_FP64 || ctx->fp64_first > 0) ? P_FP64 : P_FP32;
   ctx->cur = 0;
   ctx->cur_prec = start_prec;
   ctx->nnz[0] = ctx->nnz0;
@@ -745,8 +966,11 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
 
   // ---- iterate.  phase 0: working precision; phase 1: closing FP64 pair
   unsigned long long exec_pairs = 0;
+  // stages of a reduced-precision solve: [FP64 x fp64_first] -> [BF16] -> FP32
+  // -> closing FP64 pair; each reduced stage runs to its own stopping test.
   const bool reduced = ctx->prec != P_FP64;
-  int phase = 0;
+  ctx->op_bf16 = ctx->prec == P_BF16 ? 1 : 0;
+  int phase = 0, updates = 0;
   for (;;) {
     bool any = false;
     for (int s = 0; s < nsys; ++s) {
@@ -759,6 +983,16 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
       }
     }
     if (!any) {
+      if (phase == 0 && ctx->op_bf16) {
+        // BF16 stage done: continue with FP32 operands from where it stopped
+        ctx->op_bf16 = 0;
+        for (int s = 0; s < nsys; ++s)
+          if (mode[s] == 0 && ss[s].status >= 0 && ctx->sys[s].replay.empty()) {
+            ss[s].active = true;
+            ss[s].iota.clear();
+          }
+        continue;
+      }
       if (phase == 0 && reduced && ctx->closing == 2) {
         // closing pair in FP64: trace rule, then the opposite branch
         tc2_status cs = convert_iterate(ctx, st, P_FP64);
@@ -776,8 +1010,14 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
     }
     HIPCHK(hipMemcpyAsync(ctx->active.p, active.data(), nsys * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ctx->branch.p, branch.data(), nsys * 4, hipMemcpyHostToDevice, st));
+    ctx->h_active = active;
     tc2_status r = step(ctx, st, scal, exec_pairs);
     if (r != TC2_OK) return r;
+    ++updates;
+    if (reduced && phase == 0 && ctx->cur_prec == P_FP64 && updates >= ctx->fp64_first) {
+      r = convert_iterate(ctx, st, P_FP32);
+      if (r != TC2_OK) return r;
+    }
     HIPCHK(hipMemcpyAsync(bad.data(), ctx->bad.p, nsys * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int s = 0; s < nsys; ++s) {
@@ -808,7 +1048,8 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
         else branch[s] = S.closing_first ? 0 : 1;
         continue;
       }
-      const double tol = reduced ? std::max(si.tol, ctx->prec == P_FP32 ? 1e-6 : 1e-3) : si.tol;
+      const double tol = ctx->cur_prec == P_FP64 ? si.tol
+                                                 : std::max(si.tol, ctx->op_bf16 ? 1e-3 : 1e-6);
       bool stop = false;
       if (!si.replay.empty()) {
         if (S.k == (int)si.replay.size()) {
@@ -818,7 +1059,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
       } else if (S.k >= 2 && dmax < tol) {
         stop = true;
         S.status = TC2_OK;
-      } else if (S.k >= 3 && std::fabs(iota) < 1.0 &&
+      } else if (S.iota.size() >= 3 && std::fabs(iota) < 1.0 &&
                  std::fabs(iota) >= std::fabs(S.iota[S.iota.size() - 3])) {
         stop = true;
         S.status = TC2_FLOOR_REACHED;
@@ -875,6 +1116,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
     R.ms_numeric = ctx->ms_num;
     R.ms_compact = ctx->ms_cmp;
     R.numeric_launches = ctx->num_launches;
+    R.screened_blocks = (s == 0) ? (int64_t)ctx->screened_total : 0;
     R.kept_blocks = final_rp[ctx->sys[s].row0 + ctx->sys[s].nb] - final_rp[ctx->sys[s].row0];
     if (ctx->export_m) {
       HostBsr& x0 = ctx->out_x0[s];

@@ -1,0 +1,628 @@
+// Clustered-tile numeric kernel of the TC2 / TC2-CPSCF update for gfx950.
+//
+// Atoms are grouped into clusters of up to CS = 8 nearby atoms.  A work item
+// is a tile of output blocks (I in cluster P) x (J in cluster Q) for P <= Q;
+// it walks the common columns K of the two clusters' row panels once and, for
+// every K, stages the present blocks X_JK of cluster Q in LDS while each wave
+// holds the MFMA fragments of its X_IK in registers.  Every staged block then
+// feeds up to 8 block products instead of one, which cuts the L2/HBM operand
+// traffic of the row-by-row product (Algorithm 1) several-fold.  The
+// accumulators and the fused epilogue (branch combine, Frobenius drop,
+// traces and band energies) are the same as in the one-wave-per-block kernel.
+#include "tc2_device.h"
+
+namespace tc2 {
+
+// ------------------------------------------------------------------ cluster panels
+// Panel of cluster P: sorted union of the columns of its atoms' rows, with the
+// entry index of (I_s, K) for every member s (-1 when absent).
+__global__ __launch_bounds__(256) void k_panels(int pass, PanelArgs a) {
+  extern __shared__ unsigned sbits[];
+  __shared__ int sscan[256];
+  const int P = blockIdx.x;
+  const int sys = a.clus_sys[P];
+  const int t = threadIdx.x;
+  if (!a.active[sys]) {
+    if (pass == 0 && t == 0) a.panel_cnt[P] = 0;
+    return;
+  }
+  const int lo = a.sys_start[sys], nbits = a.sys_end[sys] - lo;
+  const int nwords = (nbits + 31) >> 5;
+  for (int w = t; w < nwords; w += blockDim.x) sbits[w] = 0u;
+  __syncthreads();
+  for (int s = 0; s < CS; ++s) {
+    const int I = a.clus_atom[P * CS + s];
+    if (I < 0) continue;
+    for (int e = a.rp[I] + t; e < a.rp[I + 1]; e += blockDim.x) {
+      const int o = a.ci[e] - lo;
+      atomicOr(&sbits[o >> 5], 1u << (o & 31));
+    }
+  }
+  __syncthreads();
+  const int per = (nwords + blockDim.x - 1) / blockDim.x;
+  const int w0 = t * per, w1 = min(nwords, w0 + per);
+  int cnt = 0;
+  for (int w = w0; w < w1; ++w) cnt += __popc(sbits[w]);
+  sscan[t] = cnt;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int v = (t >= o) ? sscan[t - o] : 0;
+    __syncthreads();
+    sscan[t] += v;
+    __syncthreads();
+  }
+  if (pass == 0) {
+    if (t == 255) a.panel_cnt[P] = sscan[255];
+    return;
+  }
+  int pos = a.panel_rp[P] + sscan[t] - cnt;
+  for (int w = w0; w < w1; ++w) {
+    unsigned x = sbits[w];
+    while (x) {
+      const int bit = __ffs(x) - 1;
+      x &= x - 1;
+      const int K = lo + (w << 5) + bit;
+      a.panel_k[pos] = K;
+      for (int s = 0; s < CS; ++s) {
+        const int I = a.clus_atom[P * CS + s];
+        int e = -1;
+        if (I >= 0) {
+          const int r0 = a.rp[I];
+          const int f = bsearch_eq(a.ci + r0, a.rp[I + 1] - r0, K);
+          e = f >= 0 ? r0 + f : -1;
+        }
+        a.panel_e[(size_t)pos * CS + s] = e;
+      }
+      ++pos;
+    }
+  }
+}
+
+// Tiles of cluster P: the clusters Q >= P holding an atom J with a column K in
+// common with some atom of P (cluster-level symbolic product).  Pass 0 also
+// bounds the number of output blocks of those tiles.
+__global__ __launch_bounds__(256) void k_tiles(int pass, PanelArgs a) {
+  extern __shared__ unsigned sbits[];
+  __shared__ int sscan[256];
+  __shared__ long long spairs[256];
+  const int P = blockIdx.x;
+  const int sys = a.clus_sys[P];
+  const int t = threadIdx.x;
+  if (!a.active[sys]) {
+    if (pass == 0 && t == 0) {
+      a.tile_cnt[P] = 0;
+      a.tile_pairs[P] = 0;
+    }
+    return;
+  }
+  const int nbits = a.csys_end[sys] - P;
+  const int nwords = (nbits + 31) >> 5;
+  for (int w = t; w < nwords; w += blockDim.x) sbits[w] = 0u;
+  __syncthreads();
+  const int wave = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
+  for (int idx = a.panel_rp[P] + wave; idx < a.panel_rp[P + 1]; idx += nw) {
+    const int K = a.panel_k[idx];
+    for (int f = a.rp[K] + lane; f < a.rp[K + 1]; f += 64) {
+      const int Q = a.atom_clus[a.ci[f]];
+      if (Q >= P) {
+        const int o = Q - P;
+        atomicOr(&sbits[o >> 5], 1u << (o & 31));
+      }
+    }
+  }
+  __syncthreads();
+  const int per = (nwords + blockDim.x - 1) / blockDim.x;
+  const int w0 = t * per, w1 = min(nwords, w0 + per);
+  int cnt = 0;
+  for (int w = w0; w < w1; ++w) cnt += __popc(sbits[w]);
+  sscan[t] = cnt;
+  if (pass == 0) {
+    int nP = 0;
+    for (int s = 0; s < CS; ++s) nP += a.clus_atom[P * CS + s] >= 0;
+    long long pairs = 0;
+    for (int w = w0; w < w1; ++w) {
+      unsigned x = sbits[w];
+      while (x) {
+        const int bit = __ffs(x) - 1;
+        x &= x - 1;
+        const int Q = P + (w << 5) + bit;
+        int nQ = 0;
+        for (int s = 0; s < CS; ++s) nQ += a.clus_atom[Q * CS + s] >= 0;
+        pairs += (Q == P) ? (long long)nP * (nP + 1) / 2 : (long long)nP * nQ;
+      }
+    }
+    spairs[t] = pairs;
+  }
+  __syncthreads();
+  if (pass == 0) {
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) {
+        sscan[t] += sscan[t + o];
+        spairs[t] += spairs[t + o];
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      a.tile_cnt[P] = sscan[0];
+      a.tile_pairs[P] = spairs[0];
+    }
+    return;
+  }
+  for (int o = 1; o < 256; o <<= 1) {
+    const int v = (t >= o) ? sscan[t - o] : 0;
+    __syncthreads();
+    sscan[t] += v;
+    __syncthreads();
+  }
+  int pos = a.tile_rp[P] + sscan[t] - cnt;
+  for (int w = w0; w < w1; ++w) {
+    unsigned x = sbits[w];
+    while (x) {
+      const int bit = __ffs(x) - 1;
+      x &= x - 1;
+      a.tile_p[pos] = P;
+      a.tile_q[pos] = P + (w << 5) + bit;
+      ++pos;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ tile numeric
+// A block owns a sub-tile of SP rows of cluster P x TQ columns of cluster Q
+// (a tile of 8 x 8 output blocks is split into (8/SP)(8/TQ) blocks).  Wave w
+// owns the "diagonal" outputs (I_s, J_t) with t = (s + w) mod TQ, one per
+// row, so that for any column K every wave has about the same number of
+// present block pairs.  The common columns K of the two panels are walked in
+// groups of KG; for each group the present blocks X_{I_s K} and X_{J_t K} are
+// copied straight from global memory into LDS with global_load_lds (16 B per
+// lane), double-buffered so that the copy of group g+1 overlaps the MFMAs of
+// group g.
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <typename T, int D, int SP, int TQ, bool BF>
+__global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
+  constexpr int PER = (1 + D) * BS;                       // elements per entry
+  constexpr int EB = PER * (int)sizeof(T);                // bytes per entry
+  constexpr int NE = SP + TQ;                             // entries per column K
+  constexpr int KG = (65536 / (NE * EB)) > 0 ? (65536 / (NE * EB)) : 1;
+  constexpr int NW = TQ;                                  // waves
+  constexpr int NT = NW * 64;
+  constexpr int NO = SP;                                  // outputs per wave
+  constexpr int KLMAX = 2048;
+  constexpr int SUBS = (CS / SP) * (CS / TQ);
+  __shared__ __attribute__((aligned(16))) T buf[2][KG][NE][PER];
+  __shared__ int sflag[2][KG][NE];
+  __shared__ int2 kl[KLMAX];
+  __shared__ int wcount[NW];
+  __shared__ int sIA[SP], sJB[TQ];
+  __shared__ int s_any;
+  __shared__ double spart[NW][NQ];
+
+  const int lb = (int)blockIdx.x;
+  const int tile = lb / SUBS, sub = lb - tile * SUBS;
+  const int ph = sub / (CS / TQ), qh = sub - ph * (CS / TQ);
+  const int P = a.tile_p[tile], Q = a.tile_q[tile];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int sys = a.clus_sys[P];
+  const bool square = a.branch[sys] != 0;
+  const double eps = a.eps[sys];
+  if (t == 0) s_any = 0;
+  if (t < SP) sIA[t] = a.clus_atom[P * CS + ph * SP + t];
+  if (t < TQ) sJB[t] = a.clus_atom[Q * CS + qh * TQ + t];
+  __syncthreads();
+
+  // outputs of this wave: o -> (row so[o], column to[o])
+  int Io[NO], Jo[NO], so[NO], to[NO];
+  bool owned[NO];
+  bool any_owned = false;
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    so[o] = o;
+    to[o] = (o + wave) % TQ;
+    Io[o] = sIA[so[o]];
+    Jo[o] = sJB[to[o]];
+    owned[o] = Io[o] >= 0 && Jo[o] >= 0 && (P != Q || Io[o] <= Jo[o]);
+    any_owned |= owned[o];
+  }
+  if (any_owned && lane == 0) s_any = 1;
+  __syncthreads();
+  if (!s_any) {  // e.g. the lower sub-tiles of a diagonal tile: no work, zero sums
+    if (t < NQ) a.partial[(size_t)lb * NQ + t] = 0.0;
+    return;
+  }
+
+  const T* X = (const T*)a.xv;
+  Acc<T> acc[NO][1 + D];
+#pragma unroll
+  for (int o = 0; o < NO; ++o)
+#pragma unroll
+    for (int m = 0; m <= D; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[o][m].v[r] = 0;
+  int np[NO];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) np[o] = 0;
+
+  const int pp0 = a.panel_rp[P], pp1 = a.panel_rp[P + 1];
+  const int pq0 = a.panel_rp[Q], nq = a.panel_rp[Q + 1] - pq0;
+
+  // copy the blocks of column group g (KG columns) into buffer bb
+  auto issue = [&](int g, int nm, int bb) {
+#pragma unroll
+    for (int gi = 0; gi < KG; ++gi) {
+      const int m = g * KG + gi;
+      for (int x = wave; x < NE; x += NW) {
+        int e = -1;
+        if (m < nm) {
+          const int2 pq = kl[m];
+          e = (x < SP) ? a.panel_e[(size_t)pq.x * CS + ph * SP + x]
+                       : a.panel_e[(size_t)pq.y * CS + qh * TQ + (x - SP)];
+        }
+        e = __builtin_amdgcn_readfirstlane(e);
+        if (lane == 0) sflag[bb][gi][x] = e;
+        if (e >= 0) {
+          const char* src = (const char*)(X + (size_t)e * PER) + lane * 16;
+          char* dst = (char*)&buf[bb][gi][x][0];
+#pragma unroll
+          for (int i = 0; i < EB / 1024; ++i)
+            __builtin_amdgcn_global_load_lds((const void*)(src + i * 1024),
+                                             (lds_void*)(dst + i * 1024), 16, 0, 0);
+        }
+      }
+    }
+  };
+
+  // common columns of the chunk [base, end) of P's panel with Q's panel -> kl
+  auto build_kl = [&](int base, int end) {
+    int nm = 0;
+    for (int c0 = base; c0 < end; c0 += NT) {
+      const int idx = c0 + t;
+      int j = -1;
+      if (idx < end) j = (P == Q) ? idx - pp0 : bsearch_eq(a.panel_k + pq0, nq, a.panel_k[idx]);
+      const bool found = j >= 0;
+      const unsigned long long mask = __ballot(found);
+      if (lane == 0) wcount[wave] = __popcll(mask);
+      __syncthreads();
+      int off = nm, tot = 0;
+      for (int w = 0; w < NW; ++w) {
+        const int c = wcount[w];
+        off += (w < wave) ? c : 0;
+        tot += c;
+      }
+      if (found) kl[off + __popcll(mask & ((1ull << lane) - 1ull))] = make_int2(idx, pq0 + j);
+      nm += tot;
+      __syncthreads();
+    }
+    return nm;
+  };
+
+  // lane o of each wave: entry of the old block (I_o, J_o), or -1
+  int my_e = -1;
+  {
+    int Il = -1, Jl = -1;
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+      if (lane == o) { Il = Io[o]; Jl = Jo[o]; }
+    if (lane < NO && Il >= 0 && Jl >= 0) {
+      const int r0 = a.rp[Il];
+      const int f = bsearch_eq(a.ci + r0, a.rp[Il + 1] - r0, Jl);
+      my_e = f >= 0 ? r0 + f : -1;
+    }
+  }
+
+  // ---- exact screen: ||C_IJ|| <= sum_K ||A_IK|| ||B_KJ|| (+ 2 ||X_IJ|| on the
+  // DOUBLE branch); an off-diagonal output whose bound is below eps for X0
+  // and every X1_d is certainly dropped, so its products are skipped.
+  const bool single_chunk = (pp1 - pp0) <= KLMAX;
+  int nm_kept = -1;
+  if (a.skip) {
+    constexpr int NSF = (int)((sizeof(buf) / 4) / (NE * (1 + D)));  // columns per norm round
+    float* ns = (float*)&buf[0][0][0][0];
+    double bsum[NO][1 + D];
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+      for (int m = 0; m <= D; ++m) bsum[o][m] = 0.0;
+    for (int base = pp0; base < pp1; base += KLMAX) {
+      const int nm = build_kl(base, min(pp1, base + KLMAX));
+      nm_kept = nm;
+      for (int r0 = 0; r0 < nm; r0 += NSF) {
+        const int nr = min(NSF, nm - r0);
+        for (int i = t; i < nr * NE; i += NT) {
+          const int m = i / NE, x = i - m * NE;
+          const int2 pq = kl[r0 + m];
+          const int e = (x < SP) ? a.panel_e[(size_t)pq.x * CS + ph * SP + x]
+                                 : a.panel_e[(size_t)pq.y * CS + qh * TQ + (x - SP)];
+#pragma unroll
+          for (int mm = 0; mm <= D; ++mm) ns[(m * NE + x) * (1 + D) + mm] = e >= 0 ? a.bn[(size_t)e * (1 + D) + mm] : 0.f;
+        }
+        __syncthreads();
+        for (int m = lane; m < nr; m += 64) {
+          const float* nk = ns + (size_t)m * NE * (1 + D);
+#pragma unroll
+          for (int o = 0; o < NO; ++o) {
+            const float* na = nk + so[o] * (1 + D);
+            const float* nb = nk + (SP + to[o]) * (1 + D);
+            bsum[o][0] += (double)na[0] * nb[0];
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+              bsum[o][1 + d] += (double)na[0] * nb[1 + d] + (double)na[1 + d] * nb[0];
+          }
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      const int eIJ = __builtin_amdgcn_readlane(my_e, o);
+      bool drop = owned[o] && Io[o] != Jo[o];
+#pragma unroll
+      for (int m = 0; m <= D; ++m) {
+        double bnd = wave_sum(bsum[o][m]);
+        if (!square && eIJ >= 0) bnd += 2.0 * (double)a.bn[(size_t)eIJ * (1 + D) + m];
+        // a relative margin covers the rounding of the float block norms
+        drop = drop && bnd * (1.0 + 1e-6) < eps;
+      }
+      if (drop) {
+        owned[o] = false;
+        if (lane == 0) atomicAdd(a.screened, 1ull);
+      }
+    }
+    any_owned = false;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) any_owned |= owned[o];
+  }
+
+  for (int base = pp0; base < pp1; base += KLMAX) {
+    // ---- common columns of this chunk of P's panel with Q's panel
+    const int end = min(pp1, base + KLMAX);
+    const int nm = (single_chunk && nm_kept >= 0) ? nm_kept : build_kl(base, end);
+    // ---- pipelined products over the common columns
+    const int ngroups = (nm + KG - 1) / KG;
+    if (ngroups > 0) issue(0, nm, 0);
+    for (int g = 0; g < ngroups; ++g) {
+      const int bb = g & 1;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      if (g + 1 < ngroups) issue(g + 1, nm, bb ^ 1);
+      if (any_owned) {
+#pragma unroll
+        for (int gi = 0; gi < KG; ++gi) {
+          if (g * KG + gi >= nm) break;
+          bool pres[NO];
+#pragma unroll
+          for (int o = 0; o < NO; ++o) {
+            pres[o] = owned[o] && sflag[bb][gi][so[o]] >= 0 && sflag[bb][gi][SP + to[o]] >= 0;
+            np[o] += pres[o] ? 1 : 0;
+          }
+          // Operands of HALF outputs are read from LDS up front (absent
+          // blocks read stale data that no MFMA consumes); the two updates of
+          // each response accumulator are issued in separate passes so that
+          // dependent MFMAs are not back to back.
+          constexpr int HALF = ((sizeof(T) == 8 || BF) && D >= 2) ? 2 : 4;
+          if constexpr (BF) {
+            // bfloat16 operands: one 16x16x16 MFMA per block product
+#pragma unroll
+            for (int h = 0; h < NO; h += HALF) {
+              s4 A0[HALF], B0[HALF], A1[HALF][D > 0 ? D : 1], B1[HALF][D > 0 ? D : 1];
+#pragma unroll
+              for (int u = 0; u < HALF; ++u) {
+                const float* xa = (const float*)&buf[bb][gi][so[h + u]][0];
+                const float* xb = (const float*)&buf[bb][gi][SP + to[h + u]][0];
+                A0[u] = bf16_frag(xa, lane);
+                B0[u] = bf16_frag(xb, lane);
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                  A1[u][d] = bf16_frag(xa + (1 + d) * BS, lane);
+                  B1[u][d] = bf16_frag(xb + (1 + d) * BS, lane);
+                }
+              }
+#pragma unroll
+              for (int u = 0; u < HALF; ++u)
+                if (pres[h + u]) mfma_bf16(acc[h + u][0], A0[u], B0[u]);
+#pragma unroll
+              for (int d = 0; d < D; ++d)
+#pragma unroll
+                for (int u = 0; u < HALF; ++u)
+                  if (pres[h + u]) mfma_bf16(acc[h + u][1 + d], A0[u], B1[u][d]);
+#pragma unroll
+              for (int d = 0; d < D; ++d)
+#pragma unroll
+                for (int u = 0; u < HALF; ++u)
+                  if (pres[h + u]) mfma_bf16(acc[h + u][1 + d], A1[u][d], B0[u]);
+            }
+            continue;
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            if (kk >= a.ksteps) break;
+#pragma unroll
+            for (int h = 0; h < NO; h += HALF) {
+              T A0[HALF], B0[HALF], A1[HALF][D > 0 ? D : 1], B1[HALF][D > 0 ? D : 1];
+#pragma unroll
+              for (int u = 0; u < HALF; ++u) {
+                const T* xa = &buf[bb][gi][so[h + u]][lane + kk * 64];
+                const T* xb = &buf[bb][gi][SP + to[h + u]][lane + kk * 64];
+                A0[u] = xa[0];
+                B0[u] = xb[0];
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                  A1[u][d] = xa[(1 + d) * BS];
+                  B1[u][d] = xb[(1 + d) * BS];
+                }
+              }
+#pragma unroll
+              for (int u = 0; u < HALF; ++u)
+                if (pres[h + u]) mfma(acc[h + u][0], A0[u], B0[u]);
+#pragma unroll
+              for (int d = 0; d < D; ++d)
+#pragma unroll
+                for (int u = 0; u < HALF; ++u)
+                  if (pres[h + u]) mfma(acc[h + u][1 + d], A0[u], B1[u][d]);
+#pragma unroll
+              for (int d = 0; d < D; ++d)
+#pragma unroll
+                for (int u = 0; u < HALF; ++u)
+                  if (pres[h + u]) mfma(acc[h + u][1 + d], A1[u][d], B0[u]);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue: lane o looks up the old block (I_o, J_o) for output o
+  EpiCtx E{a.xv, (size_t)PER, a.h_rp, a.h_ci, a.h_v, {a.h1_rp[0], a.h1_rp[1], a.h1_rp[2]},
+           {a.h1_ci[0], a.h1_ci[1], a.h1_ci[2]}, {a.h1_v[0], a.h1_v[1], a.h1_v[2]}, a.stage,
+           a.kept_ij, a.stage_count, a.stage_cap, a.overflow, a.bad};
+  double q[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) q[k] = 0.0;
+  unsigned long long issued = 0;
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const int eIJ = __builtin_amdgcn_readlane(my_e, o);
+    if (!owned[o] || np[o] == 0) continue;
+    issued += np[o];
+    epilogue<T, D>(E, acc[o], Io[o], Jo[o], eIJ, square, eps, np[o], sys, q);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) spart[wave][k] = q[k];
+    if (issued) atomicAdd(a.exec_pairs, issued);
+  }
+  __syncthreads();
+  if (t < NQ) {
+    double sum = 0.0;
+    for (int w = 0; w < NW; ++w) sum += spart[w][t];
+    a.partial[(size_t)lb * NQ + t] = sum;
+  }
+}
+
+// ------------------------------------------------------------------ copy-through
+// One wave per entry (I, J >= I) of a stopped system: its blocks go to the
+// stage unchanged (row-major upper block).
+template <typename T>
+__global__ void k_copy_through(CopyArgs a) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int nnz = a.rp[a.nb];
+  if (wave >= nnz) return;
+  const int e = wave;
+  int lo = 0, hi = a.nb;  // row of entry e
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a.rp[mid] <= e) lo = mid; else hi = mid;
+  }
+  const int I = lo, J = a.ci[e];
+  if (J < I || a.active[a.sys_of[I]]) return;
+  int slot = 0;
+  if (lane == 0) slot = atomicAdd(a.stage_count, 1);
+  slot = __builtin_amdgcn_readfirstlane(slot);
+  if (slot >= a.stage_cap) {
+    if (lane == 0) atomicOr(a.overflow, 1);
+    return;
+  }
+  const int per = (1 + a.D) * BS;
+  const T* X = (const T*)a.xv + (size_t)e * per;
+  T* st = (T*)a.stage + (size_t)slot * per;
+  for (int q = lane; q < per; q += 64) {
+    const int m = q / BS, qq = q - m * BS;  // stage index qq = r*16 + c
+    const int r = qq >> 4, c = qq & 15;
+    st[q] = X[m * BS + c * BP + r];
+  }
+  if (lane == 0) a.kept_ij[slot] = make_int2(I, J);
+}
+
+// ------------------------------------------------------------------ block norms
+// Frobenius norm of every stored block of every matrix (float), one wave per
+// entry; used by the screens.
+template <typename T>
+__global__ void k_block_norms(long long nnz, int D, const T* xv, float* bn) {
+  const long long e = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (e >= nnz) return;
+  for (int m = 0; m <= D; ++m) {
+    const T* x = xv + ((size_t)e * (1 + D) + m) * BS;
+    double ss = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double v = (double)x[lane + 64 * j];
+      ss += v * v;
+    }
+    ss = wave_sum(ss);
+    if (lane == 0) bn[(size_t)e * (1 + D) + m] = (float)sqrt(ss);
+  }
+}
+
+void launch_block_norms(hipStream_t st, int prec, long long nnz, int D, const void* xv, float* bn) {
+  if (nnz == 0) return;
+  const unsigned blocks = (unsigned)((nnz * 64 + 255) / 256);
+  if (prec == P_FP64) hipLaunchKernelGGL(k_block_norms<double>, dim3(blocks), dim3(256), 0, st, nnz, D, (const double*)xv, bn);
+  else hipLaunchKernelGGL(k_block_norms<float>, dim3(blocks), dim3(256), 0, st, nnz, D, (const float*)xv, bn);
+}
+
+// ================================================================== launchers
+void launch_panels(hipStream_t st, int pass, const PanelArgs& a) {
+  if (a.nc == 0) return;
+  const size_t lds = (size_t)((a.max_sys_atoms + 31) / 32) * 4;
+  hipLaunchKernelGGL(k_panels, dim3(a.nc), dim3(256), lds, st, pass, a);
+}
+
+void launch_tiles(hipStream_t st, int pass, const PanelArgs& a) {
+  if (a.nc == 0) return;
+  const size_t lds = (size_t)((a.max_sys_clusters + 31) / 32) * 4;
+  hipLaunchKernelGGL(k_tiles, dim3(a.nc), dim3(256), lds, st, pass, a);
+}
+
+// Sub-tile shape per precision and direction count: the accumulators of a
+// wave (TQ outputs x (1+D) tiles) stay within the 256-register budget and one
+// LDS buffer stays within 64 KB.
+template <typename T, int D> struct Shape {
+  static constexpr int SP = (sizeof(T) == 8 && D >= 2) ? 4 : 8;
+  static constexpr int TQ = (sizeof(T) == 8 && D >= 2) ? 4 : 8;
+};
+
+int tile_split(int prec, int D) {
+  if (prec == P_FP64 && D >= 2) return (CS / 4) * (CS / 4);
+  return 1;
+}
+
+template <typename T, int D>
+static void tile_launch(hipStream_t st, const TileArgs& a) {
+  constexpr int SP = Shape<T, D>::SP, TQ = Shape<T, D>::TQ;
+  const unsigned G = (unsigned)a.n_tiles * (unsigned)((CS / SP) * (CS / TQ));
+  if constexpr (sizeof(T) == 4) {
+    if (a.bf16) {
+      hipLaunchKernelGGL((k_tile_numeric<T, D, SP, TQ, true>), dim3(G), dim3(TQ * 64), 0, st, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_tile_numeric<T, D, SP, TQ, false>), dim3(G), dim3(TQ * 64), 0, st, a);
+}
+
+template <typename T>
+static void tile_d(hipStream_t st, const TileArgs& a) {
+  switch (a.D) {
+    case 0: tile_launch<T, 0>(st, a); break;
+    case 1: tile_launch<T, 1>(st, a); break;
+    case 2: tile_launch<T, 2>(st, a); break;
+    default: tile_launch<T, 3>(st, a); break;
+  }
+}
+
+void launch_tile_numeric(hipStream_t st, int prec, const TileArgs& a) {
+  if (a.n_tiles == 0) return;
+  if (prec == P_FP64) tile_d<double>(st, a);
+  else tile_d<float>(st, a);
+}
+
+void launch_copy_through(hipStream_t st, int prec, const CopyArgs& a, int nnz) {
+  if (nnz == 0) return;
+  const unsigned blocks = (unsigned)(((long long)nnz * 64 + 255) / 256);
+  if (prec == P_FP64) hipLaunchKernelGGL(k_copy_through<double>, dim3(blocks), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_copy_through<float>, dim3(blocks), dim3(256), 0, st, a);
+}
+
+}  // namespace tc2

@@ -22,6 +22,8 @@ TC2_MAX_ITER = 200
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "FLOOR_REACHED", -1: "EINVAL", -2: "ENOMEM",
           -3: "EDEVICE", -4: "ENONSYM", -5: "EDEGENERATE", -6: "ENAN", -7: "EOVERFLOW"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
+KERNEL = {"tile": 0, "block": 1}
+SKIP = {"none": 0, "bound": 1}
 
 
 class tc2_bsr(C.Structure):
@@ -32,13 +34,15 @@ class tc2_bsr(C.Structure):
 class tc2_problem(C.Structure):
     _fields_ = [("H", tc2_bsr), ("n_dir", C.c_int32), ("H1", tc2_bsr * 3),
                 ("n_occ", C.c_int64), ("eps_drop", C.c_double), ("tol", C.c_double),
-                ("max_iter", C.c_int32), ("replay", C.c_char_p)]
+                ("max_iter", C.c_int32), ("replay", C.c_char_p),
+                ("xyz", C.POINTER(C.c_double))]
 
 
 class tc2_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("closing_fp64", C.c_int32), ("skip", C.c_int32),
                 ("device", C.c_int32), ("export_matrices", C.c_int32), ("verbose", C.c_int32),
-                ("profile", C.c_int32)]
+                ("profile", C.c_int32), ("numeric_kernel", C.c_int32),
+                ("fp64_first", C.c_int32)]
 
 
 class tc2_result(C.Structure):
@@ -47,6 +51,7 @@ class tc2_result(C.Structure):
                 ("e0", C.c_double), ("e1", C.c_double * 3), ("emin", C.c_double),
                 ("emax", C.c_double), ("seconds", C.c_double), ("useful_flops", C.c_double),
                 ("executed_flops", C.c_double), ("kept_blocks", C.c_int64),
+                ("screened_blocks", C.c_int64),
                 ("ms_symbolic", C.c_double), ("ms_numeric", C.c_double),
                 ("ms_compact", C.c_double), ("numeric_launches", C.c_int32),
                 ("branches", C.c_char * (TC2_MAX_ITER + 4)),
@@ -106,6 +111,7 @@ class Result:
     useful_flops: float
     executed_flops: float
     kept_blocks: int = 0
+    screened_blocks: int = 0
     ms_symbolic: float = 0.0
     ms_numeric: float = 0.0
     ms_compact: float = 0.0
@@ -143,7 +149,8 @@ class Solver:
     def __init__(self, systems: Union[System, Sequence[System]], precision: str = "fp64",
                  closing_fp64: int = 0, export: bool = True, device: int = 0,
                  replay: Optional[Sequence[Optional[str]]] = None, verbose: bool = False,
-                 profile: bool = False):
+                 profile: bool = False, kernel: str = "tile", use_xyz: bool = True,
+                 fp64_first: int = 0, skip: str = "none"):
         if isinstance(systems, System):
             systems = [systems]
         self.systems = list(systems)
@@ -167,9 +174,14 @@ class Solver:
                 p.replay = rb
             else:
                 p.replay = None
+            if use_xyz and s.xyz is not None:
+                xyz = np.ascontiguousarray(s.xyz, dtype=np.float64)
+                self._keep.append(xyz)
+                p.xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
         self.n_dir = len(self.systems[0].H1)
-        opts = tc2_options(PRECISION[precision], int(closing_fp64), 0, int(device),
-                           1 if export else 0, 1 if verbose else 0, 1 if profile else 0)
+        opts = tc2_options(PRECISION[precision], int(closing_fp64), SKIP[skip], int(device),
+                           1 if export else 0, 1 if verbose else 0, 1 if profile else 0,
+                           KERNEL[kernel], int(fp64_first))
         self._ctx = C.c_void_p()
         st = lib().tc2_setup(probs, n, C.byref(opts), C.byref(self._ctx))
         if st != 0:
@@ -189,7 +201,8 @@ class Solver:
             out.append(Result(r.status, r.iters, r.branches.decode(), list(r.trace_x1h1[:D]),
                               r.tr_x0, r.idem_err, list(r.tr_x1[:D]), r.e0, list(r.e1[:D]),
                               r.emin, r.emax, r.seconds, r.useful_flops, r.executed_flops,
-                              r.kept_blocks, r.ms_symbolic, r.ms_numeric, r.ms_compact,
+                              r.kept_blocks, r.screened_blocks, r.ms_symbolic, r.ms_numeric,
+                              r.ms_compact,
                               r.numeric_launches, x0, x1))
         return out
 

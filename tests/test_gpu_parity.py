@@ -42,35 +42,56 @@ def run_both(sys, **kw):
     return g, o
 
 
-def test_chain64_fp64():
+KERNELS = ["tile", "block"]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_chain64_fp64(kernel):
     s = W.config_system("chain64")
-    g, o = run_both(s)
+    g, o = run_both(s, kernel=kernel)
     assert g.status == o.status == 0
     compare(s, g, o)
 
 
-def test_chain_ragged_block():
-    # b = 5 (one K-step of the padded tile is ragged), 37 atoms
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_chain_ragged_block(kernel):
+    # b = 5 (one K-step of the padded tile is ragged), 37 atoms (ragged last cluster)
     s = W.config_system("chain64", n=37, b=5, occ=2, eps=1e-6, seed=17)
-    g, o = run_both(s)
+    g, o = run_both(s, kernel=kernel)
     compare(s, g, o)
 
 
-def test_cube_b13_fp64():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_cube_b13_fp64(kernel):
     s = W.config_system("cube10", L=4)
-    g, o = run_both(s)
+    g, o = run_both(s, kernel=kernel)
     compare(s, g, o)
 
 
-def test_cube_three_directions():
+def test_cube_clusters_without_positions():
+    # clusters taken in index order when no positions are given
+    s = W.config_system("cube10", L=4)
+    g, o = run_both(s, use_xyz=False)
+    compare(s, g, o)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_cube_three_directions(kernel):
     s = W.config_system("cube20", L=3, eps=1e-6)
+    g, o = run_both(s, kernel=kernel)
+    compare(s, g, o)
+
+
+def test_cube_two_directions_odd_lattice():
+    s = W.config_system("cube20", L=5, n_dir=2, eps=1e-5)
     g, o = run_both(s)
     compare(s, g, o)
 
 
-def test_batch_uneven_systems():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_batch_uneven_systems(kernel):
     sys_list = W.batch_systems(sizes=[20, 64, 9, 41], n_dir=2)
-    gs = T.solve(sys_list)
+    gs = T.solve(sys_list, kernel=kernel)
     for s, g in zip(sys_list, gs):
         compare(s, g, O.solve_system(s))
 
@@ -128,3 +149,24 @@ def test_repeat_run_is_bitwise_identical():
     assert a.branches == b.branches
     assert np.array_equal(a.X1[0].val, b.X1[0].val)
     assert np.array_equal(a.X0.col, b.X0.col)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_norm_bound_screen_is_exact(prec):
+    # the screen only skips blocks that the drop would remove: identical results
+    s = W.config_system("cube10", L=5, eps=1e-5)
+    a = T.solve(s, precision=prec)[0]
+    b = T.solve(s, precision=prec, skip="bound")[0]
+    print(f"  screened {b.screened_blocks} output blocks over {b.iters} updates", flush=True)
+    assert b.screened_blocks > 0
+    assert a.branches == b.branches
+    assert np.array_equal(a.X0.col, b.X0.col)
+    assert np.array_equal(a.X0.val, b.X0.val)
+    assert np.array_equal(a.X1[0].val, b.X1[0].val)
+    assert a.alpha == b.alpha
+
+
+def test_norm_bound_screen_three_directions_matches_oracle():
+    s = W.config_system("cube20", L=3, eps=1e-5)
+    g, o = run_both(s, skip="bound")
+    compare(s, g, o)
