@@ -92,7 +92,9 @@ typedef struct {
                               FP64 steps of opposite branches                  */
   int32_t skip;            /* 0: every candidate block is computed; 1: exact
                               norm-bound screen (skips blocks that are certainly
-                              dropped; results unchanged); tiled kernel only   */
+                              dropped; results unchanged); 2: the exact screen,
+                              then the skip network on the remaining candidates
+                              (an approximation); tiled kernel only            */
   int32_t device;          /* HIP device ordinal                                 */
   int32_t export_matrices; /* 1: tc2_run copies X0/X1 back to host views         */
   int32_t verbose;         /* 1: per-iteration log on stderr                     */
@@ -101,6 +103,12 @@ typedef struct {
                               output block (reference kernel; FP64/FP32 only)  */
   int32_t fp64_first;      /* reduced precision only: number of leading updates
                               run in FP64 before switching (0..TC2_MAX_ITER)   */
+  const float *mlp_weights;/* skip = 2: TC2_MLP_PARAMS parameters of the skip
+                              network (copied at setup)                        */
+  float mlp_threshold;     /* skip = 2: skip a candidate whose predicted drop
+                              probability exceeds this, in (0, 1)              */
+  int64_t log_capacity;    /* > 0: log up to this many (features, dropped)
+                              samples per tc2_run for training (tiled kernel)  */
 } tc2_options;
 
 typedef struct {
@@ -117,8 +125,9 @@ typedef struct {
   double useful_flops;     /* 2 b^3 per block triple landing on a kept block     */
   double executed_flops;   /* MFMA flops issued, padding included                */
   int64_t kept_blocks;     /* stored blocks of the final X pattern (both halves) */
-  int64_t screened_blocks; /* output blocks skipped by the screen, all updates
-                              (batch total, reported on the first problem)    */
+  int64_t screened_blocks; /* output blocks skipped by the exact screen, all
+                              updates (batch total, on the first problem)     */
+  int64_t mlp_skipped_blocks; /* output blocks skipped by the skip network    */
   /* phase times in ms, summed over the updates (profile = 1 only) */
   double ms_symbolic, ms_numeric, ms_compact;
   int32_t numeric_launches;
@@ -145,6 +154,14 @@ TC2_API tc2_status tc2_setup(const tc2_problem *problems, int32_t n_problems,
  * before warnings).  May be called again; each call restarts from H. */
 TC2_API tc2_status tc2_run(tc2_ctx *ctx, void *hip_stream, tc2_result *res);
 
+/* Copy the samples logged by the last tc2_run (log_capacity > 0): features
+ * (n x TC2_MLP_IN floats: scaled log10 of the norm bounds of X0 and X1 relative
+ * to eps, of the largest single product, of the number of common columns,
+ * distance / 10, scaled log10 of the previous block norm or -3, update / 20,
+ * branch) and labels (1 = the block was dropped).  Returns the number of
+ * samples copied (at most cap), or a negative tc2_status. */
+TC2_API int64_t tc2_log_copy(tc2_ctx *ctx, float *x, float *y, int64_t cap);
+
 /* Release the context and everything it owns.  NULL-safe. */
 TC2_API void tc2_free(tc2_ctx *ctx);
 
@@ -153,6 +170,47 @@ TC2_API const char *tc2_strerror(tc2_status s);
 
 /* Library version string. */
 TC2_API const char *tc2_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Block-skip network (learned screen).  A multilayer perceptron
+ * TC2_MLP_IN -> 64 -> 64 -> 1 with ReLU hidden layers maps features of a
+ * candidate output block of an update to the logit of the probability that
+ * the block ends below the drop threshold.  theta holds TC2_MLP_PARAMS floats:
+ * W1 (64 x 8, row-major), b1 (64), W2 (64 x 64, row-major, W2[j][k] maps input
+ * k to output j), b2 (64), w3 (64), b3 (1).  The loss is the mean binary
+ * cross-entropy on logits, softplus(z) - y z.  All pointers are host pointers
+ * owned by the caller; x is n x TC2_MLP_IN row-major, y holds 0/1 labels.
+ * Errors: TC2_EINVAL (ranges, NULL), TC2_ENAN (non-finite input),
+ * TC2_EDEVICE, TC2_ENOMEM.
+ * ------------------------------------------------------------------------- */
+#define TC2_MLP_IN 8
+#define TC2_MLP_HIDDEN 64
+#define TC2_MLP_PARAMS 4801
+
+typedef struct {
+  int32_t epochs;          /* passes over the data, >= 1                        */
+  int32_t batch;           /* samples per Adam step, >= 1 (in data order)       */
+  float lr;                /* Adam step size, > 0                               */
+  float beta1, beta2;      /* Adam moment decays, in [0, 1)                     */
+  float adam_eps;          /* Adam denominator guard, > 0                       */
+  int32_t device;          /* HIP device ordinal                                */
+} tc2_mlp_train_opts;
+
+/* Logits of n samples (n >= 0). */
+TC2_API tc2_status tc2_mlp_forward(const float *theta, const float *x, int64_t n,
+                                   int32_t device, float *logits);
+
+/* Gradient (TC2_MLP_PARAMS floats) and value of the mean loss over n >= 1
+ * samples. */
+TC2_API tc2_status tc2_mlp_grad(const float *theta, const float *x, const float *y,
+                                int64_t n, int32_t device, float *grad, double *loss);
+
+/* Train with Adam on the device; theta holds the initial parameters on entry
+ * (drawn by the caller) and the trained ones on return.  loss_per_epoch, if
+ * not NULL, receives `epochs` mean losses. */
+TC2_API tc2_status tc2_mlp_train(const float *x, const float *y, int64_t n,
+                                 const tc2_mlp_train_opts *opts, float *theta,
+                                 double *loss_per_epoch);
 
 #ifdef __cplusplus
 }

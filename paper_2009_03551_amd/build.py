@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtc2.so")
-SOURCES = ["tc2_kernels.hip", "tc2_tile.hip", "tc2_runtime.hip"]
+SOURCES = ["tc2_kernels.hip", "tc2_tile.hip", "tc2_mlp.hip", "tc2_runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

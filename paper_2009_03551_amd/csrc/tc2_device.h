@@ -66,6 +66,25 @@ __device__ __forceinline__ void mfma_bf16(Acc<float>& c, s4 a, s4 b) {
   c.v = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c.v, 0, 0, 0);
 }
 
+// Skip network parameter offsets (see tc2_mlp.hip); in LDS, W2 is stored
+// transposed (W2T[k][j] = W2[j][k]) so that lane j reads row k contiguously.
+constexpr int MLP_W1 = 0, MLP_B1 = 512, MLP_W2 = 576, MLP_B2 = 4672, MLP_W3 = 4736, MLP_B3 = 4800;
+
+// Logit of the skip network for one feature vector (wave-uniform), one hidden
+// unit per lane; th points to the LDS copy with W2 transposed.
+__device__ __forceinline__ float mlp_logit_wave(const float* th, const float* f, int lane) {
+  float a1 = th[MLP_B1 + lane];
+#pragma unroll
+  for (int i = 0; i < MLP_NF; ++i) a1 += th[MLP_W1 + lane * MLP_NF + i] * f[i];
+  const float h1 = fmaxf(a1, 0.f);
+  float a2 = th[MLP_B2 + lane];
+#pragma unroll 8
+  for (int k = 0; k < MLP_NH; ++k)
+    a2 += th[MLP_W2 + k * MLP_NH + lane] * __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, h1), k));
+  const float h2 = fmaxf(a2, 0.f);
+  return (float)wave_sum((double)(th[MLP_W3 + lane] * h2)) + th[MLP_B3];
+}
+
 // Pointers used by the fused epilogue of the numeric kernels.
 struct EpiCtx {
   const void* xv;
@@ -93,7 +112,7 @@ struct EpiCtx {
 // contributions (weight 2 off the diagonal) to q.  eIJ is the entry of the
 // old block (I, J) or -1.  Called by a whole wave.
 template <typename T, int D>
-__device__ __forceinline__ void epilogue(const EpiCtx& E, const Acc<T>* acc, int I, int J,
+__device__ __forceinline__ bool epilogue(const EpiCtx& E, const Acc<T>* acc, int I, int J,
                                          int eIJ, bool square, double eps, int npairs, int sys,
                                          double* q) {
   const int lane = threadIdx.x & 63;
@@ -192,6 +211,7 @@ __device__ __forceinline__ void epilogue(const EpiCtx& E, const Acc<T>* acc, int
       q[Q_AL + d] += w * dot;
     }
   }
+  return any;
 }
 
 }  // namespace tc2

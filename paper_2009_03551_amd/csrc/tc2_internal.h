@@ -24,6 +24,9 @@ constexpr int NQ = 4 + 3 * MAXD;  // per-work-item partial sums (see Q_*)
 constexpr int CHUNK = 32;     // candidates per numeric work item
 constexpr int MAX_SYS_BITS = 1 << 19;  // atoms per system (symbolic bitmap)
 constexpr int CS = 8;         // atoms per cluster (tiled numeric kernel)
+constexpr int MLP_NF = 8;     // skip network: input features
+constexpr int MLP_NH = 64;    // hidden units per layer
+constexpr int MLP_NP = MLP_NH * MLP_NF + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NH + 1;
 
 // partial-sum slots
 enum {
@@ -133,9 +136,18 @@ struct PanelArgs {
 struct TileArgs {
   int D;
   int bf16;               // FP32 values, MFMA operands rounded to bfloat16
-  int skip;               // 0 none, 1 exact norm-bound screen
-  const float* bn;        // block norms (nnz x (1+D)) when skip != 0
-  unsigned long long* screened;  // outputs skipped by the screen
+  int skip;               // 0 none, 1 exact norm-bound screen, 2 bound + network
+  const float* bn;        // block norms (nnz x (1+D)) when skip != 0 or logging
+  unsigned long long* screened;  // outputs skipped by the exact screen
+  const float* mlp;       // skip network parameters (MLP_NP), skip == 2
+  float mlp_z;            // skip when the logit exceeds this (logit of the threshold)
+  unsigned long long* mlp_skipped;
+  const double* xyz;      // merged atom positions or nullptr
+  int iter;               // update index (feature)
+  float* log_x;           // logged features (log_cap x MLP_NF)
+  float* log_y;           // logged labels (1 = dropped)
+  unsigned long long* log_count;
+  long long log_cap;      // 0: no logging
   int ksteps;
   int n_tiles;
   const int* rp;

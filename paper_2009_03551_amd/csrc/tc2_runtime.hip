@@ -108,9 +108,16 @@ struct tc2_ctx {
   int kernel = 0;                 // 0 tiled, 1 one wave per block
   int fp64_first = 0;             // leading FP64 updates of a reduced-precision solve
   int op_bf16 = 0;                // current stage rounds MFMA operands to bfloat16
-  int skip = 0;                   // 1: exact norm-bound screen in the tiled kernel
-  DBuf bn, screened;              // block norms, screened-output counter
-  unsigned long long screened_total = 0;
+  int skip = 0;                   // 1: exact norm-bound screen, 2: + skip network
+  DBuf bn, screened;              // block norms, skip counters [exact, network]
+  unsigned long long screened_total = 0, mlp_total = 0;
+  DBuf mlp;                       // skip network parameters
+  float mlp_z = 0.f;              // logit of the skip threshold
+  DBuf xyz;                       // merged positions (all problems gave them)
+  bool have_xyz = false;
+  long long log_cap = 0, log_n = 0;
+  DBuf log_x, log_y, log_count;
+  int update_index = 0;
   std::vector<int> h_active;      // host copy of the active flags
   // clusters
   int nc = 0, max_sys_clusters = 0;
@@ -239,8 +246,14 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   if (!probs || np < 1 || !o) return TC2_EINVAL;
   if (o->precision < 0 || o->precision > 2) return TC2_EINVAL;
   if (o->closing_fp64 != 0 && o->closing_fp64 != 2) return TC2_EINVAL;
-  if (o->skip < 0 || o->skip > 1) return TC2_EINVAL;
-  if (o->skip != 0 && o->numeric_kernel != 0) return TC2_EINVAL;
+  if (o->skip < 0 || o->skip > 2) return TC2_EINVAL;
+  if ((o->skip != 0 || o->log_capacity > 0) && o->numeric_kernel != 0) return TC2_EINVAL;
+  if (o->skip == 2) {
+    if (!o->mlp_weights || !(o->mlp_threshold > 0.f && o->mlp_threshold < 1.f)) return TC2_EINVAL;
+    for (int p = 0; p < MLP_NP; ++p)
+      if (!std::isfinite(o->mlp_weights[p])) return TC2_ENAN;
+  }
+  if (o->log_capacity < 0 || o->log_capacity > ((int64_t)1 << 31)) return TC2_EINVAL;
   if (o->numeric_kernel < 0 || o->numeric_kernel > 1) return TC2_EINVAL;
   if (o->precision == P_BF16 && o->numeric_kernel != 0) return TC2_EINVAL;
   if (o->fp64_first < 0 || o->fp64_first > TC2_MAX_ITER) return TC2_EINVAL;
@@ -300,6 +313,7 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   ctx->kernel = o->numeric_kernel;
   ctx->fp64_first = o->fp64_first;
   ctx->skip = o->skip;
+  ctx->log_cap = o->log_capacity;
   tc2_status st = TC2_OK;
   auto fail = [&](tc2_status s) {
     tc2_free(ctx);
@@ -456,6 +470,27 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
     if ((st = upload(ctx, ctx->atom_clus, atom_clus)) != TC2_OK) return fail(st);
     if ((st = upload(ctx, ctx->csys_start, csys_start)) != TC2_OK) return fail(st);
     if ((st = upload(ctx, ctx->csys_end, csys_end)) != TC2_OK) return fail(st);
+  }
+  // positions (a feature of the skip network) and the network itself
+  {
+    bool all = true;
+    for (int s = 0; s < np; ++s) all = all && probs[s].xyz != nullptr;
+    if (all) {
+      std::vector<double> xyz;
+      for (int s = 0; s < np; ++s) xyz.insert(xyz.end(), probs[s].xyz, probs[s].xyz + 3 * (size_t)probs[s].H.nb);
+      if ((st = upload(ctx, ctx->xyz, xyz)) != TC2_OK) return fail(st);
+      ctx->have_xyz = true;
+    }
+    if (o->skip == 2) {
+      std::vector<float> th(o->mlp_weights, o->mlp_weights + MLP_NP);
+      if ((st = upload(ctx, ctx->mlp, th)) != TC2_OK) return fail(st);
+      ctx->mlp_z = std::log(o->mlp_threshold / (1.f - o->mlp_threshold));
+    }
+    if (ctx->log_cap > 0) {
+      if (ctx->log_x.reserve((size_t)ctx->log_cap * MLP_NF * 4) ||
+          ctx->log_y.reserve((size_t)ctx->log_cap * 4) || ctx->log_count.reserve(8))
+        return fail(TC2_ENOMEM);
+    }
   }
   if (ctx->rowlo.reserve((size_t)ctx->nb * b * 8) || ctx->rowhi.reserve((size_t)ctx->nb * b * 8))
     return fail(TC2_ENOMEM);
@@ -659,13 +694,18 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     ctx->ms_sym += ms;
   }
   HIPCHK(ctx->exec_pairs.reserve(8));
-  const bool screen = tiled && ctx->skip != 0;
+  const bool screen = tiled && (ctx->skip != 0 || ctx->log_cap > 0);
   if (screen) {
     HIPCHK(ctx->bn.reserve((size_t)std::max(ctx->nnz[c], 1) * (1 + D) * 4));
-    HIPCHK(ctx->screened.reserve(8));
+    HIPCHK(ctx->screened.reserve(16));
     launch_block_norms(st, ctx->cur_prec, ctx->nnz[c], D, ctx->xv[c].p, ctx->bn.as<float>());
   }
   int n_kept = 0;
+  unsigned long long log_before = 0;  // restored if the numeric step is retried
+  if (tiled && ctx->log_cap > 0) {
+    HIPCHK(hipMemcpyAsync(&log_before, ctx->log_count.p, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   unsigned long long pairs = 0;
   for (int attempt = 0;; ++attempt) {
     int cap = (int)std::min<long long>(std::max<long long>(ctx->stage_cap, 1), out_bound > 0 ? out_bound : 1);
@@ -743,10 +783,19 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       ta.partial = ctx->partial.as<double>();
       ta.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
       ta.bf16 = (ctx->op_bf16 && ctx->cur_prec == P_FP32) ? 1 : 0;
-      ta.skip = screen ? 1 : 0;
+      ta.skip = ctx->skip;
       ta.bn = screen ? ctx->bn.as<float>() : nullptr;
       ta.screened = screen ? ctx->screened.as<unsigned long long>() : nullptr;
-      if (screen) launch_fill_int(st, ctx->screened.as<int>(), 0, 2);
+      ta.mlp_skipped = screen ? ctx->screened.as<unsigned long long>() + 1 : nullptr;
+      ta.mlp = ctx->skip == 2 ? ctx->mlp.as<float>() : nullptr;
+      ta.mlp_z = ctx->mlp_z;
+      ta.xyz = ctx->have_xyz ? ctx->xyz.as<double>() : nullptr;
+      ta.iter = ctx->update_index;
+      ta.log_cap = ctx->log_cap;
+      ta.log_x = ctx->log_cap > 0 ? ctx->log_x.as<float>() : nullptr;
+      ta.log_y = ctx->log_cap > 0 ? ctx->log_y.as<float>() : nullptr;
+      ta.log_count = ctx->log_cap > 0 ? ctx->log_count.as<unsigned long long>() : nullptr;
+      if (screen) launch_fill_int(st, ctx->screened.as<int>(), 0, 4);
       launch_tile_numeric(st, ctx->cur_prec, ta);
     }
     HIPCHK(hipGetLastError());
@@ -781,16 +830,19 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       n_kept = hcnt[1];
       break;
     }
+    if (tiled && ctx->log_cap > 0)
+      HIPCHK(hipMemcpyAsync(ctx->log_count.p, &log_before, 8, hipMemcpyHostToDevice, st));
     // overflow: the counter still counts every kept block
     ctx->stage_cap = (int)std::min<long long>((long long)hcnt[1] * 5 / 4 + 1024, out_bound);
     if (attempt > 3) return TC2_ENOMEM;
   }
   exec_pairs_total += pairs;
   if (screen) {
-    unsigned long long sc = 0;
-    HIPCHK(hipMemcpyAsync(&sc, ctx->screened.p, 8, hipMemcpyDeviceToHost, st));
+    unsigned long long sc[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(sc, ctx->screened.p, 16, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    ctx->screened_total += sc;
+    ctx->screened_total += sc[0];
+    ctx->mlp_total += sc[1];
   }
   if (ctx->verbose) {
     float ms = 0.f;
@@ -905,6 +957,9 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
   std::vector<SysState> ss(nsys);
   ctx->ms_sym = ctx->ms_num = ctx->ms_cmp = 0.0;
   ctx->screened_total = 0;
+  ctx->mlp_total = 0;
+  ctx->log_n = 0;
+  if (ctx->log_cap > 0) launch_fill_int(st, ctx->log_count.as<int>(), 0, 2);
   ctx->num_launches = 0;
   hipEvent_t ev0, ev1;
   HIPCHK(hipEventCreate(&ev0));
@@ -971,6 +1026,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
   const bool reduced = ctx->prec != P_FP64;
   ctx->op_bf16 = ctx->prec == P_BF16 ? 1 : 0;
   int phase = 0, updates = 0;
+  bool later_stage = false;
   for (;;) {
     bool any = false;
     for (int s = 0; s < nsys; ++s) {
@@ -986,6 +1042,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
       if (phase == 0 && ctx->op_bf16) {
         // BF16 stage done: continue with FP32 operands from where it stopped
         ctx->op_bf16 = 0;
+        later_stage = true;
         for (int s = 0; s < nsys; ++s)
           if (mode[s] == 0 && ss[s].status >= 0 && ctx->sys[s].replay.empty()) {
             ss[s].active = true;
@@ -1011,6 +1068,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
     HIPCHK(hipMemcpyAsync(ctx->active.p, active.data(), nsys * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ctx->branch.p, branch.data(), nsys * 4, hipMemcpyHostToDevice, st));
     ctx->h_active = active;
+    ctx->update_index = updates;
     tc2_status r = step(ctx, st, scal, exec_pairs);
     if (r != TC2_OK) return r;
     ++updates;
@@ -1059,8 +1117,15 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
       } else if (S.k >= 2 && dmax < tol) {
         stop = true;
         S.status = TC2_OK;
-      } else if (S.iota.size() >= 3 && std::fabs(iota) < 1.0 &&
+      } else if (ctx->op_bf16 && S.k >= 3 && std::fabs(iota) < 1e-2 * (double)si.n_occ) {
+        // bfloat16 stage: hand over to FP32 while the spectrum of X0 is still
+        // well inside (0, 1), before bfloat16 rounding can push it out
+        stop = true;
+        S.status = TC2_OK;
+      } else if (S.iota.size() >= 3 && (std::fabs(iota) < 1.0 || later_stage) &&
                  std::fabs(iota) >= std::fabs(S.iota[S.iota.size() - 3])) {
+        // precision floor; in a stage that starts from a reduced-precision
+        // iterate, also a growing |iota| (eigenvalues pushed out of [0, 1])
         stop = true;
         S.status = TC2_FLOOR_REACHED;
       } else if (S.k >= si.max_iter) {
@@ -1072,6 +1137,12 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
     }
   }
   HIPCHK(hipEventRecord(ev1, st));
+  if (ctx->log_cap > 0) {
+    unsigned long long n = 0;
+    HIPCHK(hipMemcpyAsync(&n, ctx->log_count.p, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ctx->log_n = std::min<long long>((long long)n, ctx->log_cap);
+  }
   HIPCHK(hipEventSynchronize(ev1));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
@@ -1117,6 +1188,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
     R.ms_compact = ctx->ms_cmp;
     R.numeric_launches = ctx->num_launches;
     R.screened_blocks = (s == 0) ? (int64_t)ctx->screened_total : 0;
+    R.mlp_skipped_blocks = (s == 0) ? (int64_t)ctx->mlp_total : 0;
     R.kept_blocks = final_rp[ctx->sys[s].row0 + ctx->sys[s].nb] - final_rp[ctx->sys[s].row0];
     if (ctx->export_m) {
       HostBsr& x0 = ctx->out_x0[s];
@@ -1142,4 +1214,16 @@ extern "C" tc2_status tc2_run(tc2_ctx* ctx, void* hip_stream, tc2_result* res) {
   } catch (...) {
     return TC2_EDEVICE;
   }
+}
+
+extern "C" int64_t tc2_log_copy(tc2_ctx* ctx, float* x, float* y, int64_t cap) {
+  if (!ctx || cap < 0 || (cap > 0 && (!x || !y))) return TC2_EINVAL;
+  if (ctx->log_cap <= 0) return 0;
+  if (hipSetDevice(ctx->device) != hipSuccess) return TC2_EDEVICE;
+  const long long n = std::min<long long>(ctx->log_n, cap);
+  if (n == 0) return 0;
+  if (hipMemcpy(x, ctx->log_x.p, (size_t)n * MLP_NF * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(y, ctx->log_y.p, (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return TC2_EDEVICE;
+  return n;
 }

@@ -312,17 +312,39 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
 
   // ---- exact screen: ||C_IJ|| <= sum_K ||A_IK|| ||B_KJ|| (+ 2 ||X_IJ|| on the
   // DOUBLE branch); an off-diagonal output whose bound is below eps for X0
-  // and every X1_d is certainly dropped, so its products are skipped.
+  // and every X1_d is certainly dropped, so its products are skipped.  The
+  // learned screen then evaluates the skip network on features of the
+  // remaining outputs and skips those it predicts to be dropped; features and
+  // the true outcome can be logged for training.
   const bool single_chunk = (pp1 - pp0) <= KLMAX;
   int nm_kept = -1;
-  if (a.skip) {
-    constexpr int NSF = (int)((sizeof(buf) / 4) / (NE * (1 + D)));  // columns per norm round
-    float* ns = (float*)&buf[0][0][0][0];
+  int my_slot = -1;  // lane o: log slot of output o
+  if (a.skip || a.log_cap > 0) {
+    constexpr int THF = 4864;  // floats reserved for the network at the start of buf
+    constexpr int NSF = (int)((sizeof(buf) / 4 - THF) / (NE * (1 + D)));  // columns per norm round
+    float* th = (float*)&buf[0][0][0][0];
+    float* ns = th + THF;
+    if (a.skip == 2) {
+      for (int p = t; p < MLP_NP; p += NT) {
+        float v = a.mlp[p];
+        int q = p;
+        if (p >= MLP_W2 && p < MLP_B2) {  // transpose W2 (j, k) -> (k, j)
+          const int j = (p - MLP_W2) / MLP_NH, k = (p - MLP_W2) - j * MLP_NH;
+          q = MLP_W2 + k * MLP_NH + j;
+        }
+        th[q] = v;
+      }
+    }
     double bsum[NO][1 + D];
+    float bmax[NO];
+    int bcnt[NO];
 #pragma unroll
-    for (int o = 0; o < NO; ++o)
+    for (int o = 0; o < NO; ++o) {
+      bmax[o] = 0.f;
+      bcnt[o] = 0;
 #pragma unroll
       for (int m = 0; m <= D; ++m) bsum[o][m] = 0.0;
+    }
     for (int base = pp0; base < pp1; base += KLMAX) {
       const int nm = build_kl(base, min(pp1, base + KLMAX));
       nm_kept = nm;
@@ -334,7 +356,8 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
           const int e = (x < SP) ? a.panel_e[(size_t)pq.x * CS + ph * SP + x]
                                  : a.panel_e[(size_t)pq.y * CS + qh * TQ + (x - SP)];
 #pragma unroll
-          for (int mm = 0; mm <= D; ++mm) ns[(m * NE + x) * (1 + D) + mm] = e >= 0 ? a.bn[(size_t)e * (1 + D) + mm] : 0.f;
+          for (int mm = 0; mm <= D; ++mm)
+            ns[(m * NE + x) * (1 + D) + mm] = e >= 0 ? a.bn[(size_t)e * (1 + D) + mm] : -1.f;
         }
         __syncthreads();
         for (int m = lane; m < nr; m += 64) {
@@ -343,6 +366,9 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
           for (int o = 0; o < NO; ++o) {
             const float* na = nk + so[o] * (1 + D);
             const float* nb = nk + (SP + to[o]) * (1 + D);
+            if (na[0] < 0.f || nb[0] < 0.f) continue;  // block absent
+            bcnt[o] += 1;
+            bmax[o] = fmaxf(bmax[o], na[0] * nb[0]);
             bsum[o][0] += (double)na[0] * nb[0];
 #pragma unroll
             for (int d = 0; d < D; ++d)
@@ -352,22 +378,91 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
         __syncthreads();
       }
     }
+    int nlog = 0;
+    bool logit_o[NO];
+    float feat[MLP_NF];
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
+      logit_o[o] = false;
       const int eIJ = __builtin_amdgcn_readlane(my_e, o);
+      double bnd[1 + D];
       bool drop = owned[o] && Io[o] != Jo[o];
 #pragma unroll
       for (int m = 0; m <= D; ++m) {
-        double bnd = wave_sum(bsum[o][m]);
-        if (!square && eIJ >= 0) bnd += 2.0 * (double)a.bn[(size_t)eIJ * (1 + D) + m];
+        bnd[m] = wave_sum(bsum[o][m]);
+        if (!square && eIJ >= 0) bnd[m] += 2.0 * (double)a.bn[(size_t)eIJ * (1 + D) + m];
         // a relative margin covers the rounding of the float block norms
-        drop = drop && bnd * (1.0 + 1e-6) < eps;
+        drop = drop && bnd[m] * (1.0 + 1e-6) < eps;
       }
-      if (drop) {
+      if (a.skip && drop) {
         owned[o] = false;
         if (lane == 0) atomicAdd(a.screened, 1ull);
+        continue;
+      }
+      if (!owned[o] || Io[o] == Jo[o]) continue;
+      // features of the candidate (scaled logs relative to eps)
+      const int cnt = (int)wave_sum((double)bcnt[o]);
+      float mx = bmax[o];
+#pragma unroll
+      for (int sh = 32; sh > 0; sh >>= 1) mx = fmaxf(mx, __shfl_xor(mx, sh, 64));
+      double b1 = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) b1 = fmax(b1, bnd[1 + d]);
+      const double le = log10(eps > 0.0 ? eps : 1e-300);
+      feat[0] = (float)(0.1 * (log10(fmax(bnd[0], 1e-300)) - le));
+      feat[1] = (float)(0.1 * (log10(fmax(b1, 1e-300)) - le));
+      feat[2] = (float)(0.1 * (log10(fmax((double)mx, 1e-300)) - le));
+      feat[3] = (float)(0.5 * log10(1.0 + cnt));
+      double r = 0.0;
+      if (a.xyz) {
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          const double dd = a.xyz[3 * Io[o] + k] - a.xyz[3 * Jo[o] + k];
+          d2 += dd * dd;
+        }
+        r = sqrt(d2);
+      }
+      feat[4] = (float)(0.1 * r);
+      feat[5] = eIJ >= 0 ? (float)(0.1 * (log10(fmax((double)a.bn[(size_t)eIJ * (1 + D)], 1e-300)) - le))
+                         : -3.f;
+      feat[6] = 0.05f * (float)a.iter;
+      feat[7] = square ? 1.f : 0.f;
+      if (a.skip == 2) {
+        const float z = mlp_logit_wave(th, feat, lane);
+        if (z > a.mlp_z) {
+          owned[o] = false;
+          if (lane == 0) atomicAdd(a.mlp_skipped, 1ull);
+          continue;
+        }
+      }
+      if (a.log_cap > 0) {
+        logit_o[o] = true;
+        // features to a slot claimed below; lane o keeps them until then
+        if (lane < MLP_NF) {
+          float v = 0.f;
+#pragma unroll
+          for (int i = 0; i < MLP_NF; ++i) v = (lane == i) ? feat[i] : v;
+          ns[wave * NO * MLP_NF + o * MLP_NF + lane] = v;  // wave-private scratch
+        }
+        ++nlog;
       }
     }
+    if (a.log_cap > 0 && nlog > 0) {
+      int base_slot = 0;
+      if (lane == 0) base_slot = (int)atomicAdd(a.log_count, (unsigned long long)nlog);
+      base_slot = __builtin_amdgcn_readfirstlane(base_slot);
+      int rank = 0;
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+        if (!logit_o[o]) continue;
+        const long long slot = (long long)base_slot + rank++;
+        if (slot < a.log_cap) {
+          if (lane < MLP_NF) a.log_x[slot * MLP_NF + lane] = ns[wave * NO * MLP_NF + o * MLP_NF + lane];
+          if (lane == o) my_slot = (int)slot;
+        }
+      }
+    }
+    __syncthreads();  // the network and the scratch in buf are dead from here
     any_owned = false;
 #pragma unroll
     for (int o = 0; o < NO; ++o) any_owned |= owned[o];
@@ -483,9 +578,14 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
     const int eIJ = __builtin_amdgcn_readlane(my_e, o);
-    if (!owned[o] || np[o] == 0) continue;
-    issued += np[o];
-    epilogue<T, D>(E, acc[o], Io[o], Jo[o], eIJ, square, eps, np[o], sys, q);
+    const int slot = __builtin_amdgcn_readlane(my_slot, o);
+    if (!owned[o]) continue;
+    bool kept = false;
+    if (np[o] > 0) {
+      issued += np[o];
+      kept = epilogue<T, D>(E, acc[o], Io[o], Jo[o], eIJ, square, eps, np[o], sys, q);
+    }
+    if (slot >= 0 && lane == 0) a.log_y[slot] = kept ? 0.f : 1.f;  // label: dropped
   }
   if (lane == 0) {
 #pragma unroll

@@ -23,7 +23,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "FLOOR_REACHED", -1: "EINVAL", -2: "EN
           -3: "EDEVICE", -4: "ENONSYM", -5: "EDEGENERATE", -6: "ENAN", -7: "EOVERFLOW"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 KERNEL = {"tile": 0, "block": 1}
-SKIP = {"none": 0, "bound": 1}
+SKIP = {"none": 0, "bound": 1, "mlp": 2}
 
 
 class tc2_bsr(C.Structure):
@@ -42,7 +42,8 @@ class tc2_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("closing_fp64", C.c_int32), ("skip", C.c_int32),
                 ("device", C.c_int32), ("export_matrices", C.c_int32), ("verbose", C.c_int32),
                 ("profile", C.c_int32), ("numeric_kernel", C.c_int32),
-                ("fp64_first", C.c_int32)]
+                ("fp64_first", C.c_int32), ("mlp_weights", C.POINTER(C.c_float)),
+                ("mlp_threshold", C.c_float), ("log_capacity", C.c_int64)]
 
 
 class tc2_result(C.Structure):
@@ -51,7 +52,7 @@ class tc2_result(C.Structure):
                 ("e0", C.c_double), ("e1", C.c_double * 3), ("emin", C.c_double),
                 ("emax", C.c_double), ("seconds", C.c_double), ("useful_flops", C.c_double),
                 ("executed_flops", C.c_double), ("kept_blocks", C.c_int64),
-                ("screened_blocks", C.c_int64),
+                ("screened_blocks", C.c_int64), ("mlp_skipped_blocks", C.c_int64),
                 ("ms_symbolic", C.c_double), ("ms_numeric", C.c_double),
                 ("ms_compact", C.c_double), ("numeric_launches", C.c_int32),
                 ("branches", C.c_char * (TC2_MAX_ITER + 4)),
@@ -84,7 +85,69 @@ def lib() -> C.CDLL:
     return _lib
 
 
-EXPORTED = ("tc2_setup", "tc2_run", "tc2_free", "tc2_strerror", "tc2_version")
+EXPORTED = ("tc2_setup", "tc2_run", "tc2_free", "tc2_strerror", "tc2_version",
+            "tc2_mlp_forward", "tc2_mlp_grad", "tc2_mlp_train", "tc2_log_copy")
+
+MLP_IN, MLP_PARAMS = 8, 4801
+
+
+class tc2_mlp_train_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("adam_eps", C.c_float),
+                ("device", C.c_int32)]
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def mlp_forward(theta, X, device: int = 0) -> np.ndarray:
+    """Logits of the skip network for rows of X (n x 8), on the device."""
+    th, X = _f32(theta, (MLP_PARAMS,)), _f32(X, (-1, MLP_IN))
+    out = np.empty(X.shape[0], dtype=np.float32)
+    L = lib()
+    L.tc2_mlp_forward.restype = C.c_int
+    st = L.tc2_mlp_forward(_fptr(th), _fptr(X), C.c_int64(X.shape[0]), C.c_int32(device), _fptr(out))
+    if st != 0:
+        raise TC2Error(st, "tc2_mlp_forward")
+    return out
+
+
+def mlp_grad(theta, X, y, device: int = 0):
+    """(gradient, loss) of the mean binary cross-entropy on logits."""
+    th, X, y = _f32(theta, (MLP_PARAMS,)), _f32(X, (-1, MLP_IN)), _f32(y, (-1,))
+    g = np.empty(MLP_PARAMS, dtype=np.float32)
+    loss = C.c_double()
+    L = lib()
+    L.tc2_mlp_grad.restype = C.c_int
+    st = L.tc2_mlp_grad(_fptr(th), _fptr(X), _fptr(y), C.c_int64(X.shape[0]), C.c_int32(device),
+                        _fptr(g), C.byref(loss))
+    if st != 0:
+        raise TC2Error(st, "tc2_mlp_grad")
+    return g, loss.value
+
+
+def mlp_train(X, y, theta0, epochs: int = 10, batch: int = 4096, lr: float = 1e-3,
+              beta1: float = 0.9, beta2: float = 0.999, adam_eps: float = 1e-8, device: int = 0):
+    """Train on the device with Adam; returns (theta, loss per epoch)."""
+    th = _f32(theta0, (MLP_PARAMS,)).copy()
+    X, y = _f32(X, (-1, MLP_IN)), _f32(y, (-1,))
+    losses = np.zeros(epochs, dtype=np.float64)
+    o = tc2_mlp_train_opts(epochs, batch, lr, beta1, beta2, adam_eps, device)
+    L = lib()
+    L.tc2_mlp_train.restype = C.c_int
+    st = L.tc2_mlp_train(_fptr(X), _fptr(y), C.c_int64(X.shape[0]), C.byref(o), _fptr(th),
+                         losses.ctypes.data_as(C.POINTER(C.c_double)))
+    if st != 0:
+        raise TC2Error(st, "tc2_mlp_train")
+    return th, losses
 
 
 class TC2Error(RuntimeError):
@@ -112,6 +175,7 @@ class Result:
     executed_flops: float
     kept_blocks: int = 0
     screened_blocks: int = 0
+    mlp_skipped_blocks: int = 0
     ms_symbolic: float = 0.0
     ms_numeric: float = 0.0
     ms_compact: float = 0.0
@@ -150,7 +214,8 @@ class Solver:
                  closing_fp64: int = 0, export: bool = True, device: int = 0,
                  replay: Optional[Sequence[Optional[str]]] = None, verbose: bool = False,
                  profile: bool = False, kernel: str = "tile", use_xyz: bool = True,
-                 fp64_first: int = 0, skip: str = "none"):
+                 fp64_first: int = 0, skip: str = "none", mlp_weights=None,
+                 mlp_threshold: float = 0.99, log_capacity: int = 0):
         if isinstance(systems, System):
             systems = [systems]
         self.systems = list(systems)
@@ -179,9 +244,16 @@ class Solver:
                 self._keep.append(xyz)
                 p.xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
         self.n_dir = len(self.systems[0].H1)
+        wptr = None
+        if mlp_weights is not None:
+            w = _f32(mlp_weights, (MLP_PARAMS,))
+            self._keep.append(w)
+            wptr = _fptr(w)
         opts = tc2_options(PRECISION[precision], int(closing_fp64), SKIP[skip], int(device),
                            1 if export else 0, 1 if verbose else 0, 1 if profile else 0,
-                           KERNEL[kernel], int(fp64_first))
+                           KERNEL[kernel], int(fp64_first), wptr, float(mlp_threshold),
+                           int(log_capacity))
+        self.log_capacity = int(log_capacity)
         self._ctx = C.c_void_p()
         st = lib().tc2_setup(probs, n, C.byref(opts), C.byref(self._ctx))
         if st != 0:
@@ -201,10 +273,23 @@ class Solver:
             out.append(Result(r.status, r.iters, r.branches.decode(), list(r.trace_x1h1[:D]),
                               r.tr_x0, r.idem_err, list(r.tr_x1[:D]), r.e0, list(r.e1[:D]),
                               r.emin, r.emax, r.seconds, r.useful_flops, r.executed_flops,
-                              r.kept_blocks, r.screened_blocks, r.ms_symbolic, r.ms_numeric,
-                              r.ms_compact,
+                              r.kept_blocks, r.screened_blocks, r.mlp_skipped_blocks,
+                              r.ms_symbolic, r.ms_numeric, r.ms_compact,
                               r.numeric_launches, x0, x1))
         return out
+
+    def log(self):
+        """(features n x 8, labels n) logged by the last run (1 = dropped)."""
+        cap = self.log_capacity
+        x = np.empty((max(cap, 1), MLP_IN), dtype=np.float32)
+        y = np.empty(max(cap, 1), dtype=np.float32)
+        L = lib()
+        L.tc2_log_copy.restype = C.c_int64
+        L.tc2_log_copy.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int64]
+        n = L.tc2_log_copy(self._ctx, _fptr(x), _fptr(y), cap)
+        if n < 0:
+            raise TC2Error(int(n), "tc2_log_copy")
+        return x[:n].copy(), y[:n].copy()
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -1,0 +1,55 @@
+"""Learned block skip: logged training data, GPU-trained network, and what it
+gains over the exact norm-bound screen on a system it was not trained on.
+The exact-screen solve is the judge of the error the network introduces."""
+import numpy as np
+import pytest
+
+from paper_2009_03551_amd import skipnet
+from paper_2009_03551_amd import tc2 as T
+from paper_2009_03551_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def dense_x1(r):
+    return [T.bsr_dense(x) for x in r.X1]
+
+
+@pytest.fixture(scope="module")
+def trained():
+    train_sys = [W.config_system("cube10", L=L, seed=500 + L, eps=1e-5) for L in (5, 6, 7)]
+    x, y = skipnet.collect(train_sys)
+    print(f"  logged {len(y)} candidates, dropped fraction {y.mean():.3f}", flush=True)
+    theta, losses = skipnet.train(x, y, epochs=25)
+    print(f"  training loss {losses[0]:.4f} -> {losses[-1]:.4f}", flush=True)
+    return theta, losses, x, y
+
+
+def test_logged_features_are_finite_and_labelled(trained):
+    _, _, x, y = trained
+    assert len(y) > 1000
+    assert np.all(np.isfinite(x))
+    assert set(np.unique(y)) <= {0.0, 1.0}
+    assert 0.02 < y.mean() < 0.98
+
+
+def test_training_reduces_loss(trained):
+    _, losses, _, _ = trained
+    assert losses[-1] < 0.7 * losses[0]
+
+
+def test_network_gain_over_exact_screen(trained):
+    theta = trained[0]
+    s = W.config_system("cube10", L=7, seed=42, eps=1e-5)      # not a training system
+    a = T.solve(s, skip="bound", profile=True)[0]
+    b = T.solve(s, skip="mlp", mlp_weights=theta, mlp_threshold=0.995, profile=True)[0]
+    dx1 = max(np.abs(p - q).max() for p, q in zip(dense_x1(a), dense_x1(b)))
+    dal = abs(a.alpha[0] - b.alpha[0]) / abs(a.alpha[0])
+    gain = 1.0 - b.executed_flops / a.executed_flops
+    print(f"  exact screen: {a.screened_blocks} skipped, {a.executed_flops / 1e12:.3f} TF; "
+          f"network: +{b.mlp_skipped_blocks} skipped, {b.executed_flops / 1e12:.3f} TF "
+          f"({100 * gain:.1f}% less); max|dX1| vs exact screen {dx1:.2e}, rel|dalpha| {dal:.2e}",
+          flush=True)
+    assert b.mlp_skipped_blocks > 0
+    assert b.executed_flops < a.executed_flops
+    assert dx1 < 1e-4
