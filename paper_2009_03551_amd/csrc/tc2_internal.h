@@ -148,6 +148,7 @@ struct TileArgs {
   float* log_y;           // logged labels (1 = dropped)
   unsigned long long* log_count;
   long long log_cap;      // 0: no logging
+  int kl_chunk;           // 0: default panel pass length
   int ksteps;
   int n_tiles;
   const int* rp;

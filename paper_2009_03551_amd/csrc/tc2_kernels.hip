@@ -72,35 +72,37 @@ template <typename T>
 __global__ void k_init(long long n, int D, int b, const int* row_of, const int* ci,
                        const int* src_h, InitPtrs p, const double* hv, const int* sys_of,
                        const double* emin, const double* emax, const int* mode, T* xv) {
-  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  int per = (1 + D) * BS;
-  long long e = idx / per;
-  int rem = (int)(idx - e * per);
-  int m = rem / BS, q = rem - m * BS;
-  int c = q / BP, r = q - c * BP;
-  int I = row_of[e], J = ci[e];
-  int s = sys_of[I];
-  double v = 0.0;
-  if (r < b && c < b) {
-    int md = mode[s];
-    if (md == 0) {
-      double W = emax[s] - emin[s];
-      if (m == 0) {
-        int eh = src_h[e];
-        double h = eh >= 0 ? hv[(size_t)eh * BS + q] : 0.0;
-        double d = (I == J && r == c) ? emax[s] : 0.0;
-        v = (d - h) / W;
-      } else {
-        int eh = p.src_h1[m - 1][e];
-        double h = eh >= 0 ? p.h1v[m - 1][(size_t)eh * BS + q] : 0.0;
-        v = -h / W;
+  // grid-stride: a dispatch covers at most 2^32 work-items
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int per = (1 + D) * BS;
+    long long e = idx / per;
+    int rem = (int)(idx - e * per);
+    int m = rem / BS, q = rem - m * BS;
+    int c = q / BP, r = q - c * BP;
+    int I = row_of[e], J = ci[e];
+    int s = sys_of[I];
+    double v = 0.0;
+    if (r < b && c < b) {
+      int md = mode[s];
+      if (md == 0) {
+        double W = emax[s] - emin[s];
+        if (m == 0) {
+          int eh = src_h[e];
+          double h = eh >= 0 ? hv[(size_t)eh * BS + q] : 0.0;
+          double d = (I == J && r == c) ? emax[s] : 0.0;
+          v = (d - h) / W;
+        } else {
+          int eh = p.src_h1[m - 1][e];
+          double h = eh >= 0 ? p.h1v[m - 1][(size_t)eh * BS + q] : 0.0;
+          v = -h / W;
+        }
+      } else if (md == 2) {
+        v = (m == 0 && I == J && r == c) ? 1.0 : 0.0;
       }
-    } else if (md == 2) {
-      v = (m == 0 && I == J && r == c) ? 1.0 : 0.0;
     }
+    xv[idx] = (T)v;
   }
-  xv[idx] = (T)v;
 }
 
 // ------------------------------------------------------------------ symbolic
@@ -445,16 +447,17 @@ __global__ __launch_bounds__(256) void k_row_sort(CompactArgs a) {
 // C_IJ^T column-major, i.e. the stage as it is.
 template <typename T>
 __global__ void k_gather(long long n, int D, const int* new_src, const T* stage, T* xv) {
-  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  int per = (1 + D) * BS;
-  long long e = idx / per;
-  int rem = (int)(idx - e * per);
-  int m = rem / BS, qd = rem - m * BS;
-  int src = new_src[e];
-  int slot = src >> 1;
-  int qs = (src & 1) ? qd : ((qd & 15) * BP + (qd >> 4));
-  xv[idx] = stage[(size_t)slot * per + m * BS + qs];
+  const int per = (1 + D) * BS;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (long long)gridDim.x * blockDim.x) {
+    long long e = idx / per;
+    int rem = (int)(idx - e * per);
+    int m = rem / BS, qd = rem - m * BS;
+    int src = new_src[e];
+    int slot = src >> 1;
+    int qs = (src & 1) ? qd : ((qd & 15) * BP + (qd >> 4));
+    xv[idx] = stage[(size_t)slot * per + m * BS + qs];
+  }
 }
 
 // ------------------------------------------------------------------ reductions
@@ -480,28 +483,38 @@ __global__ __launch_bounds__(256) void k_reduce(const int* lo, const int* hi,
 // ------------------------------------------------------------------ export / convert
 template <typename T>
 __global__ void k_export(long long n, int D, int m, int b, const T* xv, double* out) {
-  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  int bb = b * b;
-  long long e = idx / bb;
-  int rem = (int)(idx - e * bb);
-  int r = rem / b, c = rem - r * b;
-  out[idx] = (double)xv[((size_t)e * (1 + D) + m) * BS + c * BP + r];
+  const int bb = b * b;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (long long)gridDim.x * blockDim.x) {
+    long long e = idx / bb;
+    int rem = (int)(idx - e * bb);
+    int r = rem / b, c = rem - r * b;
+    out[idx] = (double)xv[((size_t)e * (1 + D) + m) * BS + c * BP + r];
+  }
 }
 
 template <typename A, typename B>
 __global__ void k_convert(long long n, const A* in, B* out) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (B)in[i];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = (B)in[i];
 }
 
 __global__ void k_fill_int(int* p, int v, long long n) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 
 // ================================================================== launchers
 static inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+// Grid of a grid-stride elementwise kernel: enough blocks to fill the chip
+// several times over, while blocks x threads stays far below 2^32 (a dispatch
+// counts its work-items in 32 bits).
+static inline unsigned sblk(long long n, int bs) {
+  long long g = (n + bs - 1) / bs;
+  return (unsigned)(g < 65536 ? (g > 0 ? g : 1) : 65536);
+}
 
 void launch_gershgorin(hipStream_t st, int nb, int b, const int* rp, const int* ci,
                        const double* hv, double* rowlo, double* rowhi) {
@@ -530,10 +543,10 @@ void launch_init(hipStream_t st, int prec, int nnz, int D, int b, const int* row
   long long n = (long long)nnz * (1 + D) * BS;
   if (n == 0) return;
   if (prec == P_FP64)
-    hipLaunchKernelGGL(k_init<double>, dim3(nblk(n, 256)), dim3(256), 0, st, n, D, b, row_of, ci,
+    hipLaunchKernelGGL(k_init<double>, dim3(sblk(n, 256)), dim3(256), 0, st, n, D, b, row_of, ci,
                        src_h, p, hv, sys_of, emin, emax, mode, (double*)xv);
   else
-    hipLaunchKernelGGL(k_init<float>, dim3(nblk(n, 256)), dim3(256), 0, st, n, D, b, row_of, ci,
+    hipLaunchKernelGGL(k_init<float>, dim3(sblk(n, 256)), dim3(256), 0, st, n, D, b, row_of, ci,
                        src_h, p, hv, sys_of, emin, emax, mode, (float*)xv);
 }
 
@@ -619,10 +632,10 @@ void launch_gather(hipStream_t st, int prec, int nnz, int D, const int* new_src,
   long long n = (long long)nnz * (1 + D) * BS;
   if (n == 0) return;
   if (prec == P_FP64)
-    hipLaunchKernelGGL(k_gather<double>, dim3(nblk(n, 256)), dim3(256), 0, st, n, D, new_src,
+    hipLaunchKernelGGL(k_gather<double>, dim3(sblk(n, 256)), dim3(256), 0, st, n, D, new_src,
                        (const double*)stage, (double*)xv);
   else
-    hipLaunchKernelGGL(k_gather<float>, dim3(nblk(n, 256)), dim3(256), 0, st, n, D, new_src,
+    hipLaunchKernelGGL(k_gather<float>, dim3(sblk(n, 256)), dim3(256), 0, st, n, D, new_src,
                        (const float*)stage, (float*)xv);
 }
 
@@ -636,10 +649,10 @@ void launch_export(hipStream_t st, int prec, int nnz, int D, int m, int b, const
   long long n = (long long)nnz * b * b;
   if (n == 0) return;
   if (prec == P_FP64)
-    hipLaunchKernelGGL(k_export<double>, dim3(nblk(n, 256)), dim3(256), 0, st, n, D, m, b,
+    hipLaunchKernelGGL(k_export<double>, dim3(sblk(n, 256)), dim3(256), 0, st, n, D, m, b,
                        (const double*)xv, out);
   else
-    hipLaunchKernelGGL(k_export<float>, dim3(nblk(n, 256)), dim3(256), 0, st, n, D, m, b,
+    hipLaunchKernelGGL(k_export<float>, dim3(sblk(n, 256)), dim3(256), 0, st, n, D, m, b,
                        (const float*)xv, out);
 }
 
@@ -648,16 +661,16 @@ void launch_convert(hipStream_t st, int from_prec, int to_prec, long long n, con
   if (n == 0) return;
   bool f64in = from_prec == P_FP64, f64out = to_prec == P_FP64;
   if (f64in && !f64out)
-    hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(n, 256)), dim3(256), 0, st, n,
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(sblk(n, 256)), dim3(256), 0, st, n,
                        (const double*)in, (float*)out);
   else if (!f64in && f64out)
-    hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(n, 256)), dim3(256), 0, st, n,
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(sblk(n, 256)), dim3(256), 0, st, n,
                        (const float*)in, (double*)out);
 }
 
 void launch_fill_int(hipStream_t st, int* p, int v, long long n) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_fill_int, dim3(nblk(n, 256)), dim3(256), 0, st, p, v, n);
+  hipLaunchKernelGGL(k_fill_int, dim3(sblk(n, 256)), dim3(256), 0, st, p, v, n);
 }
 
 }  // namespace tc2

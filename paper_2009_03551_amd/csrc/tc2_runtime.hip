@@ -118,6 +118,10 @@ struct tc2_ctx {
   long long log_cap = 0, log_n = 0;
   DBuf log_x, log_y, log_count;
   int update_index = 0;
+  // test knobs (environment, read at setup): shorter panel passes in the
+  // tiled kernel, and a tiny stage that overflows every update
+  int test_kl_chunk = 0;
+  long long test_stage_cap = 0;
   std::vector<int> h_active;      // host copy of the active flags
   // clusters
   int nc = 0, max_sys_clusters = 0;
@@ -314,6 +318,8 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   ctx->fp64_first = o->fp64_first;
   ctx->skip = o->skip;
   ctx->log_cap = o->log_capacity;
+  if (const char* v = getenv("TC2_TEST_KL_CHUNK")) ctx->test_kl_chunk = std::max(0, atoi(v));
+  if (const char* v = getenv("TC2_TEST_STAGE_CAP")) ctx->test_stage_cap = std::max(0LL, atoll(v));
   tc2_status st = TC2_OK;
   auto fail = [&](tc2_status s) {
     tc2_free(ctx);
@@ -682,7 +688,9 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   // ---- numeric (retried with a larger stage if it overflows).  The stage
   // holds every possible output block when that fits a modest budget.
   if (any_stopped) out_bound += ctx->nnz[c];
-  {
+  if (ctx->test_stage_cap > 0) {
+    ctx->stage_cap = ctx->test_stage_cap;  // forces the overflow / retry path
+  } else {
     const size_t budget = (size_t)16 << 30;
     if ((size_t)out_bound * tile <= budget) ctx->stage_cap = std::max<long long>(ctx->stage_cap, out_bound);
     else if (ctx->stage_cap == 0) ctx->stage_cap = std::max(ctx->nnz[c], nb) + 1024;
@@ -795,6 +803,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       ta.log_x = ctx->log_cap > 0 ? ctx->log_x.as<float>() : nullptr;
       ta.log_y = ctx->log_cap > 0 ? ctx->log_y.as<float>() : nullptr;
       ta.log_count = ctx->log_cap > 0 ? ctx->log_count.as<unsigned long long>() : nullptr;
+      ta.kl_chunk = ctx->test_kl_chunk;
       if (screen) launch_fill_int(st, ctx->screened.as<int>(), 0, 4);
       launch_tile_numeric(st, ctx->cur_prec, ta);
     }

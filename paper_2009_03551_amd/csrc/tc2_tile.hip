@@ -316,7 +316,10 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
   // learned screen then evaluates the skip network on features of the
   // remaining outputs and skips those it predicts to be dropped; features and
   // the true outcome can be logged for training.
-  const bool single_chunk = (pp1 - pp0) <= KLMAX;
+  // columns of P's panel taken per pass (a smaller chunk can be forced to test
+  // the multi-pass path on small inputs)
+  const int KLC = (a.kl_chunk > 0 && a.kl_chunk < KLMAX) ? a.kl_chunk : KLMAX;
+  const bool single_chunk = (pp1 - pp0) <= KLC;
   int nm_kept = -1;
   int my_slot = -1;  // lane o: log slot of output o
   if (a.skip || a.log_cap > 0) {
@@ -345,8 +348,8 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
 #pragma unroll
       for (int m = 0; m <= D; ++m) bsum[o][m] = 0.0;
     }
-    for (int base = pp0; base < pp1; base += KLMAX) {
-      const int nm = build_kl(base, min(pp1, base + KLMAX));
+    for (int base = pp0; base < pp1; base += KLC) {
+      const int nm = build_kl(base, min(pp1, base + KLC));
       nm_kept = nm;
       for (int r0 = 0; r0 < nm; r0 += NSF) {
         const int nr = min(NSF, nm - r0);
@@ -468,9 +471,9 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
     for (int o = 0; o < NO; ++o) any_owned |= owned[o];
   }
 
-  for (int base = pp0; base < pp1; base += KLMAX) {
+  for (int base = pp0; base < pp1; base += KLC) {
     // ---- common columns of this chunk of P's panel with Q's panel
-    const int end = min(pp1, base + KLMAX);
+    const int end = min(pp1, base + KLC);
     const int nm = (single_chunk && nm_kept >= 0) ? nm_kept : build_kl(base, end);
     // ---- pipelined products over the common columns
     const int ngroups = (nm + KG - 1) / KG;
@@ -605,34 +608,36 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
 // stage unchanged (row-major upper block).
 template <typename T>
 __global__ void k_copy_through(CopyArgs a) {
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   const int nnz = a.rp[a.nb];
-  if (wave >= nnz) return;
-  const int e = wave;
-  int lo = 0, hi = a.nb;  // row of entry e
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (a.rp[mid] <= e) lo = mid; else hi = mid;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < nnz;
+       w += nwaves) {
+    const int e = (int)w;
+    int lo = 0, hi = a.nb;  // row of entry e
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.rp[mid] <= e) lo = mid; else hi = mid;
+    }
+    const int I = lo, J = a.ci[e];
+    if (J < I || a.active[a.sys_of[I]]) continue;
+    int slot = 0;
+    if (lane == 0) slot = atomicAdd(a.stage_count, 1);
+    slot = __builtin_amdgcn_readfirstlane(slot);
+    if (slot >= a.stage_cap) {
+      if (lane == 0) atomicOr(a.overflow, 1);
+      continue;
+    }
+    const int per = (1 + a.D) * BS;
+    const T* X = (const T*)a.xv + (size_t)e * per;
+    T* st = (T*)a.stage + (size_t)slot * per;
+    for (int q = lane; q < per; q += 64) {
+      const int m = q / BS, qq = q - m * BS;  // stage index qq = r*16 + c
+      const int r = qq >> 4, c = qq & 15;
+      st[q] = X[m * BS + c * BP + r];
+    }
+    if (lane == 0) a.kept_ij[slot] = make_int2(I, J);
   }
-  const int I = lo, J = a.ci[e];
-  if (J < I || a.active[a.sys_of[I]]) return;
-  int slot = 0;
-  if (lane == 0) slot = atomicAdd(a.stage_count, 1);
-  slot = __builtin_amdgcn_readfirstlane(slot);
-  if (slot >= a.stage_cap) {
-    if (lane == 0) atomicOr(a.overflow, 1);
-    return;
-  }
-  const int per = (1 + a.D) * BS;
-  const T* X = (const T*)a.xv + (size_t)e * per;
-  T* st = (T*)a.stage + (size_t)slot * per;
-  for (int q = lane; q < per; q += 64) {
-    const int m = q / BS, qq = q - m * BS;  // stage index qq = r*16 + c
-    const int r = qq >> 4, c = qq & 15;
-    st[q] = X[m * BS + c * BP + r];
-  }
-  if (lane == 0) a.kept_ij[slot] = make_int2(I, J);
 }
 
 // ------------------------------------------------------------------ block norms
@@ -640,25 +645,29 @@ __global__ void k_copy_through(CopyArgs a) {
 // entry; used by the screens.
 template <typename T>
 __global__ void k_block_norms(long long nnz, int D, const T* xv, float* bn) {
-  const long long e = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (e >= nnz) return;
-  for (int m = 0; m <= D; ++m) {
-    const T* x = xv + ((size_t)e * (1 + D) + m) * BS;
-    double ss = 0.0;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long e = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < nnz;
+       e += nwaves) {
+    for (int m = 0; m <= D; ++m) {
+      const T* x = xv + ((size_t)e * (1 + D) + m) * BS;
+      double ss = 0.0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const double v = (double)x[lane + 64 * j];
-      ss += v * v;
+      for (int j = 0; j < 4; ++j) {
+        const double v = (double)x[lane + 64 * j];
+        ss += v * v;
+      }
+      ss = wave_sum(ss);
+      if (lane == 0) bn[(size_t)e * (1 + D) + m] = (float)sqrt(ss);
     }
-    ss = wave_sum(ss);
-    if (lane == 0) bn[(size_t)e * (1 + D) + m] = (float)sqrt(ss);
   }
 }
 
 void launch_block_norms(hipStream_t st, int prec, long long nnz, int D, const void* xv, float* bn) {
   if (nnz == 0) return;
-  const unsigned blocks = (unsigned)((nnz * 64 + 255) / 256);
+  // one wave per entry, waves loop over entries beyond 2^24 blocks of 4 waves
+  const long long want = (nnz + 3) / 4;
+  const unsigned blocks = (unsigned)(want < (1 << 20) ? want : (1 << 20));
   if (prec == P_FP64) hipLaunchKernelGGL(k_block_norms<double>, dim3(blocks), dim3(256), 0, st, nnz, D, (const double*)xv, bn);
   else hipLaunchKernelGGL(k_block_norms<float>, dim3(blocks), dim3(256), 0, st, nnz, D, (const float*)xv, bn);
 }
@@ -720,7 +729,8 @@ void launch_tile_numeric(hipStream_t st, int prec, const TileArgs& a) {
 
 void launch_copy_through(hipStream_t st, int prec, const CopyArgs& a, int nnz) {
   if (nnz == 0) return;
-  const unsigned blocks = (unsigned)(((long long)nnz * 64 + 255) / 256);
+  const long long want = ((long long)nnz + 3) / 4;
+  const unsigned blocks = (unsigned)(want < (1 << 20) ? want : (1 << 20));
   if (prec == P_FP64) hipLaunchKernelGGL(k_copy_through<double>, dim3(blocks), dim3(256), 0, st, a);
   else hipLaunchKernelGGL(k_copy_through<float>, dim3(blocks), dim3(256), 0, st, a);
 }

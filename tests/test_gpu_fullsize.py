@@ -1,0 +1,86 @@
+"""Parity at the benchmark sizes.
+
+cube10 (10^3 atoms, b = 13, N = 13000): the GPU solve against the FP64
+oracle's result stored in tests/golden/cube10_oracle.json (written by
+tests/golden/make_golden.py, which calls only the oracle): branch sequence,
+scalars, and a seeded sample of 32 blocks of X0 and X1.
+
+cube20 (8000 atoms, N = 104000, three directions): too large for the dense
+oracle; checked through properties that hold at any size (trace and
+idempotency of X0, traceless response, vanishing Tr(X1 H)).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2009_03551_amd import tc2 as T
+from paper_2009_03551_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def golden(name):
+    with open(os.path.join(HERE, "golden", f"{name}_oracle.json")) as f:
+        return json.load(f)
+
+
+def block(m, I, J):
+    lo, hi = int(m.row_ptr[I]), int(m.row_ptr[I + 1])
+    k = np.searchsorted(m.col[lo:hi], J)
+    if k < hi - lo and m.col[lo + k] == J:
+        return m.val[lo + k]
+    return np.zeros((m.b, m.b))
+
+
+@pytest.mark.parametrize("variant", [dict(kernel="tile"), dict(kernel="tile", skip="bound"),
+                                     dict(kernel="block")])
+def test_cube10_matches_oracle(variant):
+    g0 = golden("cube10")
+    s = W.config_system("cube10")
+    r = T.solve(s, **variant)[0]
+    print(f"  {variant}: {r.status_name} it={r.iters} alpha={r.alpha[0]:.14f} "
+          f"(oracle {g0['alpha'][0]:.14f})", flush=True)
+    assert r.branches == g0["branches"] and r.iters == g0["iters"] and r.status == g0["status"]
+    assert abs(r.alpha[0] - g0["alpha"][0]) < 1e-10 * abs(g0["alpha"][0])
+    assert abs(r.emin - g0["emin"]) < 1e-12 and abs(r.emax - g0["emax"]) < 1e-12
+    assert abs(r.tr_x0 - g0["tr_x0"]) < 1e-8
+    assert abs(r.e0 - g0["e0"]) < 1e-10 * abs(g0["e0"])
+    dx0 = dx1 = 0.0
+    for blk in g0["blocks"]:
+        I, J = blk["I"], blk["J"]
+        dx0 = max(dx0, np.abs(block(r.X0, I, J) - np.array(blk["X0"])).max())
+        dx1 = max(dx1, np.abs(block(r.X1[0], I, J) - np.array(blk["X1"][0])).max())
+    print(f"    sampled blocks: max|dX0|={dx0:.2e} max|dX1|={dx1:.2e}", flush=True)
+    assert dx0 < 1e-9 and dx1 < 1e-9
+
+
+def test_cube10_fp32_against_oracle():
+    g0 = golden("cube10")
+    s = W.config_system("cube10")
+    r = T.solve(s, precision="fp32", closing_fp64=2, fp64_first=8)[0]
+    dal = abs(r.alpha[0] - g0["alpha"][0]) / abs(g0["alpha"][0])
+    dx1 = max(np.abs(block(r.X1[0], b["I"], b["J"]) - np.array(b["X1"][0])).max() for b in g0["blocks"])
+    print(f"  fp32 (8 leading FP64 updates, closing pair): sampled max|dX1|={dx1:.2e} "
+          f"rel|dalpha|={dal:.2e}", flush=True)
+    assert abs(r.tr_x0 - s.n_occ) < 1e-6
+    assert dx1 < 5e-6 and dal < 1e-5
+
+
+def test_cube20_invariants_three_directions():
+    s = W.config_system("cube20")
+    r = T.solve(s, export=False, skip="bound")[0]
+    print(f"  cube20: {r.status_name} it={r.iters} kept blocks {r.kept_blocks} "
+          f"tr-Nocc={r.tr_x0 - s.n_occ:.2e} idem={r.idem_err:.2e} trX1={r.tr_x1} "
+          f"trX1H={r.e1} alpha={r.alpha} {r.seconds:.2f}s", flush=True)
+    assert r.status in (0, 2)
+    assert abs(r.tr_x0 - s.n_occ) < 1e-6
+    assert abs(r.idem_err) < 1e-4
+    for d in range(3):
+        assert abs(r.tr_x1[d]) < 1e-6
+        assert abs(r.e1[d]) < 1e-5
+        assert r.alpha[d] < 0
+    # the three directions are equivalent on a cube up to the random couplings
+    assert max(r.alpha) / min(r.alpha) > 0.9

@@ -170,3 +170,28 @@ def test_norm_bound_screen_three_directions_matches_oracle():
     s = W.config_system("cube20", L=3, eps=1e-5)
     g, o = run_both(s, skip="bound")
     compare(s, g, o)
+
+
+@pytest.fixture
+def knob(monkeypatch):
+    def set_(name, value):
+        monkeypatch.setenv(name, str(value))
+    return set_
+
+
+@pytest.mark.parametrize("dirs,skip", [(1, "none"), (3, "none"), (3, "bound")])
+def test_forced_multipass_panels(knob, dirs, skip):
+    # panel passes of 64 columns: the path taken by large systems
+    knob("TC2_TEST_KL_CHUNK", 64)
+    s = W.config_system("cube20", L=4, n_dir=dirs, eps=1e-6)
+    g, o = run_both(s, skip=skip)
+    compare(s, g, o)
+
+
+@pytest.mark.parametrize("dirs", [1, 3])
+def test_forced_stage_overflow(knob, dirs):
+    # a stage of 16 blocks overflows at every update and is grown and retried
+    knob("TC2_TEST_STAGE_CAP", 16)
+    s = W.config_system("cube20", L=4, n_dir=dirs, eps=1e-6)
+    g, o = run_both(s)
+    compare(s, g, o)
