@@ -3,19 +3,19 @@
  *
  * The library purifies the zero-order density matrix X0 of a Hamiltonian H
  * given in an orthonormal atom-block basis with the second-order
- * trace-correcting recursion (Sec. 2.3, Eq. TC2), and, coupled with it, the
- * first-order response X1 to a homogeneous electric field (Sec. 2.3,
+ * trace-correcting recursion (Sec. 2.2, Eq. TC2), and, coupled with it, the
+ * first-order response X1 to a homogeneous electric field (Sec. 2.2,
  * Eq. TC2-CPSCF):
  *
  *   X0 <- (emax*I - H)/(emax - emin),  X1_d <- -H1_d/(emax - emin)
  *   repeat:  if Tr X0 >= Nocc:  X0 <- X0 X0,        X1_d <- X1_d X0 + X0 X1_d
  *            else:              X0 <- 2X0 - X0 X0,  X1_d <- 2X1_d - X1_d X0 - X0 X1_d
  *            drop every off-diagonal atom block whose Frobenius norm is < eps
- *                                     (filter of Sec. 2.4, made block-wise)
+ *                                     (filter of Sec. 2.3, made block-wise)
  *   until the band energies Tr(X0 H), Tr(X1_d H) and the traces
- *   Tr(X1_d H1_d) change by less than tol (tolerance of Sec. 2.4).
+ *   Tr(X1_d H1_d) change by less than tol (tolerance of Sec. 2.3).
  *
- * emin/emax are Gershgorin bounds of H (Sec. 2.3).  Each iteration is a
+ * emin/emax are Gershgorin bounds of H (Sec. 2.2).  Each iteration is a
  * truncated block-sparse product (symbolic pattern, numeric block products
  * X0X0, X0X1, X1X0 on MFMA, norm drop, trace reduction choosing the next
  * branch), all in HIP kernels on one GPU.  Several independent systems can be
@@ -109,6 +109,19 @@ typedef struct {
                               probability exceeds this, in (0, 1)              */
   int64_t log_capacity;    /* > 0: log up to this many (features, dropped)
                               samples per tc2_run for training (tiled kernel)  */
+  int32_t wide_accumulate; /* 0 or 1 (tiled kernel): in FP32 stages, the FP32
+                              MFMA product of each column block is added to an
+                              FP64 sum over the common columns, instead of one
+                              FP32 sum over all of them                         */
+  int32_t tune;            /* 0: default sub-tile shapes; 1 (tiled kernel):
+                              per kernel kind, take the shape from tune_cache
+                              or, failing that, time every available shape on
+                              the first update past the peak of the candidate
+                              outputs of a tc2_run and keep the fastest for the
+                              context (results do not depend on the shape)     */
+  const char *tune_cache;  /* NULL, or a file: tuned shapes are read from it at
+                              setup and appended to it (one JSON object per
+                              line) when measured                              */
 } tc2_options;
 
 typedef struct {
@@ -131,6 +144,15 @@ typedef struct {
   /* phase times in ms, summed over the updates (profile = 1 only) */
   double ms_symbolic, ms_numeric, ms_compact;
   int32_t numeric_launches;
+  int32_t tile_shape[4];   /* sub-tile shape used per kernel kind (FP64, FP32,
+                              BF16, FP32 with FP64 sums): 0 8x8, 1 4x8, 2 8x4,
+                              3 4x4 output blocks per workgroup; -1 unused     */
+  double ms_tune;          /* device time spent timing shapes in this run      */
+  /* per kernel kind (index as tile_shape): useful flops of the updates run
+     with it, and (profile = 1) numeric-kernel time in ms and launches */
+  double useful_flops_kind[4];
+  double ms_numeric_kind[4];
+  int32_t numeric_launches_kind[4];
   char branches[TC2_MAX_ITER + 4]; /* 'S'/'D' per update, NUL-terminated        */
   /* Library-owned host copies (valid until the next tc2_run or tc2_free) when
      export_matrices = 1; same layout as the inputs.  Otherwise zeroed. */

@@ -41,6 +41,13 @@ template <> struct Acc<float> {
   f4 v;
   __device__ static int row(int l, int j) { return 4 * (l >> 4) + j; }
 };
+// FP64 sums of f32 MFMA tiles (same element layout as Acc<float>): each
+// column block's FP32 product is added here, so that the long sum over the
+// common columns K runs in FP64.
+struct AccW {
+  d4 v;
+  __device__ static int row(int l, int j) { return 4 * (l >> 4) + j; }
+};
 
 __device__ __forceinline__ void mfma(Acc<double>& c, double a, double b) {
   c.v = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c.v, 0, 0, 0);
@@ -104,15 +111,16 @@ struct EpiCtx {
 };
 
 // Epilogue of one output block C_IJ (accumulators of X0*X0 and of
-// X0*X1_d + X1_d*X0) for the TC2 update (Sec. 2.3): combine with the branch
+// X0*X1_d + X1_d*X0) for the TC2 update (Sec. 2.2): combine with the branch
 // (SQUARE: C; DOUBLE: 2X - C), round to the working precision, Frobenius
-// norm of each matrix's block, drop below eps (filter of Sec. 2.4, never on
+// norm of each matrix's block, drop below eps (filter of Sec. 2.3, never on
 // the diagonal), append the kept block to the stage as the upper block
 // (min(I,J), max(I,J)) row-major, and add Tr, ||X0||_F^2, Tr(X H), Tr(X1 H1)
 // contributions (weight 2 off the diagonal) to q.  eIJ is the entry of the
-// old block (I, J) or -1.  Called by a whole wave.
-template <typename T, int D>
-__device__ __forceinline__ bool epilogue(const EpiCtx& E, const Acc<T>* acc, int I, int J,
+// old block (I, J) or -1.  A is the accumulator type (its element layout and
+// precision).  Called by a whole wave.
+template <typename T, int D, typename A = Acc<T>>
+__device__ __forceinline__ bool epilogue(const EpiCtx& E, const A* acc, int I, int J,
                                          int eIJ, bool square, double eps, int npairs, int sys,
                                          double* q) {
   const int lane = threadIdx.x & 63;
@@ -124,7 +132,7 @@ __device__ __forceinline__ bool epilogue(const EpiCtx& E, const Acc<T>* acc, int
   for (int m = 0; m <= D; ++m)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int r = Acc<T>::row(lane, j);
+      const int r = A::row(lane, j);
       const double c = (double)acc[m].v[j];
       double x = c;
       if (!square) {
@@ -160,7 +168,7 @@ __device__ __forceinline__ bool epilogue(const EpiCtx& E, const Acc<T>* acc, int
       for (int m = 0; m <= D; ++m)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int r = Acc<T>::row(lane, j);
+          const int r = A::row(lane, j);
           st[m * BS + (tr ? col * BP + r : r * BP + col)] = keep[m] ? (T)v[m][j] : (T)0;
         }
       if (lane == 0) E.kept_ij[slot] = tr ? make_int2(J, I) : make_int2(I, J);
@@ -175,7 +183,7 @@ __device__ __forceinline__ bool epilogue(const EpiCtx& E, const Acc<T>* acc, int
     for (int m = 0; m <= D; ++m) {
       double tr = 0.0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) tr += (Acc<T>::row(lane, j) == col) ? v[m][j] : 0.0;
+      for (int j = 0; j < 4; ++j) tr += (A::row(lane, j) == col) ? v[m][j] : 0.0;
       tr = wave_sum(tr);
       if (m == 0) q[Q_TR0] += tr; else q[Q_TR1 + m - 1] += tr;
     }
@@ -191,7 +199,7 @@ __device__ __forceinline__ bool epilogue(const EpiCtx& E, const Acc<T>* acc, int
       if (!keep[m]) continue;
       double dot = 0.0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) dot += v[m][j] * hb[col * BP + Acc<T>::row(lane, j)];
+      for (int j = 0; j < 4; ++j) dot += v[m][j] * hb[col * BP + A::row(lane, j)];
       dot = wave_sum(dot);
       if (m == 0) q[Q_E0] += w * dot; else q[Q_E1 + m - 1] += w * dot;
     }
@@ -206,7 +214,7 @@ __device__ __forceinline__ bool epilogue(const EpiCtx& E, const Acc<T>* acc, int
       const double* hb = E.h1_v[d] + (size_t)e1 * BS;
       double dot = 0.0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) dot += v[1 + d][j] * hb[col * BP + Acc<T>::row(lane, j)];
+      for (int j = 0; j < 4; ++j) dot += v[1 + d][j] * hb[col * BP + A::row(lane, j)];
       dot = wave_sum(dot);
       q[Q_AL + d] += w * dot;
     }

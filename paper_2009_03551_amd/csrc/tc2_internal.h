@@ -41,6 +41,14 @@ enum {
 
 enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2 };
 
+// Kinds of the tiled numeric kernel: FP64 values; FP32 values with FP32 sums;
+// FP32 values with bfloat16 MFMA operands; FP32 values with FP64 sums over the
+// column blocks.
+enum Kind { K_FP64 = 0, K_FP32 = 1, K_BF16 = 2, K_WIDE = 3 };
+// Sub-tile shapes of the tiled kernel: rows of cluster P x columns of cluster Q
+enum TileShape { TS_8x8 = 0, TS_4x8 = 1, TS_8x4 = 2, TS_4x4 = 3 };
+constexpr int TS_N = 4;
+
 struct SymArgs {
   int nb;
   const int* rp;        // current pattern
@@ -136,6 +144,8 @@ struct PanelArgs {
 struct TileArgs {
   int D;
   int bf16;               // FP32 values, MFMA operands rounded to bfloat16
+  int wide;               // FP32 values, per-block products summed in FP64
+  int shape;              // TileShape (must exist for the kind and D)
   int skip;               // 0 none, 1 exact norm-bound screen, 2 bound + network
   const float* bn;        // block norms (nnz x (1+D)) when skip != 0 or logging
   unsigned long long* screened;  // outputs skipped by the exact screen
@@ -232,8 +242,11 @@ void launch_numeric(hipStream_t st, int prec, const NumArgs& a);
 void launch_measure(hipStream_t st, int prec, const MeasArgs& a);
 void launch_panels(hipStream_t st, int pass, const PanelArgs& a);
 void launch_tiles(hipStream_t st, int pass, const PanelArgs& a);
-void launch_tile_numeric(hipStream_t st, int prec, const TileArgs& a);
-int tile_split(int prec, int D);  // blocks per tile of the tiled kernel
+bool launch_tile_numeric(hipStream_t st, int prec, const TileArgs& a);  // false: no such shape
+bool tile_shape_available(int kind, int D, int shape);
+int tile_shape_default(int kind, int D);
+int tile_subs(int shape);  // workgroups per tile of 8 x 8 output blocks
+const char* tile_shape_name(int shape);
 void launch_copy_through(hipStream_t st, int prec, const CopyArgs& a, int nnz);
 void launch_block_norms(hipStream_t st, int prec, long long nnz, int D, const void* xv, float* bn);
 void launch_compact_count(hipStream_t st, const CompactArgs& a, int n_kept);

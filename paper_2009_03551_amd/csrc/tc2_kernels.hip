@@ -1,6 +1,6 @@
 // HIP kernels of the TC2 / TC2-CPSCF solver for gfx950 (MI355X).
 //
-// One iteration of the recursion (Sec. 2.3, Eq. TC2 and Eq. TC2-CPSCF) is
+// One iteration of the recursion (Sec. 2.2, Eq. TC2 and Eq. TC2-CPSCF) is
 //   symbolic  : upper-triangle pattern of X*X by row-wise union (Gustavson's
 //               row formulation, Algorithm 1, restricted to J >= I), built in
 //               an LDS bitmap;
@@ -8,7 +8,7 @@
 //               sorted column lists of rows I and J, then accumulate
 //               X0_IK X0_KJ, X0_IK X1_KJ + X1_IK X0_KJ over the common K with
 //               MFMA on padded 16 x 16 tiles; fused epilogue: branch combine,
-//               block Frobenius norms, drop (filter of Sec. 2.4), traces and
+//               block Frobenius norms, drop (filter of Sec. 2.3), traces and
 //               band-energy partial sums;
 //   compact   : kept upper blocks -> new sorted symmetric pattern + values.
 #include "tc2_device.h"
@@ -16,7 +16,7 @@
 namespace tc2 {
 
 // ------------------------------------------------------------------ Gershgorin
-// Bounds of the spectrum of H (Sec. 2.3): per scalar row i, H_ii -+ sum_{j!=i} |H_ij|.
+// Bounds of the spectrum of H (Sec. 2.2): per scalar row i, H_ii -+ sum_{j!=i} |H_ij|.
 __global__ void k_gershgorin(int nb, int b, const int* rp, const int* ci, const double* hv,
                              double* rowlo, double* rowhi) {
   int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -62,7 +62,7 @@ __global__ void k_sys_minmax(const int* sys_start, const int* sys_end, int b, co
 }
 
 // ------------------------------------------------------------------ init
-// X0 = (emax I - H)/(emax - emin), X1_d = -H1_d/(emax - emin)  (Sec. 2.3).
+// X0 = (emax I - H)/(emax - emin), X1_d = -H1_d/(emax - emin)  (Sec. 2.2).
 struct InitPtrs {
   const int* src_h1[MAXD];
   const double* h1v[MAXD];

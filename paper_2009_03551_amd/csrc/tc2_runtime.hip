@@ -2,9 +2,9 @@
 //
 // tc2_setup validates and uploads the problems (a batch is merged into one
 // block-diagonal matrix with a system id per atom row); tc2_run drives the
-// recursion of Sec. 2.3 (Eq. TC2 coupled with Eq. TC2-CPSCF) on the device,
+// recursion of Sec. 2.2 (Eq. TC2 coupled with Eq. TC2-CPSCF) on the device,
 // one merged kernel sequence per update, and applies the stopping rule of
-// Sec. 2.4 (band-energy change below the tolerance) per system.
+// Sec. 2.3 (band-energy change below the tolerance) per system.
 #include "tc2_internal.h"
 #include "../../include/tc2.h"
 
@@ -71,6 +71,7 @@ struct SysState {
   int closing_first = 1;
   tc2_status status = TC2_OK;
   double trip = 0;
+  double trip_kind[4] = {0, 0, 0, 0};  // the same, per kernel kind
 };
 
 }  // namespace
@@ -82,6 +83,9 @@ struct tc2_ctx {
   int profile = 0;
   hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};
   double ms_sym = 0, ms_num = 0, ms_cmp = 0;
+  double ms_num_kind[4] = {0, 0, 0, 0};
+  int launches_kind[4] = {0, 0, 0, 0};
+  int last_kind = 0;                // kernel kind of the last update
   int num_launches = 0;
   int max_sys_atoms = 0;
   std::vector<SysInfo> sys;
@@ -108,6 +112,15 @@ struct tc2_ctx {
   int kernel = 0;                 // 0 tiled, 1 one wave per block
   int fp64_first = 0;             // leading FP64 updates of a reduced-precision solve
   int op_bf16 = 0;                // current stage rounds MFMA operands to bfloat16
+  int wide = 0;                   // FP32 stages: FP64 sums over the column blocks
+  int shape[4] = {0, 0, 0, 0};    // sub-tile shape per kernel kind
+  bool tuned[4] = {false, false, false, false};
+  int tune = 0;                   // 1: measure the shapes once per kind
+  std::string tune_cache;         // file of tuned shapes ("" = none)
+  std::string arch;               // device architecture name (cache key)
+  long long prev_out_bound = -1;  // candidate outputs of the previous update
+  double ms_tune = 0.0;
+  bool kind_used[4] = {false, false, false, false};
   int skip = 0;                   // 1: exact norm-bound screen, 2: + skip network
   DBuf bn, screened;              // block norms, skip counters [exact, network]
   unsigned long long screened_total = 0, mlp_total = 0;
@@ -242,6 +255,64 @@ void tc2_free(tc2_ctx* ctx) {
   delete ctx;
 }
 
+// ---- tuned sub-tile shapes.  The cache file holds one JSON object per line,
+//   {"key": "<arch>/<kind>/D<d>/k<ksteps>/s<skip>", "shape": "<SPxTQ>", "ms": {...}}
+// keyed by what changes the best shape: kernel kind, directions, K-steps per
+// block (block size) and screening.  Later lines win.
+static const char* kind_name(int k) {
+  static const char* n[4] = {"fp64", "fp32", "bf16", "fp32w"};
+  return n[k];
+}
+
+static std::string tune_key(const tc2_ctx* ctx, int kind) {
+  char buf[160];
+  snprintf(buf, sizeof(buf), "%s/%s/D%d/k%d/s%d", ctx->arch.c_str(), kind_name(kind), ctx->D,
+           (ctx->b + 3) / 4, ctx->skip);
+  return buf;
+}
+
+static void tune_load(tc2_ctx* ctx) {
+  if (ctx->tune_cache.empty()) return;
+  FILE* f = fopen(ctx->tune_cache.c_str(), "r");
+  if (!f) return;
+  std::string keys[4];
+  for (int k = 0; k < 4; ++k) keys[k] = "\"key\": \"" + tune_key(ctx, k) + "\"";
+  char line[1024];
+  while (fgets(line, sizeof(line), f)) {
+    for (int k = 0; k < 4; ++k) {
+      if (!strstr(line, keys[k].c_str())) continue;
+      const char* p = strstr(line, "\"shape\": \"");
+      if (!p) continue;
+      p += 10;
+      for (int sh = 0; sh < TS_N; ++sh) {
+        const char* nm = tile_shape_name(sh);
+        if (strncmp(p, nm, strlen(nm)) == 0 && p[strlen(nm)] == '"' &&
+            tile_shape_available(k, ctx->D, sh)) {
+          ctx->shape[k] = sh;
+          ctx->tuned[k] = true;
+        }
+      }
+    }
+  }
+  fclose(f);
+}
+
+static void tune_store(const tc2_ctx* ctx, int kind, const float* ms) {
+  if (ctx->tune_cache.empty()) return;
+  FILE* f = fopen(ctx->tune_cache.c_str(), "a");
+  if (!f) return;
+  fprintf(f, "{\"key\": \"%s\", \"shape\": \"%s\", \"ms\": {", tune_key(ctx, kind).c_str(),
+          tile_shape_name(ctx->shape[kind]));
+  bool first = true;
+  for (int sh = 0; sh < TS_N; ++sh) {
+    if (ms[sh] < 0.f) continue;
+    fprintf(f, "%s\"%s\": %.4f", first ? "" : ", ", tile_shape_name(sh), ms[sh]);
+    first = false;
+  }
+  fprintf(f, "}}\n");
+  fclose(f);
+}
+
 static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_options* o,
                              tc2_ctx** out) {
   tc2_ctx* ctx = nullptr;
@@ -258,6 +329,9 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
       if (!std::isfinite(o->mlp_weights[p])) return TC2_ENAN;
   }
   if (o->log_capacity < 0 || o->log_capacity > ((int64_t)1 << 31)) return TC2_EINVAL;
+  if (o->wide_accumulate < 0 || o->wide_accumulate > 1) return TC2_EINVAL;
+  if (o->wide_accumulate && o->numeric_kernel != 0) return TC2_EINVAL;
+  if (o->tune < 0 || o->tune > 1 || (o->tune && o->numeric_kernel != 0)) return TC2_EINVAL;
   if (o->numeric_kernel < 0 || o->numeric_kernel > 1) return TC2_EINVAL;
   if (o->precision == P_BF16 && o->numeric_kernel != 0) return TC2_EINVAL;
   if (o->fp64_first < 0 || o->fp64_first > TC2_MAX_ITER) return TC2_EINVAL;
@@ -295,10 +369,12 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TC2_EDEVICE;
   if (o->device < 0 || o->device >= ndev) return TC2_EDEVICE;
   if (hipSetDevice(o->device) != hipSuccess) return TC2_EDEVICE;
+  std::string arch;
   {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, o->device) != hipSuccess) return TC2_EDEVICE;
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TC2_EDEVICE;
+    arch.assign(prop.gcnArchName, strcspn(prop.gcnArchName, ":"));
   }
 
   ctx = new (std::nothrow) tc2_ctx();
@@ -318,6 +394,12 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   ctx->fp64_first = o->fp64_first;
   ctx->skip = o->skip;
   ctx->log_cap = o->log_capacity;
+  ctx->wide = o->wide_accumulate;
+  ctx->tune = o->tune;
+  if (o->tune_cache) ctx->tune_cache = o->tune_cache;
+  ctx->arch = arch;
+  for (int k = 0; k < 4; ++k) ctx->shape[k] = tile_shape_default(k, D);
+  if (ctx->tune) tune_load(ctx);
   if (const char* v = getenv("TC2_TEST_KL_CHUNK")) ctx->test_kl_chunk = std::max(0, atoi(v));
   if (const char* v = getenv("TC2_TEST_STAGE_CAP")) ctx->test_stage_cap = std::max(0LL, atoll(v));
   tc2_status st = TC2_OK;
@@ -587,7 +669,12 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[0], st));
   int n_work = 0;          // work items (atom path) or tile blocks (tiled path)
   long long out_bound = 0; // upper bound of computed output blocks
-  const int mult = tiled ? tile_split(ctx->cur_prec, D) : 1;
+  const int kind = ctx->cur_prec == P_FP64 ? K_FP64
+                   : (ctx->op_bf16 ? K_BF16 : (ctx->wide ? K_WIDE : K_FP32));
+  const int wide_now = kind == K_WIDE ? 1 : 0;
+  int mult = tiled ? tile_subs(ctx->shape[kind]) : 1;
+  if (tiled) ctx->kind_used[kind] = true;
+  ctx->last_kind = kind;
   if (!tiled) {
     // ---- atom-level symbolic product and work items
     HIPCHK(ctx->cand_cnt.reserve((size_t)nb * 4));
@@ -679,10 +766,9 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     n_work = ntiles;
     HIPCHK(ctx->sys_lo.reserve((size_t)ctx->nsys * 4));
     HIPCHK(ctx->sys_hi.reserve((size_t)ctx->nsys * 4));
-    launch_sys_items(st, ctx->nsys, mult, ctx->csys_start.as<int>(), ctx->csys_end.as<int>(),
-                     ctx->tile_rp.as<int>(), ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>());
   }
-  HIPCHK(ctx->partial.reserve((size_t)std::max((long long)n_work * mult, (long long)nb) * NQ * 8));
+  // room for the partial sums of any sub-tile shape (at most 4 per tile)
+  HIPCHK(ctx->partial.reserve((size_t)std::max((long long)n_work * (tiled ? 4 : 1), (long long)nb) * NQ * 8));
   if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[1], st));
 
   // ---- numeric (retried with a larger stage if it overflows).  The stage
@@ -714,6 +800,112 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     HIPCHK(hipMemcpyAsync(&log_before, ctx->log_count.p, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
   }
+  auto tile_args = [&](int cap, int shape) {
+    TileArgs ta{};
+    ta.D = D;
+    ta.ksteps = (ctx->b + 3) / 4;
+    ta.n_tiles = n_work;
+    ta.rp = ctx->rp[c].as<int>();
+    ta.ci = ctx->ci[c].as<int>();
+    ta.xv = ctx->xv[c].p;
+    ta.tile_p = ctx->tile_p.as<int>();
+    ta.tile_q = ctx->tile_q.as<int>();
+    ta.clus_atom = ctx->clus_atom.as<int>();
+    ta.clus_sys = ctx->clus_sys.as<int>();
+    ta.panel_rp = ctx->panel_rp.as<int>();
+    ta.panel_k = ctx->panel_k.as<int>();
+    ta.panel_e = ctx->panel_e.as<int>();
+    ta.branch = ctx->branch.as<int>();
+    ta.eps = ctx->eps.as<double>();
+    ta.h_rp = ctx->h_rp.as<int>();
+    ta.h_ci = ctx->h_ci.as<int>();
+    ta.h_v = ctx->h_v.as<double>();
+    for (int d = 0; d < D; ++d) {
+      ta.h1_rp[d] = ctx->h1_rp[d].as<int>();
+      ta.h1_ci[d] = ctx->h1_ci[d].as<int>();
+      ta.h1_v[d] = ctx->h1_v[d].as<double>();
+    }
+    ta.stage = ctx->stage.p;
+    ta.kept_ij = ctx->kept_ij.as<int2>();
+    ta.stage_count = cnt + 1;
+    ta.stage_cap = cap;
+    ta.shape = shape;
+    ta.overflow = cnt + 2;
+    ta.bad = ctx->bad.as<int>();
+    ta.partial = ctx->partial.as<double>();
+    ta.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
+    ta.bf16 = (ctx->op_bf16 && ctx->cur_prec == P_FP32) ? 1 : 0;
+    ta.wide = wide_now;
+    ta.skip = ctx->skip;
+    ta.bn = screen ? ctx->bn.as<float>() : nullptr;
+    ta.screened = screen ? ctx->screened.as<unsigned long long>() : nullptr;
+    ta.mlp_skipped = screen ? ctx->screened.as<unsigned long long>() + 1 : nullptr;
+    ta.mlp = ctx->skip == 2 ? ctx->mlp.as<float>() : nullptr;
+    ta.mlp_z = ctx->mlp_z;
+    ta.xyz = ctx->have_xyz ? ctx->xyz.as<double>() : nullptr;
+    ta.iter = ctx->update_index;
+    ta.log_cap = ctx->log_cap;
+    ta.log_x = ctx->log_cap > 0 ? ctx->log_x.as<float>() : nullptr;
+    ta.log_y = ctx->log_cap > 0 ? ctx->log_y.as<float>() : nullptr;
+    ta.log_count = ctx->log_cap > 0 ? ctx->log_count.as<unsigned long long>() : nullptr;
+    ta.kl_chunk = ctx->test_kl_chunk;
+    return ta;
+  };
+
+  // ---- autotuning of the sub-tile shape: once per kernel kind, at the first
+  // update past the peak of the candidate outputs (representative of the
+  // densest updates, which dominate the solve), every available shape runs
+  // this update's products twice (warm-up, then timed); the fastest is kept
+  // and appended to the cache file.  The products are recomputed below.
+  if (tiled && ctx->tune && !ctx->tuned[kind] && ctx->log_cap == 0 && n_work > 0 &&
+      ctx->prev_out_bound >= 0 && out_bound <= ctx->prev_out_bound) {
+    float ms_s[TS_N];
+    int best = ctx->shape[kind];
+    float best_ms = 3.0e38f;
+    const int cap = (int)std::min<long long>(std::max<long long>(ctx->stage_cap, 1), out_bound);
+    HIPCHK(ctx->stage.reserve((size_t)cap * tile));
+    HIPCHK(ctx->kept_ij.reserve((size_t)cap * 8));
+    hipEvent_t t0, t1;
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    for (int sh = 0; sh < TS_N; ++sh) {
+      ms_s[sh] = -1.f;
+      if (!tile_shape_available(kind, D, sh)) continue;
+      const TileArgs ta = tile_args(cap, sh);
+      for (int rep = 0; rep < 2; ++rep) {
+        launch_fill_int(st, cnt, 0, 4);
+        launch_fill_int(st, ctx->exec_pairs.as<int>(), 0, 2);
+        if (screen) launch_fill_int(st, ctx->screened.as<int>(), 0, 4);
+        HIPCHK(hipEventRecord(t0, st));
+        if (!launch_tile_numeric(st, ctx->cur_prec, ta)) return TC2_EINVAL;
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(t1, st));
+        HIPCHK(hipEventSynchronize(t1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+        ctx->ms_tune += ms;
+        ms_s[sh] = ms;
+      }
+      if (ms_s[sh] < best_ms) {
+        best_ms = ms_s[sh];
+        best = sh;
+      }
+      if (ctx->verbose)
+        fprintf(stderr, "tc2 tune %s: shape %s %.3f ms\n", tune_key(ctx, kind).c_str(),
+                tile_shape_name(sh), ms_s[sh]);
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    ctx->shape[kind] = best;
+    ctx->tuned[kind] = true;
+    tune_store(ctx, kind, ms_s);
+    mult = tile_subs(best);
+  }
+  ctx->prev_out_bound = out_bound;
+  if (tiled)
+    launch_sys_items(st, ctx->nsys, mult, ctx->csys_start.as<int>(), ctx->csys_end.as<int>(),
+                     ctx->tile_rp.as<int>(), ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>());
+
   unsigned long long pairs = 0;
   for (int attempt = 0;; ++attempt) {
     int cap = (int)std::min<long long>(std::max<long long>(ctx->stage_cap, 1), out_bound > 0 ? out_bound : 1);
@@ -758,54 +950,9 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       na.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
       launch_numeric(st, ctx->cur_prec, na);
     } else {
-      TileArgs ta{};
-      ta.D = D;
-      ta.ksteps = (ctx->b + 3) / 4;
-      ta.n_tiles = n_work;
-      ta.rp = ctx->rp[c].as<int>();
-      ta.ci = ctx->ci[c].as<int>();
-      ta.xv = ctx->xv[c].p;
-      ta.tile_p = ctx->tile_p.as<int>();
-      ta.tile_q = ctx->tile_q.as<int>();
-      ta.clus_atom = ctx->clus_atom.as<int>();
-      ta.clus_sys = ctx->clus_sys.as<int>();
-      ta.panel_rp = ctx->panel_rp.as<int>();
-      ta.panel_k = ctx->panel_k.as<int>();
-      ta.panel_e = ctx->panel_e.as<int>();
-      ta.branch = ctx->branch.as<int>();
-      ta.eps = ctx->eps.as<double>();
-      ta.h_rp = ctx->h_rp.as<int>();
-      ta.h_ci = ctx->h_ci.as<int>();
-      ta.h_v = ctx->h_v.as<double>();
-      for (int d = 0; d < D; ++d) {
-        ta.h1_rp[d] = ctx->h1_rp[d].as<int>();
-        ta.h1_ci[d] = ctx->h1_ci[d].as<int>();
-        ta.h1_v[d] = ctx->h1_v[d].as<double>();
-      }
-      ta.stage = ctx->stage.p;
-      ta.kept_ij = ctx->kept_ij.as<int2>();
-      ta.stage_count = cnt + 1;
-      ta.stage_cap = cap;
-      ta.overflow = cnt + 2;
-      ta.bad = ctx->bad.as<int>();
-      ta.partial = ctx->partial.as<double>();
-      ta.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
-      ta.bf16 = (ctx->op_bf16 && ctx->cur_prec == P_FP32) ? 1 : 0;
-      ta.skip = ctx->skip;
-      ta.bn = screen ? ctx->bn.as<float>() : nullptr;
-      ta.screened = screen ? ctx->screened.as<unsigned long long>() : nullptr;
-      ta.mlp_skipped = screen ? ctx->screened.as<unsigned long long>() + 1 : nullptr;
-      ta.mlp = ctx->skip == 2 ? ctx->mlp.as<float>() : nullptr;
-      ta.mlp_z = ctx->mlp_z;
-      ta.xyz = ctx->have_xyz ? ctx->xyz.as<double>() : nullptr;
-      ta.iter = ctx->update_index;
-      ta.log_cap = ctx->log_cap;
-      ta.log_x = ctx->log_cap > 0 ? ctx->log_x.as<float>() : nullptr;
-      ta.log_y = ctx->log_cap > 0 ? ctx->log_y.as<float>() : nullptr;
-      ta.log_count = ctx->log_cap > 0 ? ctx->log_count.as<unsigned long long>() : nullptr;
-      ta.kl_chunk = ctx->test_kl_chunk;
+      TileArgs ta = tile_args(cap, ctx->shape[kind]);
       if (screen) launch_fill_int(st, ctx->screened.as<int>(), 0, 4);
-      launch_tile_numeric(st, ctx->cur_prec, ta);
+      if (!launch_tile_numeric(st, ctx->cur_prec, ta)) return TC2_EINVAL;
     }
     HIPCHK(hipGetLastError());
     if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[3], st));
@@ -834,6 +981,8 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       HIPCHK(hipEventElapsedTime(&ms, ctx->pev[2], ctx->pev[3]));
       ctx->ms_num += ms;
       ctx->num_launches++;
+      ctx->ms_num_kind[kind] += ms;
+      ctx->launches_kind[kind]++;
     }
     if (!hcnt[2]) {
       n_kept = hcnt[1];
@@ -965,6 +1114,13 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
   const int nsys = ctx->nsys, D = ctx->D, b = ctx->b, nb = ctx->nb;
   std::vector<SysState> ss(nsys);
   ctx->ms_sym = ctx->ms_num = ctx->ms_cmp = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    ctx->ms_num_kind[k] = 0.0;
+    ctx->launches_kind[k] = 0;
+  }
+  ctx->ms_tune = 0.0;
+  ctx->prev_out_bound = -1;
+  for (bool& u : ctx->kind_used) u = false;
   ctx->screened_total = 0;
   ctx->mlp_total = 0;
   ctx->log_n = 0;
@@ -1094,6 +1250,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
       const double* q = &scal[(size_t)s * NQ];
       S.k++;
       S.trip += q[Q_TRIP];
+      S.trip_kind[ctx->last_kind] += q[Q_TRIP];
       double cur[1 + 2 * MAXD];
       energies(q, D, cur);
       const double iota = q[Q_TR0] - q[Q_FRO0];
@@ -1194,8 +1351,15 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
     strncpy(R.branches, ss[s].branches.c_str(), TC2_MAX_ITER + 3);
     R.ms_symbolic = ctx->ms_sym;
     R.ms_numeric = ctx->ms_num;
+    for (int k = 0; k < 4; ++k) {
+      R.useful_flops_kind[k] = ss[s].trip_kind[k] * b3 * (1 + 2 * D);
+      R.ms_numeric_kind[k] = ctx->ms_num_kind[k];
+      R.numeric_launches_kind[k] = ctx->launches_kind[k];
+    }
     R.ms_compact = ctx->ms_cmp;
     R.numeric_launches = ctx->num_launches;
+    for (int k = 0; k < 4; ++k) R.tile_shape[k] = ctx->kind_used[k] ? ctx->shape[k] : -1;
+    R.ms_tune = ctx->ms_tune;
     R.screened_blocks = (s == 0) ? (int64_t)ctx->screened_total : 0;
     R.mlp_skipped_blocks = (s == 0) ? (int64_t)ctx->mlp_total : 0;
     R.kept_blocks = final_rp[ctx->sys[s].row0 + ctx->sys[s].nb] - final_rp[ctx->sys[s].row0];

@@ -179,7 +179,10 @@ __global__ __launch_bounds__(256) void k_tiles(int pass, PanelArgs a) {
 // group g.
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <typename T, int D, int SP, int TQ, bool BF>
+// W (FP32 values only): the FP32 MFMA product of each column block K is added
+// to FP64 accumulators, so that only the short sum inside one block runs in
+// FP32 and the long sum over K runs in FP64.
+template <typename T, int D, int SP, int TQ, bool BF, bool W>
 __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
   constexpr int PER = (1 + D) * BS;                       // elements per entry
   constexpr int EB = PER * (int)sizeof(T);                // bytes per entry
@@ -233,12 +236,16 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
 
   const T* X = (const T*)a.xv;
   Acc<T> acc[NO][1 + D];
+  AccW wacc[W ? NO : 1][W ? 1 + D : 1];
 #pragma unroll
   for (int o = 0; o < NO; ++o)
 #pragma unroll
     for (int m = 0; m <= D; ++m)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[o][m].v[r] = 0;
+      for (int r = 0; r < 4; ++r) {
+        acc[o][m].v[r] = 0;
+        if constexpr (W) wacc[o][m].v[r] = 0.0;
+      }
   int np[NO];
 #pragma unroll
   for (int o = 0; o < NO; ++o) np[o] = 0;
@@ -246,19 +253,29 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
   const int pp0 = a.panel_rp[P], pp1 = a.panel_rp[P + 1];
   const int pq0 = a.panel_rp[Q], nq = a.panel_rp[Q + 1] - pq0;
 
-  // copy the blocks of column group g (KG columns) into buffer bb
-  auto issue = [&](int g, int nm, int bb) {
+  // Entries of column group g (KG columns x NE blocks), one per lane: lane
+  // gi*NE + x holds the entry of block x of column g*KG + gi, or -1.  Loaded
+  // one group ahead, so that issuing the copies never waits on this load.
+  static_assert(KG * NE <= 64, "entries of a column group exceed one wave");
+  auto load_entries = [&](int g, int nm) {
+    int e = -1;
+    if (lane < KG * NE) {
+      const int gi = lane / NE, x = lane - gi * NE;
+      const int m = g * KG + gi;
+      if (m < nm) {
+        const int2 pq = kl[m];
+        e = (x < SP) ? a.panel_e[(size_t)pq.x * CS + ph * SP + x]
+                     : a.panel_e[(size_t)pq.y * CS + qh * TQ + (x - SP)];
+      }
+    }
+    return e;
+  };
+  // copy the blocks of a column group (entries eg, as load_entries) into buffer bb
+  auto issue = [&](int eg, int bb) {
 #pragma unroll
     for (int gi = 0; gi < KG; ++gi) {
-      const int m = g * KG + gi;
       for (int x = wave; x < NE; x += NW) {
-        int e = -1;
-        if (m < nm) {
-          const int2 pq = kl[m];
-          e = (x < SP) ? a.panel_e[(size_t)pq.x * CS + ph * SP + x]
-                       : a.panel_e[(size_t)pq.y * CS + qh * TQ + (x - SP)];
-        }
-        e = __builtin_amdgcn_readfirstlane(e);
+        const int e = __builtin_amdgcn_readlane(eg, gi * NE + x);
         if (lane == 0) sflag[bb][gi][x] = e;
         if (e >= 0) {
           const char* src = (const char*)(X + (size_t)e * PER) + lane * 16;
@@ -477,12 +494,19 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
     const int nm = (single_chunk && nm_kept >= 0) ? nm_kept : build_kl(base, end);
     // ---- pipelined products over the common columns
     const int ngroups = (nm + KG - 1) / KG;
-    if (ngroups > 0) issue(0, nm, 0);
+    int e_next = 0;
+    if (ngroups > 0) {
+      issue(load_entries(0, nm), 0);
+      e_next = load_entries(1, nm);
+    }
     for (int g = 0; g < ngroups; ++g) {
       const int bb = g & 1;
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
-      if (g + 1 < ngroups) issue(g + 1, nm, bb ^ 1);
+      if (g + 1 < ngroups) {
+        issue(e_next, bb ^ 1);
+        e_next = load_entries(g + 2, nm);
+      }
       if (any_owned) {
 #pragma unroll
         for (int gi = 0; gi < KG; ++gi) {
@@ -497,7 +521,7 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
           // blocks read stale data that no MFMA consumes); the two updates of
           // each response accumulator are issued in separate passes so that
           // dependent MFMAs are not back to back.
-          constexpr int HALF = ((sizeof(T) == 8 || BF) && D >= 2) ? 2 : 4;
+          constexpr int HALF = ((sizeof(T) == 8 || BF || W) && D >= 2) ? 2 : 4;
           if constexpr (BF) {
             // bfloat16 operands: one 16x16x16 MFMA per block product
 #pragma unroll
@@ -564,6 +588,20 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
                   if (pres[h + u]) mfma(acc[h + u][1 + d], A1[u][d], B0[u]);
             }
           }
+          if constexpr (W) {
+            // column block K done: its FP32 products join the FP64 sums
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+              if (!pres[o]) continue;
+#pragma unroll
+              for (int m = 0; m <= D; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  wacc[o][m].v[r] += (double)acc[o][m].v[r];
+                  acc[o][m].v[r] = 0.f;
+                }
+            }
+          }
         }
       }
     }
@@ -586,7 +624,10 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
     bool kept = false;
     if (np[o] > 0) {
       issued += np[o];
-      kept = epilogue<T, D>(E, acc[o], Io[o], Jo[o], eIJ, square, eps, np[o], sys, q);
+      if constexpr (W)
+        kept = epilogue<T, D, AccW>(E, wacc[o], Io[o], Jo[o], eIJ, square, eps, np[o], sys, q);
+      else
+        kept = epilogue<T, D>(E, acc[o], Io[o], Jo[o], eIJ, square, eps, np[o], sys, q);
     }
     if (slot >= 0 && lane == 0) a.log_y[slot] = kept ? 0.f : 1.f;  // label: dropped
   }
@@ -685,46 +726,87 @@ void launch_tiles(hipStream_t st, int pass, const PanelArgs& a) {
   hipLaunchKernelGGL(k_tiles, dim3(a.nc), dim3(256), lds, st, pass, a);
 }
 
-// Sub-tile shape per precision and direction count: the accumulators of a
-// wave (TQ outputs x (1+D) tiles) stay within the 256-register budget and one
-// LDS buffer stays within 64 KB.
-template <typename T, int D> struct Shape {
-  static constexpr int SP = (sizeof(T) == 8 && D >= 2) ? 4 : 8;
-  static constexpr int TQ = (sizeof(T) == 8 && D >= 2) ? 4 : 8;
-};
+// Sub-tile shapes (rows of cluster P x columns of cluster Q per workgroup).
+// Which ones exist depends on the kernel kind and D: the accumulators of a
+// wave ((1 + D) tiles per owned output) must stay within its register budget.
+constexpr int SHAPE_SP[TS_N] = {8, 4, 8, 4};
+constexpr int SHAPE_TQ[TS_N] = {8, 8, 4, 4};
 
-int tile_split(int prec, int D) {
-  if (prec == P_FP64 && D >= 2) return (CS / 4) * (CS / 4);
-  return 1;
+constexpr bool shape_ok(int kind, int D, int s) {
+  return ((kind == K_FP64 || kind == K_WIDE) && D >= 2)
+             ? s == TS_4x4
+             : (s == TS_8x8 || ((D == 1 || D == 3) && s == TS_4x8) ||
+                (D == 1 && kind != K_BF16 && s == TS_8x4));
+}
+
+bool tile_shape_available(int kind, int D, int shape) {
+  return kind >= 0 && kind < 4 && D >= 0 && D <= MAXD && shape >= 0 && shape < TS_N &&
+         shape_ok(kind, D, shape);
+}
+
+int tile_shape_default(int kind, int D) {
+  return ((kind == K_FP64 || kind == K_WIDE) && D >= 2) ? TS_4x4 : TS_8x8;
+}
+
+int tile_subs(int shape) { return (CS / SHAPE_SP[shape]) * (CS / SHAPE_TQ[shape]); }
+
+const char* tile_shape_name(int shape) {
+  static const char* names[TS_N] = {"8x8", "4x8", "8x4", "4x4"};
+  return (shape >= 0 && shape < TS_N) ? names[shape] : "?";
+}
+
+template <typename T, int D, bool BF, bool W, int S>
+static void tile_go(hipStream_t st, const TileArgs& a) {
+  constexpr int SP = SHAPE_SP[S], TQ = SHAPE_TQ[S];
+  const unsigned G = (unsigned)a.n_tiles * (unsigned)((CS / SP) * (CS / TQ));
+  hipLaunchKernelGGL((k_tile_numeric<T, D, SP, TQ, BF, W>), dim3(G), dim3(TQ * 64), 0, st, a);
+}
+
+// false when the shape does not exist for this kind
+template <typename T, int D, bool BF, bool W>
+static bool tile_shape_go(hipStream_t st, const TileArgs& a) {
+  constexpr int KIND = sizeof(T) == 8 ? K_FP64 : (BF ? K_BF16 : (W ? K_WIDE : K_FP32));
+  switch (a.shape) {
+    case TS_8x8:
+      if constexpr (shape_ok(KIND, D, TS_8x8)) { tile_go<T, D, BF, W, TS_8x8>(st, a); return true; }
+      break;
+    case TS_4x8:
+      if constexpr (shape_ok(KIND, D, TS_4x8)) { tile_go<T, D, BF, W, TS_4x8>(st, a); return true; }
+      break;
+    case TS_8x4:
+      if constexpr (shape_ok(KIND, D, TS_8x4)) { tile_go<T, D, BF, W, TS_8x4>(st, a); return true; }
+      break;
+    case TS_4x4:
+      if constexpr (shape_ok(KIND, D, TS_4x4)) { tile_go<T, D, BF, W, TS_4x4>(st, a); return true; }
+      break;
+    default: break;
+  }
+  return false;
 }
 
 template <typename T, int D>
-static void tile_launch(hipStream_t st, const TileArgs& a) {
-  constexpr int SP = Shape<T, D>::SP, TQ = Shape<T, D>::TQ;
-  const unsigned G = (unsigned)a.n_tiles * (unsigned)((CS / SP) * (CS / TQ));
+static bool tile_launch(hipStream_t st, const TileArgs& a) {
   if constexpr (sizeof(T) == 4) {
-    if (a.bf16) {
-      hipLaunchKernelGGL((k_tile_numeric<T, D, SP, TQ, true>), dim3(G), dim3(TQ * 64), 0, st, a);
-      return;
-    }
+    if (a.bf16) return tile_shape_go<T, D, true, false>(st, a);
+    if (a.wide) return tile_shape_go<T, D, false, true>(st, a);
   }
-  hipLaunchKernelGGL((k_tile_numeric<T, D, SP, TQ, false>), dim3(G), dim3(TQ * 64), 0, st, a);
+  return tile_shape_go<T, D, false, false>(st, a);
 }
 
 template <typename T>
-static void tile_d(hipStream_t st, const TileArgs& a) {
+static bool tile_d(hipStream_t st, const TileArgs& a) {
   switch (a.D) {
-    case 0: tile_launch<T, 0>(st, a); break;
-    case 1: tile_launch<T, 1>(st, a); break;
-    case 2: tile_launch<T, 2>(st, a); break;
-    default: tile_launch<T, 3>(st, a); break;
+    case 0: return tile_launch<T, 0>(st, a);
+    case 1: return tile_launch<T, 1>(st, a);
+    case 2: return tile_launch<T, 2>(st, a);
+    default: return tile_launch<T, 3>(st, a);
   }
 }
 
-void launch_tile_numeric(hipStream_t st, int prec, const TileArgs& a) {
-  if (a.n_tiles == 0) return;
-  if (prec == P_FP64) tile_d<double>(st, a);
-  else tile_d<float>(st, a);
+bool launch_tile_numeric(hipStream_t st, int prec, const TileArgs& a) {
+  if (a.n_tiles == 0) return true;
+  if (prec == P_FP64) return tile_d<double>(st, a);
+  return tile_d<float>(st, a);
 }
 
 void launch_copy_through(hipStream_t st, int prec, const CopyArgs& a, int nnz) {

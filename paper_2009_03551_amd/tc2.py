@@ -43,7 +43,8 @@ class tc2_options(C.Structure):
                 ("device", C.c_int32), ("export_matrices", C.c_int32), ("verbose", C.c_int32),
                 ("profile", C.c_int32), ("numeric_kernel", C.c_int32),
                 ("fp64_first", C.c_int32), ("mlp_weights", C.POINTER(C.c_float)),
-                ("mlp_threshold", C.c_float), ("log_capacity", C.c_int64)]
+                ("mlp_threshold", C.c_float), ("log_capacity", C.c_int64),
+                ("wide_accumulate", C.c_int32), ("tune", C.c_int32), ("tune_cache", C.c_char_p)]
 
 
 class tc2_result(C.Structure):
@@ -55,6 +56,9 @@ class tc2_result(C.Structure):
                 ("screened_blocks", C.c_int64), ("mlp_skipped_blocks", C.c_int64),
                 ("ms_symbolic", C.c_double), ("ms_numeric", C.c_double),
                 ("ms_compact", C.c_double), ("numeric_launches", C.c_int32),
+                ("tile_shape", C.c_int32 * 4), ("ms_tune", C.c_double),
+                ("useful_flops_kind", C.c_double * 4), ("ms_numeric_kind", C.c_double * 4),
+                ("numeric_launches_kind", C.c_int32 * 4),
                 ("branches", C.c_char * (TC2_MAX_ITER + 4)),
                 ("X0", tc2_bsr), ("X1", tc2_bsr * 3)]
 
@@ -180,6 +184,11 @@ class Result:
     ms_numeric: float = 0.0
     ms_compact: float = 0.0
     numeric_launches: int = 0
+    tile_shape: List[int] = field(default_factory=list)
+    ms_tune: float = 0.0
+    useful_flops_kind: List[float] = field(default_factory=list)
+    ms_numeric_kind: List[float] = field(default_factory=list)
+    numeric_launches_kind: List[int] = field(default_factory=list)
     X0: Optional[BSR] = None
     X1: List[BSR] = field(default_factory=list)
 
@@ -215,7 +224,8 @@ class Solver:
                  replay: Optional[Sequence[Optional[str]]] = None, verbose: bool = False,
                  profile: bool = False, kernel: str = "tile", use_xyz: bool = True,
                  fp64_first: int = 0, skip: str = "none", mlp_weights=None,
-                 mlp_threshold: float = 0.99, log_capacity: int = 0):
+                 mlp_threshold: float = 0.99, log_capacity: int = 0, wide: bool = False,
+                 tune: bool = False, tune_cache: Optional[str] = None):
         if isinstance(systems, System):
             systems = [systems]
         self.systems = list(systems)
@@ -252,7 +262,8 @@ class Solver:
         opts = tc2_options(PRECISION[precision], int(closing_fp64), SKIP[skip], int(device),
                            1 if export else 0, 1 if verbose else 0, 1 if profile else 0,
                            KERNEL[kernel], int(fp64_first), wptr, float(mlp_threshold),
-                           int(log_capacity))
+                           int(log_capacity), 1 if wide else 0, 1 if tune else 0,
+                           tune_cache.encode() if tune_cache else None)
         self.log_capacity = int(log_capacity)
         self._ctx = C.c_void_p()
         st = lib().tc2_setup(probs, n, C.byref(opts), C.byref(self._ctx))
@@ -275,7 +286,9 @@ class Solver:
                               r.emin, r.emax, r.seconds, r.useful_flops, r.executed_flops,
                               r.kept_blocks, r.screened_blocks, r.mlp_skipped_blocks,
                               r.ms_symbolic, r.ms_numeric, r.ms_compact,
-                              r.numeric_launches, x0, x1))
+                              r.numeric_launches, list(r.tile_shape), r.ms_tune,
+                              list(r.useful_flops_kind), list(r.ms_numeric_kind),
+                              list(r.numeric_launches_kind), x0, x1))
         return out
 
     def log(self):

@@ -16,7 +16,7 @@ and molecules, Sec. 3, which are not available):
   block with entries U(-amp, amp) * exp(-r / decay) is drawn (pairs in
   row-major (I, J) order, entries row-major), and H_JI = H_IJ^T;
 * H1_d = blockdiag((x_{I,d} - mean_d) * 1_b), the position operator of the
-  homogeneous field (Sec. 2.1) in the point-atom approximation, centred.
+  homogeneous field (Sec. 2) in the point-atom approximation, centred.
 
 Random numbers come from ``numpy.random.default_rng(seed)`` (PCG64).
 """

@@ -112,6 +112,8 @@ def test_rejects_mismatched_batch():
 def test_rejects_bad_options():
     assert _setup_status(small(), closing_fp64=1) == -1
     assert _setup_status(small(), replay=["SX"]) == -1
+    # FP64 sums of the per-block FP32 products exist in the tiled kernel only
+    assert _setup_status(small(), precision="fp32", wide=True, kernel="block") == -1
 
 
 def test_valid_problem_needs_a_device():

@@ -69,6 +69,20 @@ def test_cube10_fp32_against_oracle():
     assert dx1 < 5e-6 and dal < 1e-5
 
 
+def test_cube10_fp32_wide_meets_gate():
+    # FP32 products, FP64 sums over the column blocks, 8 leading FP64 updates,
+    # closing pair: the reduced-precision gate (max|dX1| < 1e-6, rel|dalpha| < 1e-6)
+    g0 = golden("cube10")
+    s = W.config_system("cube10")
+    r = T.solve(s, precision="fp32", closing_fp64=2, fp64_first=8, wide=True, skip="bound")[0]
+    dal = abs(r.alpha[0] - g0["alpha"][0]) / abs(g0["alpha"][0])
+    dx1 = max(np.abs(block(r.X1[0], b["I"], b["J"]) - np.array(b["X1"][0])).max() for b in g0["blocks"])
+    print(f"  fp32 wide (8 leading FP64 updates, closing pair, exact screen): sampled "
+          f"max|dX1|={dx1:.2e} rel|dalpha|={dal:.2e} {r.seconds:.3f}s", flush=True)
+    assert abs(r.tr_x0 - s.n_occ) < 1e-6
+    assert dx1 < 1e-6 and dal < 1e-6
+
+
 def test_cube20_invariants_three_directions():
     s = W.config_system("cube20")
     r = T.solve(s, export=False, skip="bound")[0]

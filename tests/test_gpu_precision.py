@@ -35,6 +35,30 @@ def test_fp32_closing_pair(fp64_first):
     assert dx1 < 1e-5 and dal < 1e-5
 
 
+@pytest.mark.parametrize("fp64_first", [0, 8])
+def test_fp32_wide_accumulation(fp64_first):
+    # FP32 block products with FP64 sums over the column blocks: the long
+    # FP32 sum was the dominant error of the FP32 stage
+    s = W.config_system("cube10", L=4)
+    o = O.solve_system(s)
+    g = T.solve(s, precision="fp32", closing_fp64=2, fp64_first=fp64_first, wide=True)[0]
+    n = T.solve(s, precision="fp32", closing_fp64=2, fp64_first=fp64_first)[0]
+    dx1, dal = errors(s, g, o)
+    dx1n, daln = errors(s, n, o)
+    assert g.status >= 0 and g.branches[-1] != g.branches[-2]
+    assert abs(g.tr_x0 - s.n_occ) < 1e-6 and abs(g.idem_err) < 1e-6
+    assert dal <= daln
+    assert dx1 < 1e-6 and dal < (1e-6 if fp64_first else 2e-6)
+
+
+def test_fp32_wide_three_directions():
+    s = W.config_system("cube20", L=3)
+    o = O.solve_system(s)
+    g = T.solve(s, precision="fp32", closing_fp64=2, fp64_first=8, wide=True)[0]
+    dx1, dal = errors(s, g, o)
+    assert dx1 < 1e-6 and dal < 1e-6
+
+
 def test_fp32_without_closing_is_worse():
     s = W.config_system("cube10", L=4)
     a = T.solve(s, precision="fp32", closing_fp64=2)[0]

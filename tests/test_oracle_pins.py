@@ -250,7 +250,7 @@ def test_atom_permutation():
 
 
 def test_filter_error_grows_with_eps():
-    # the filter error grows roughly linearly with the threshold (Sec. 2.4)
+    # the filter error grows roughly linearly with the threshold (Sec. 2.3)
     s = W.config_system("chain64", n=32)
     H, H1 = dense(s.H), dense(s.H1[0])
     P1 = E.exact_response(H, H1, s.n_occ)
