@@ -1,9 +1,9 @@
 """Closed-form limits of TC2 and TC2-CPSCF (test infrastructure).
 
 Without truncation the TC2 iterates converge to the projector onto the
-N_occ lowest eigenvectors of H (Sec. 2.3: the density matrix as a sum over
+N_occ lowest eigenvectors of H (Sec. 2.2: the density matrix as a sum over
 occupied states) and the response iterates to its derivative, which the
-O(N^3) route of Sec. 2.2 writes with the expansion C1 = C0 U1,
+O(N^3) route of Sec. 2.1 writes with the expansion C1 = C0 U1,
 U1_pq = -(C0^T H1 C0)_pq / (e_p - e_q), U1_pp = 0 (Eq. cpscf-LCAO), and
 P1 = sum_i f_i (C1_i C0_i^T + C0_i C1_i^T) with f_i = 1 in the orthonormal,
 spin-free notation used by TC2.

@@ -3,7 +3,7 @@
 Plain, slow and literal: every matrix is dense, every product is a numpy
 matmul, every step follows the paper (Shang et al., "Efficient parallel
 linear scaling method to get the response density matrix in all-electron
-real-space DFPT", Sec. 2.3 "The O(N) method to get the first order density
+real-space DFPT", Sec. 2.2 "The O(N) method to get the first order density
 matrix").  Nothing here is blocked, fused or reordered beyond what the paper
 states.  The GPU library shares no code with this file.
 
@@ -13,12 +13,12 @@ library, which implements them independently):
 * spectral bounds: Gershgorin discs of the scalar rows of the full H, FP64;
 * branch: SQUARE when Tr X0 >= N_occ (ties go to SQUARE); the response
   uses the same branch as X0;
-* filter ("NTPoly-filter", Sec. 2.4): applied after each update, per atom
+* filter ("NTPoly-filter", Sec. 2.3): applied after each update, per atom
   block, by Frobenius norm: an off-diagonal block (I, J), I < J, whose norm is
   strictly below ``eps`` is zeroed together with its mirror (J, I); each of
   X0 and X1_d is filtered on its own; diagonal blocks are never filtered;
   the initial matrices are not filtered;
-* stopping ("NTPoly-tolerance", Sec. 2.4; band energies of Sec. 2.3):
+* stopping ("NTPoly-tolerance", Sec. 2.3; band energies of Sec. 2.2):
   after k >= 2 updates, stop when the change of E0 = Tr(X0 H), of every
   E1_d = Tr(X1_d H) and of every alpha_d = Tr(X1_d H1_d) is below ``tol``;
 * stall guard: once |iota| < 1, with iota = Tr X0 - ||X0||_F^2, stop when
@@ -56,7 +56,7 @@ def bsr_to_dense(nb: int, b: int, row_ptr, col, val) -> np.ndarray:
 
 
 def gershgorin(H: np.ndarray):
-    """Spectral bounds of H by Gershgorin's circle theorem (Sec. 2.3, used for
+    """Spectral bounds of H by Gershgorin's circle theorem (Sec. 2.2, used for
     the TC2 initial guess): each eigenvalue lies in some disc centred at
     H_ii with radius sum_{j != i} |H_ij|."""
     d = np.diag(H)
@@ -65,7 +65,7 @@ def gershgorin(H: np.ndarray):
 
 
 def tc2_init(H: np.ndarray, H1s: Sequence[np.ndarray], emin: float, emax: float):
-    """Initial matrices of the TC2 recursion and of its response (Sec. 2.3):
+    """Initial matrices of the TC2 recursion and of its response (Sec. 2.2):
     X0 = (emax*I - H) / (emax - emin) and X1 = -H1 / (emax - emin)."""
     W = emax - emin
     n = H.shape[0]
@@ -104,7 +104,7 @@ def tc2_step(X0: np.ndarray, X1s: Sequence[np.ndarray], square: bool):
 
 
 def band_energies(X0, X1s, H, H1s):
-    """E0 = Tr(X0 H) and E1_d = Tr(X1_d H) (band energies of Sec. 2.3), and
+    """E0 = Tr(X0 H) and E1_d = Tr(X1_d H) (band energies of Sec. 2.2), and
     alpha_d = Tr(X1_d H1_d), the raw polarizability trace."""
     E0 = float(np.sum(X0 * H.T))
     E1 = [float(np.sum(X1 * H.T)) for X1 in X1s]
@@ -133,7 +133,7 @@ def tc2_solve(H: np.ndarray, H1s: Sequence[np.ndarray], n_occ: int, b: int,
               eps: float, tol: float, max_iter: int = 100,
               replay: Optional[str] = None, closing_pair: bool = False,
               stall_guard: bool = True, keep_history: bool = False) -> OracleResult:
-    """TC2 purification of X0 coupled with its response X1 (Sec. 2.3), in
+    """TC2 purification of X0 coupled with its response X1 (Sec. 2.2), in
     dense FP64, with the block filter and the band-energy stopping test.
 
     ``replay`` forces the branch of every update ('S'/'D' per step) and runs
