@@ -30,15 +30,16 @@ HBM_PEAK_GBS = 8000.0
 SHAPES = ((8, 8), (4, 8), (8, 4), (4, 4))   # sub-tile shape id -> (rows, columns)
 
 
-def kernel_name(kernel: str, kind: int, D: int, shape: int) -> str:
+def kernel_name(kernel: str, kind: int, D: int, shape: int, b: int) -> str:
     """Template instance of the numeric kernel of one kind (FP64, FP32, BF16
     operands, FP32 with FP64 sums), as rocprofv3 names it."""
     T = "double" if kind == 0 else "float"
     if kernel == "block":
         return f"k_numeric<{T}, {D}>"
     sp, tq = SHAPES[max(shape, 0)]
-    return (f"k_tile_numeric<{T}, {D}, {sp}, {tq}, {'true' if kind == 2 else 'false'}, "
-            f"{'true' if kind == 3 else 'false'}>")
+    full_k = b > 12 and kind != 2
+    tf = lambda v: "true" if v else "false"
+    return f"k_tile_numeric<{T}, {D}, {sp}, {tq}, {tf(kind == 2)}, {tf(kind == 3)}, {tf(full_k)}>"
 
 KERNEL_SOURCES = ("paper_2009_03551_amd/csrc/tc2_tile.hip", "paper_2009_03551_amd/csrc/tc2_device.h",
                   "paper_2009_03551_amd/csrc/tc2_internal.h", "paper_2009_03551_amd/csrc/tc2_kernels.hip")
@@ -138,16 +139,24 @@ def main() -> int:
     ap.add_argument("--workload", default="cube10")
     # default: the fastest variant that passes the gate on this workload (FP32
     # block products summed in FP64 over the column blocks, 4 leading FP64
-    # updates, exact screen, closing FP64 pair)
+    # updates, exact screen, closing FP64 pair, updates as captured graphs)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--kernel", default="tile", choices=["tile", "block"])
-    ap.add_argument("--skip", default="bound", choices=["none", "bound"])
+    ap.add_argument("--skip", default="bound", choices=["none", "bound", "mlp"],
+                    help="mlp: train the skip network first on logged solves of smaller "
+                         "cubes (seeds 500+L, same drop threshold), then skip with it")
+    ap.add_argument("--mlp-threshold", type=float, default=0.995)
     ap.add_argument("--fp64-first", type=int, default=4)
     ap.add_argument("--wide", type=int, default=1, choices=[0, 1],
                     help="FP32 stages: FP64 sums of the per-block FP32 products")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the sub-tile shapes (timed in the warm-up solve)")
     ap.add_argument("--tune-cache", default=None, help="tuned-shape cache file (read and appended)")
+    ap.add_argument("--graph", type=int, default=1, choices=[0, 1],
+                    help="run each update as one captured hipGraph with a persistent "
+                         "numeric launch (tiled kernel)")
+    ap.add_argument("--group-atoms", type=int, default=16000,
+                    help="batch workloads: most atoms per context")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=1)
     ap.add_argument("--no-reference", action="store_true",
@@ -173,71 +182,142 @@ def main() -> int:
         return copy_calibration(args.copy_calibration, 10)
     stream = torch.cuda.current_stream().cuda_stream
 
-    sysm = W.config_system(args.workload)
-    log(f"workload {args.workload}: atoms={sysm.H.nb} b={sysm.H.b} N={sysm.H.n} "
-        f"nnzb(H)={sysm.H.nnzb} dirs={len(sysm.H1)} eps={sysm.eps} tol={sysm.tol}")
+    # workload -> units: lists of systems solved in one context (one merged
+    # launch per update).  A batch is packed into units of at most
+    # --group-atoms atoms so that each unit's iterates fit in HBM.
+    if args.workload.startswith("batch"):
+        n_sys = int(args.workload[5:] or 32)
+        systems = W.batch_systems(n_sys=n_sys)
+        units, cur, acc = [], [], 0
+        for sy in systems:
+            if cur and acc + sy.H.nb > args.group_atoms:
+                units.append(cur)
+                cur, acc = [], 0
+            cur.append(sy)
+            acc += sy.H.nb
+        units.append(cur)
+    else:
+        systems = [W.config_system(args.workload)]
+        units = [systems]
+    sysm = systems[0]
+    n_atoms = sum(sy.H.nb for sy in systems)
+    log(f"workload {args.workload}: {len(systems)} system(s) in {len(units)} unit(s), atoms="
+        f"{n_atoms} b={sysm.H.b} N={sum(sy.H.n for sy in systems)} dirs={len(sysm.H1)} "
+        f"eps={sysm.eps} tol={sysm.tol}")
 
-    def timed(solver):
-        for _ in range(args.warmup):
-            solver.run(stream=stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = [solver.run(stream=stream)[0] for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        return res, (time.perf_counter() - t0) / args.steps * 1e3
+    def timed(kw):
+        """Seconds per solve of all units (each unit: warm-up, then timed solves)
+        and the results of the last timed solve of every system."""
+        total_ms, last, per = 0.0, [], []
+        for u in units:
+            solver = T.Solver(u, **kw)
+            for _ in range(args.warmup):
+                solver.run(stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = [solver.run(stream=stream) for _ in range(args.steps)]
+            torch.cuda.synchronize()
+            total_ms += (time.perf_counter() - t0) / args.steps * 1e3
+            solver.close()
+            last += res[-1]
+            per.append(res)
+        return total_ms, last, per
 
+    def exported(kw):
+        out = []
+        for u in units:
+            out += T.solve(u, export=True, **kw)
+        return out
+
+    def bsr_maxdiff(a, b):
+        """max |A - B| over the union of two block patterns (no dense copy)."""
+        ra = np.repeat(np.arange(a.nb, dtype=np.int64), np.diff(a.row_ptr))
+        rb = np.repeat(np.arange(b.nb, dtype=np.int64), np.diff(b.row_ptr))
+        ka, kb = ra * a.nb + a.col, rb * b.nb + b.col
+        _, ia, ib = np.intersect1d(ka, kb, assume_unique=True, return_indices=True)
+        d = float(np.abs(a.val[ia] - b.val[ib]).max()) if len(ia) else 0.0
+        oa = np.setdiff1d(np.arange(len(ka)), ia, assume_unique=True)
+        ob = np.setdiff1d(np.arange(len(kb)), ib, assume_unique=True)
+        if len(oa):
+            d = max(d, float(np.abs(a.val[oa]).max()))
+        if len(ob):
+            d = max(d, float(np.abs(b.val[ob]).max()))
+        return d
+
+    tile_kw = (dict(tune=args.tune, tune_cache=args.tune_cache, graph=bool(args.graph))
+               if args.kernel == "tile" else {})
     # plain FP64 path (every candidate block computed): reference for the gate
     # and the speed-up, timed the same way as the chosen variant
-    ref = None
+    refs = None
     if not args.no_reference:
-        tune = dict(tune=args.tune, tune_cache=args.tune_cache) if args.kernel == "tile" else {}
-        ref_solver = T.Solver(sysm, precision="fp64", export=True, kernel=args.kernel, **tune)
-        ref = ref_solver.run(stream=stream)[0]
-        ref_solver.close()
-        plain_solver = T.Solver(sysm, precision="fp64", export=False, kernel=args.kernel, **tune)
-        _, ref_ms = timed(plain_solver)
-        plain_solver.close()
-        log(f"plain fp64: {ref.status_name} iters={ref.iters} {ref.branches} "
-            f"alpha={ref.alpha} kept={ref.kept_blocks} {ref_ms:.1f} ms/solve")
+        refs = exported(dict(precision="fp64", kernel=args.kernel, **tile_kw))
+        ref_ms, ref_last, _ = timed(dict(precision="fp64", export=False, kernel=args.kernel,
+                                         **tile_kw))
+        ref_useful = sum(x.useful_flops for x in ref_last)
+        log(f"plain fp64: {refs[0].status_name} iters={refs[0].iters} {refs[0].branches} "
+            f"alpha={refs[0].alpha} kept={sum(x.kept_blocks for x in refs)} {ref_ms:.1f} ms/solve")
 
     chosen = args.precision
     closing = 0 if chosen == "fp64" else 2
+    if args.skip == "mlp":
+        from paper_2009_03551_amd import skipnet
+        train_sys = [W.config_system("cube10", L=L, seed=500 + L, eps=sysm.eps, n_dir=len(sysm.H1))
+                     for L in (5, 6, 7)]
+        t0 = time.perf_counter()
+        x, y = skipnet.collect(train_sys)
+        theta, losses = skipnet.train(x, y, epochs=25)
+        log(f"skip network: {len(y)} logged candidates ({y.mean():.3f} dropped), loss "
+            f"{losses[0]:.4f} -> {losses[-1]:.4f}, {time.perf_counter() - t0:.1f} s")
     variant = dict(precision=chosen, closing_fp64=closing, kernel=args.kernel, skip=args.skip,
                    fp64_first=args.fp64_first if chosen != "fp64" else 0,
                    wide=bool(args.wide and chosen != "fp64"))
-    if args.tune and args.kernel == "tile":
-        variant.update(tune=True, tune_cache=args.tune_cache)
-    solver = T.Solver(sysm, export=False, profile=True, **variant)
-    results, ms_per_step = timed(solver)
-    r = results[-1]
-    value = r.useful_flops / (ms_per_step * 1e-3) / 1e9
-    ms_num = sum(x.ms_numeric for x in results) / len(results)
-    launches = results[-1].numeric_launches
+    if args.kernel == "tile":
+        variant.update(tile_kw)
+    if args.skip == "mlp":
+        variant.update(mlp_weights=theta, mlp_threshold=args.mlp_threshold)
+    ms_per_step, last, per = timed(dict(export=False, profile=True, **variant))
+    r = last[0]
+    useful = sum(x.useful_flops for x in last)
+    executed = sum(x.executed_flops for x in last)
+    value = useful / (ms_per_step * 1e-3) / 1e9
+    # numeric-kernel times per solve, summed over the units (the library
+    # times a context's launches once, on its first system's result)
+    ms_num = sum(sum(x[0].ms_numeric for x in res) / len(res) for res in per)
+    launches = sum(res[-1][0].numeric_launches for res in per)
     # roofline of the dominant kernel: the numeric kernel kind (FP64, FP32,
     # BF16 operands, FP32 with FP64 sums) that takes most of the numeric time
-    nk = len(results)
-    ms_kind = [sum(x.ms_numeric_kind[k] for x in results) / nk for k in range(4)]
+    ms_kind = [sum(sum(x[0].ms_numeric_kind[k] for x in res) / len(res) for res in per)
+               for k in range(4)]
     dom = max(range(4), key=lambda k: ms_kind[k])
-    dom_launches = results[-1].numeric_launches_kind[dom]
-    dom_flops = r.useful_flops_kind[dom]
+    dom_launches = sum(res[-1][0].numeric_launches_kind[dom] for res in per)
+    dom_flops = sum(x.useful_flops_kind[dom] for x in last)
     achieved = dom_flops / (ms_kind[dom] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[("fp64", "fp32", "bf16", "fp32")[dom]]
-    kname = kernel_name(args.kernel, dom, len(sysm.H1), r.tile_shape[dom])
+    kname = kernel_name(args.kernel, dom, len(sysm.H1), r.tile_shape[dom], sysm.H.b)
     log(f"{chosen}: {ms_per_step:.1f} ms/solve, numeric {ms_num:.1f} ms in {launches} launches, "
-        f"symbolic {r.ms_symbolic:.1f} ms, compact {r.ms_compact:.1f} ms, "
-        f"useful {r.useful_flops / 1e12:.3f} TF, executed {r.executed_flops / 1e12:.3f} TF")
+        f"useful {useful / 1e12:.3f} TF, executed {executed / 1e12:.3f} TF")
 
     # gate of the chosen variant against the plain FP64 path
     gate = None
-    if ref is not None:
-        g = T.Solver(sysm, export=True, **variant).run(stream=stream)[0]
-        dx1 = max(float(np.abs(T.bsr_dense(a) - T.bsr_dense(b)).max())
-                  for a, b in zip(g.X1, ref.X1))
-        dal = max(abs(x - y) / abs(y) for x, y in zip(g.alpha, ref.alpha))
+    if refs is not None:
+        gs = exported(variant)
+        dx1 = max(bsr_maxdiff(a, b) for g, f in zip(gs, refs) for a, b in zip(g.X1, f.X1))
+        dal = max(abs(x - y) / abs(y) for g, f in zip(gs, refs) for x, y in zip(g.alpha, f.alpha))
         gate = {"max_abs_dX1": dx1, "rel_dalpha": dal, "pass": bool(dx1 < 1e-6 and dal < 1e-6),
                 "against": "plain FP64 GPU path"}
     traffic = measured_traffic(kname.split("<")[0], args.workload,
                                ("fp64", "fp32", "bf16", "fp32w")[dom])
+    config = {"workload": args.workload, "systems": len(systems), "units": len(units),
+              "atoms": n_atoms, "b": sysm.H.b, "N": sum(sy.H.n for sy in systems),
+              "directions": len(sysm.H1), "eps": sysm.eps, "tol": sysm.tol, "precision": chosen,
+              "closing_fp64": closing, "iters": r.iters, "status": r.status_name,
+              "kernel": args.kernel, "skip": args.skip, "fp64_first": variant["fp64_first"],
+              "wide_accumulate": variant["wide"], "tuned": bool(args.tune),
+              "tile_shape": r.tile_shape, "graph_updates": r.graph_updates,
+              "screened_blocks": sum(res[-1][0].screened_blocks for res in per),
+              "mlp_skipped_blocks": sum(res[-1][0].mlp_skipped_blocks for res in per)}
+    if len(systems) > 1:
+        config["iters_range"] = [min(x.iters for x in last), max(x.iters for x in last)]
     out = {
         "metric": "TC2+response s/solve & useful GFLOP/s, chosen vs plain FP64 at max|dX1|<1e-6",
         "value": round(value, 3),
@@ -252,21 +332,14 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[chosen],
         "data": "synthetic",
-        "config": {"workload": args.workload, "atoms": sysm.H.nb, "b": sysm.H.b,
-                   "N": sysm.H.n, "directions": len(sysm.H1), "eps": sysm.eps,
-                   "tol": sysm.tol, "precision": chosen, "closing_fp64": closing,
-                   "iters": r.iters, "status": r.status_name, "kernel": args.kernel,
-                   "skip": args.skip, "fp64_first": variant["fp64_first"],
-                   "wide_accumulate": variant["wide"], "tuned": bool(args.tune),
-                   "tile_shape": r.tile_shape,
-                   "screened_blocks": r.screened_blocks},
-        "plain_fp64": None if ref is None else {
+        "config": config,
+        "plain_fp64": None if refs is None else {
             "s_per_solve": round(ref_ms * 1e-3, 4),
-            "useful_gflops": round(ref.useful_flops / (ref_ms * 1e-3) / 1e9, 3)},
-        "speedup_vs_plain_fp64": None if ref is None else round(ref_ms / ms_per_step, 3),
+            "useful_gflops": round(ref_useful / (ref_ms * 1e-3) / 1e9, 3)},
+        "speedup_vs_plain_fp64": None if refs is None else round(ref_ms / ms_per_step, 3),
         "gate": gate,
-        "useful_tflop_per_solve": round(r.useful_flops / 1e12, 4),
-        "executed_tflop_per_solve": round(r.executed_flops / 1e12, 4),
+        "useful_tflop_per_solve": round(useful / 1e12, 4),
+        "executed_tflop_per_solve": round(executed / 1e12, 4),
         "roofline": {"bound": "mfma",
                      "kernel": kname, "achieved": round(achieved, 3),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
@@ -278,10 +351,12 @@ def main() -> int:
                                      "ms_per_kind": [round(x, 3) for x in ms_kind]}},
     }
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(sysm, r.iters, r.useful_flops, args.cpu_sample_iters)
+        if len(systems) == 1 and sysm.H.n <= 20000:
+            log("cpu baseline (oracle) ...")
+            out["cpu_baseline"] = cpu_baseline(sysm, r.iters, useful, args.cpu_sample_iters)
+        else:
+            log("cpu baseline skipped: the dense oracle does not fit this workload")
     print(json.dumps(out), flush=True)
-    solver.close()
     return 0
 
 

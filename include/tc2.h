@@ -122,6 +122,12 @@ typedef struct {
   const char *tune_cache;  /* NULL, or a file: tuned shapes are read from it at
                               setup and appended to it (one JSON object per
                               line) when measured                              */
+  int32_t graph;           /* 0 or 1 (tiled kernel): run each update as one
+                              captured hipGraph (persistent numeric launch, no
+                              size read back within the update), replayed while
+                              its buffers suffice.  Not with skip = 2, logging,
+                              or an update that is being tuned (those updates
+                              run without a graph); results are identical      */
 } tc2_options;
 
 typedef struct {
@@ -153,6 +159,7 @@ typedef struct {
   double useful_flops_kind[4];
   double ms_numeric_kind[4];
   int32_t numeric_launches_kind[4];
+  int32_t graph_updates;   /* updates run as a captured graph                   */
   char branches[TC2_MAX_ITER + 4]; /* 'S'/'D' per update, NUL-terminated        */
   /* Library-owned host copies (valid until the next tc2_run or tc2_free) when
      export_matrices = 1; same layout as the inputs.  Otherwise zeroed. */

@@ -146,6 +146,9 @@ struct TileArgs {
   int bf16;               // FP32 values, MFMA operands rounded to bfloat16
   int wide;               // FP32 values, per-block products summed in FP64
   int shape;              // TileShape (must exist for the kind and D)
+  int* work;              // nullptr: one block per sub-tile; else a zeroed
+                          // counter and a persistent grid (see the kernel)
+  const int* n_tiles_dev; // nullptr, or the tile count on the device
   int skip;               // 0 none, 1 exact norm-bound screen, 2 bound + network
   const float* bn;        // block norms (nnz x (1+D)) when skip != 0 or logging
   unsigned long long* screened;  // outputs skipped by the exact screen
@@ -222,6 +225,8 @@ struct CompactArgs {
   const int* sys_start;
   const int* sys_end;
   int max_sys_atoms;
+  const int* n_kept_dev;  // nullptr, or the kept count on the device (then
+                          // clamped to the host count, the stage capacity)
 };
 
 // kernels (launch wrappers), all asynchronous on `st`
@@ -248,12 +253,15 @@ int tile_shape_default(int kind, int D);
 int tile_subs(int shape);  // workgroups per tile of 8 x 8 output blocks
 const char* tile_shape_name(int shape);
 void launch_copy_through(hipStream_t st, int prec, const CopyArgs& a, int nnz);
-void launch_block_norms(hipStream_t st, int prec, long long nnz, int D, const void* xv, float* bn);
+// nnz_dev (optional): the entry count on the device, at most nnz (the grid)
+void launch_block_norms(hipStream_t st, int prec, long long nnz, int D, const void* xv, float* bn,
+                        const int* nnz_dev = nullptr);
 void launch_compact_count(hipStream_t st, const CompactArgs& a, int n_kept);
 void launch_compact_scatter(hipStream_t st, const CompactArgs& a, int n_kept);
 void launch_row_sort(hipStream_t st, const CompactArgs& a);
+// nnz_dev (optional): the new entry count on the device, at most nnz
 void launch_gather(hipStream_t st, int prec, int nnz, int D, const int* new_src,
-                   const void* stage, void* xv);
+                   const void* stage, void* xv, const int* nnz_dev = nullptr);
 void launch_reduce(hipStream_t st, int nsys, const int* sys_item_lo, const int* sys_item_hi,
                    const double* partial, double* scal);
 void launch_sys_items(hipStream_t st, int nsys, int mult, const int* sys_start, const int* sys_end,

@@ -374,6 +374,7 @@ __global__ __launch_bounds__(64) void k_measure(MeasArgs a) {
 // ------------------------------------------------------------------ compaction
 __global__ void k_compact_count(CompactArgs a, int n_kept) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a.n_kept_dev) n_kept = min(n_kept, *a.n_kept_dev);
   if (k >= n_kept) return;
   int2 ij = a.kept_ij[k];
   atomicAdd(&a.rowcnt[ij.x], 1);
@@ -382,6 +383,7 @@ __global__ void k_compact_count(CompactArgs a, int n_kept) {
 
 __global__ void k_compact_scatter(CompactArgs a, int n_kept) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a.n_kept_dev) n_kept = min(n_kept, *a.n_kept_dev);
   if (k >= n_kept) return;
   int2 ij = a.kept_ij[k];
   int p = a.new_rp[ij.x] + atomicAdd(&a.cursor[ij.x], 1);
@@ -446,8 +448,10 @@ __global__ __launch_bounds__(256) void k_row_sort(CompactArgs a) {
 // needs it column-major (a transpose), the mirrored entry (J, I) needs
 // C_IJ^T column-major, i.e. the stage as it is.
 template <typename T>
-__global__ void k_gather(long long n, int D, const int* new_src, const T* stage, T* xv) {
+__global__ void k_gather(long long n, int D, const int* new_src, const T* stage, T* xv,
+                         const int* nnz_dev) {
   const int per = (1 + D) * BS;
+  if (nnz_dev) n = min(n, (long long)*nnz_dev * per);
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
        idx += (long long)gridDim.x * blockDim.x) {
     long long e = idx / per;
@@ -628,15 +632,15 @@ void launch_row_sort(hipStream_t st, const CompactArgs& a) {
 }
 
 void launch_gather(hipStream_t st, int prec, int nnz, int D, const int* new_src,
-                   const void* stage, void* xv) {
+                   const void* stage, void* xv, const int* nnz_dev) {
   long long n = (long long)nnz * (1 + D) * BS;
   if (n == 0) return;
   if (prec == P_FP64)
     hipLaunchKernelGGL(k_gather<double>, dim3(sblk(n, 256)), dim3(256), 0, st, n, D, new_src,
-                       (const double*)stage, (double*)xv);
+                       (const double*)stage, (double*)xv, nnz_dev);
   else
     hipLaunchKernelGGL(k_gather<float>, dim3(sblk(n, 256)), dim3(256), 0, st, n, D, new_src,
-                       (const float*)stage, (float*)xv);
+                       (const float*)stage, (float*)xv, nnz_dev);
 }
 
 void launch_reduce(hipStream_t st, int nsys, const int* lo, const int* hi,

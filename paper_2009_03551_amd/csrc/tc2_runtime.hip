@@ -81,7 +81,7 @@ struct tc2_ctx {
   hipStream_t own = nullptr;
   int nsys = 0, D = 0, b = 0, nb = 0, prec = P_FP64, closing = 0, verbose = 0, export_m = 0;
   int profile = 0;
-  hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t pev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   double ms_sym = 0, ms_num = 0, ms_cmp = 0;
   double ms_num_kind[4] = {0, 0, 0, 0};
   int launches_kind[4] = {0, 0, 0, 0};
@@ -138,7 +138,17 @@ struct tc2_ctx {
   std::vector<int> h_active;      // host copy of the active flags
   // clusters
   int nc = 0, max_sys_clusters = 0;
+  long long tile_bound = 0;       // most tiles an update can have (P <= Q per system)
   DBuf clus_atom, clus_sys, atom_clus, csys_start, csys_end;
+  // graph-captured updates (tiled kernel): one executable graph per iterate
+  // buffer, valid while the key (buffers, sizes, kind, shape) is unchanged
+  int graph = 0;                  // option: capture updates in hipGraphs
+  bool graph_ok = true;           // false after a capture the runtime refused
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec_post[2] = {nullptr, nullptr};  // profiling: the part after the products
+  std::vector<unsigned long long> gkey[2];
+  long long kept_prev = 0, kept_prev2 = 0;  // kept upper blocks of the last updates
+  int graph_updates = 0, graph_captures = 0;
   DBuf panel_cnt, panel_rp, panel_k, panel_e, tile_cnt, tile_rp, tile_pairs, tile_p, tile_q;
   // results
   std::vector<HostBsr> out_x0;
@@ -252,6 +262,10 @@ void tc2_free(tc2_ctx* ctx) {
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
   for (hipEvent_t& e : ctx->pev)
     if (e) (void)hipEventDestroy(e);
+  for (hipGraphExec_t& g : ctx->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (hipGraphExec_t& g : ctx->gexec_post)
+    if (g) (void)hipGraphExecDestroy(g);
   delete ctx;
 }
 
@@ -332,6 +346,7 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   if (o->wide_accumulate < 0 || o->wide_accumulate > 1) return TC2_EINVAL;
   if (o->wide_accumulate && o->numeric_kernel != 0) return TC2_EINVAL;
   if (o->tune < 0 || o->tune > 1 || (o->tune && o->numeric_kernel != 0)) return TC2_EINVAL;
+  if (o->graph < 0 || o->graph > 1 || (o->graph && o->numeric_kernel != 0)) return TC2_EINVAL;
   if (o->numeric_kernel < 0 || o->numeric_kernel > 1) return TC2_EINVAL;
   if (o->precision == P_BF16 && o->numeric_kernel != 0) return TC2_EINVAL;
   if (o->fp64_first < 0 || o->fp64_first > TC2_MAX_ITER) return TC2_EINVAL;
@@ -397,6 +412,7 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   ctx->wide = o->wide_accumulate;
   ctx->tune = o->tune;
   if (o->tune_cache) ctx->tune_cache = o->tune_cache;
+  ctx->graph = o->graph;
   ctx->arch = arch;
   for (int k = 0; k < 4; ++k) ctx->shape[k] = tile_shape_default(k, D);
   if (ctx->tune) tune_load(ctx);
@@ -553,6 +569,10 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
     }
     ctx->nc = (int)clus_sys.size();
     ctx->max_sys_clusters = maxc;
+    for (int s = 0; s < np; ++s) {
+      const long long m = csys_end[s] - csys_start[s];
+      ctx->tile_bound += m * (m + 1) / 2;
+    }
     if ((st = upload(ctx, ctx->clus_atom, clus_atom)) != TC2_OK) return fail(st);
     if ((st = upload(ctx, ctx->clus_sys, clus_sys)) != TC2_OK) return fail(st);
     if ((st = upload(ctx, ctx->atom_clus, atom_clus)) != TC2_OK) return fail(st);
@@ -1065,6 +1085,327 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   return TC2_OK;
 }
 
+// One update of the tiled path as a single captured hipGraph: panels, tiles,
+// block norms, the persistent numeric kernel (sub-tiles taken from an atomic
+// counter, their count read on the device), copy-through, compaction and the
+// per-system reductions.  No size is read back in between: buffers are sized
+// from bounds known before the update (panel entries <= stored blocks, tiles
+// <= tile_bound, new entries <= 2 x stage capacity) and from an estimate of
+// the kept blocks; when the stage overflows, the update is run again with a
+// larger stage (the iterate it reads is untouched).  The graph is replayed as
+// long as the buffers, sizes and kernel choice it captured are unchanged.
+// Returns TC2_OK, an error, or 1 when the runtime refused the capture (the
+// caller then runs the update without a graph).
+int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
+               unsigned long long& exec_pairs_total) {
+  const int c = ctx->cur, n = c ^ 1;
+  const int nb = ctx->nb, D = ctx->D, nc = ctx->nc;
+  const int kind = ctx->cur_prec == P_FP64 ? K_FP64
+                   : (ctx->op_bf16 ? K_BF16 : (ctx->wide ? K_WIDE : K_FP32));
+  const int shape = ctx->shape[kind];
+  const int mult = tile_subs(shape);
+  const size_t tile = (size_t)(1 + D) * BS * prec_bytes(ctx->cur_prec);
+  const bool screen = ctx->skip != 0;
+  bool any_stopped = false;
+  for (int s = 0; s < ctx->nsys; ++s) any_stopped |= !ctx->h_active[s];
+  ctx->kind_used[kind] = true;
+  ctx->last_kind = kind;
+  const long long nnz_c = ctx->nnz[c];
+  const long long cap_c = std::max<long long>((long long)(ctx->xv[c].cap / tile), 1);
+
+  // kept-block estimate: the last count grown by the last growth factor
+  long long est;
+  if (ctx->kept_prev == 0) {
+    est = 2 * nnz_c + 1024;
+  } else {
+    double g = ctx->kept_prev2 > 0 ? (double)ctx->kept_prev / (double)ctx->kept_prev2 : 2.0;
+    g = std::min(2.0, std::max(1.0, g));
+    est = (long long)(ctx->kept_prev * g * 1.1) + 1024;
+  }
+  if (ctx->test_stage_cap > 0) est = ctx->test_stage_cap;
+  est = std::min<long long>(est, INT32_MAX / 2);
+
+  int hcnt[8];
+  unsigned long long pairs = 0, sc[2] = {0, 0};
+  int nnz_new = 0;
+  for (int attempt = 0;; ++attempt) {
+    const int cap = (int)est;
+    HIPCHK(ctx->counters.reserve(64));
+    HIPCHK(ctx->exec_pairs.reserve(8));
+    HIPCHK(ctx->panel_cnt.reserve((size_t)nc * 4));
+    HIPCHK(ctx->panel_rp.reserve((size_t)(nc + 1) * 4));
+    HIPCHK(ctx->tile_cnt.reserve((size_t)nc * 4));
+    HIPCHK(ctx->tile_rp.reserve((size_t)(nc + 1) * 4));
+    HIPCHK(ctx->tile_pairs.reserve((size_t)nc * 8));
+    HIPCHK(ctx->panel_k.reserve((size_t)std::max<long long>(nnz_c, 1) * 4));
+    HIPCHK(ctx->panel_e.reserve((size_t)std::max<long long>(nnz_c, 1) * CS * 4));
+    HIPCHK(ctx->tile_p.reserve((size_t)std::max<long long>(ctx->tile_bound, 1) * 4));
+    HIPCHK(ctx->tile_q.reserve((size_t)std::max<long long>(ctx->tile_bound, 1) * 4));
+    HIPCHK(ctx->partial.reserve((size_t)std::max(ctx->tile_bound * 4, (long long)nb) * NQ * 8));
+    HIPCHK(ctx->sys_lo.reserve((size_t)ctx->nsys * 4));
+    HIPCHK(ctx->sys_hi.reserve((size_t)ctx->nsys * 4));
+    if (screen) {
+      HIPCHK(ctx->bn.reserve((size_t)cap_c * (1 + D) * 4));
+      HIPCHK(ctx->screened.reserve(16));
+    }
+    HIPCHK(ctx->stage.reserve((size_t)cap * tile));
+    HIPCHK(ctx->kept_ij.reserve((size_t)cap * 8));
+    HIPCHK(ctx->rowcnt.reserve((size_t)nb * 4));
+    HIPCHK(ctx->cursor.reserve((size_t)nb * 4));
+    HIPCHK(ctx->rp[n].reserve((size_t)(nb + 1) * 4));
+    const size_t cap2 = (size_t)2 * cap;
+    HIPCHK(ctx->tmp_ci.reserve(cap2 * 4));
+    HIPCHK(ctx->tmp_src.reserve(cap2 * 4));
+    HIPCHK(ctx->new_src.reserve(cap2 * 4));
+    HIPCHK(ctx->ci[n].reserve(cap2 * 4));
+    HIPCHK(ctx->xv[n].reserve(cap2 * tile));
+    HIPCHK(ctx->scal.reserve((size_t)ctx->nsys * NQ * 8));
+    int* cnt = ctx->counters.as<int>();  // [1] stage count [2] overflow [4] work counter
+
+    // what the graph captures: everything that would change a launch
+    const std::vector<unsigned long long> key = {
+        (unsigned long long)kind, (unsigned long long)shape, (unsigned long long)screen,
+        (unsigned long long)any_stopped, (unsigned long long)cap, (unsigned long long)cap_c,
+        (unsigned long long)ctx->profile, (unsigned long long)(uintptr_t)st,
+        (uintptr_t)ctx->xv[c].p, (uintptr_t)ctx->rp[c].p, (uintptr_t)ctx->ci[c].p,
+        (uintptr_t)ctx->xv[n].p, (uintptr_t)ctx->rp[n].p, (uintptr_t)ctx->ci[n].p,
+        (uintptr_t)ctx->panel_k.p, (uintptr_t)ctx->panel_e.p, (uintptr_t)ctx->tile_p.p,
+        (uintptr_t)ctx->tile_q.p, (uintptr_t)ctx->partial.p, (uintptr_t)ctx->bn.p,
+        (uintptr_t)ctx->stage.p, (uintptr_t)ctx->kept_ij.p, (uintptr_t)ctx->tmp_ci.p,
+        (uintptr_t)ctx->tmp_src.p, (uintptr_t)ctx->new_src.p, (uintptr_t)ctx->scal.p,
+        (uintptr_t)ctx->counters.p, (uintptr_t)ctx->screened.p, (uintptr_t)ctx->exec_pairs.p,
+        (uintptr_t)ctx->rowcnt.p, (uintptr_t)ctx->cursor.p, (uintptr_t)ctx->sys_lo.p,
+        (uintptr_t)ctx->sys_hi.p, (uintptr_t)ctx->panel_cnt.p, (uintptr_t)ctx->panel_rp.p,
+        (uintptr_t)ctx->tile_cnt.p, (uintptr_t)ctx->tile_rp.p, (uintptr_t)ctx->tile_pairs.p};
+    // the three parts of the update, as stream work (captured or not)
+    auto rec_pre = [&]() {
+      PanelArgs pa{};
+      pa.nc = nc;
+      pa.rp = ctx->rp[c].as<int>();
+      pa.ci = ctx->ci[c].as<int>();
+      pa.clus_atom = ctx->clus_atom.as<int>();
+      pa.clus_sys = ctx->clus_sys.as<int>();
+      pa.sys_start = ctx->sys_start.as<int>();
+      pa.sys_end = ctx->sys_end.as<int>();
+      pa.csys_start = ctx->csys_start.as<int>();
+      pa.csys_end = ctx->csys_end.as<int>();
+      pa.atom_clus = ctx->atom_clus.as<int>();
+      pa.active = ctx->active.as<int>();
+      pa.max_sys_atoms = ctx->max_sys_atoms;
+      pa.max_sys_clusters = ctx->max_sys_clusters;
+      pa.panel_cnt = ctx->panel_cnt.as<int>();
+      pa.panel_rp = ctx->panel_rp.as<int>();
+      pa.tile_cnt = ctx->tile_cnt.as<int>();
+      pa.tile_pairs = ctx->tile_pairs.as<long long>();
+      pa.tile_rp = ctx->tile_rp.as<int>();
+      pa.panel_k = ctx->panel_k.as<int>();
+      pa.panel_e = ctx->panel_e.as<int>();
+      pa.tile_p = ctx->tile_p.as<int>();
+      pa.tile_q = ctx->tile_q.as<int>();
+      launch_panels(st, 0, pa);
+      launch_scan(st, nc, ctx->panel_cnt.as<int>(), ctx->panel_rp.as<int>(), cnt);
+      launch_panels(st, 1, pa);
+      launch_tiles(st, 0, pa);
+      launch_scan(st, nc, ctx->tile_cnt.as<int>(), ctx->tile_rp.as<int>(), cnt);
+      launch_tiles(st, 1, pa);
+      launch_sys_items(st, ctx->nsys, mult, ctx->csys_start.as<int>(), ctx->csys_end.as<int>(),
+                       ctx->tile_rp.as<int>(), ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>());
+      if (screen) {
+        launch_fill_int(st, ctx->screened.as<int>(), 0, 4);
+        launch_block_norms(st, ctx->cur_prec, cap_c, D, ctx->xv[c].p, ctx->bn.as<float>(),
+                           ctx->rp[c].as<int>() + nb);
+      }
+      launch_fill_int(st, cnt, 0, 8);
+      launch_fill_int(st, ctx->exec_pairs.as<int>(), 0, 2);
+    };
+    auto rec_num = [&]() -> bool {
+      TileArgs ta{};
+      ta.D = D;
+      ta.ksteps = (ctx->b + 3) / 4;
+      ta.n_tiles = (int)std::min<long long>(ctx->tile_bound, INT32_MAX / 4);
+      ta.n_tiles_dev = ctx->tile_rp.as<int>() + nc;
+      ta.work = cnt + 4;
+      ta.rp = ctx->rp[c].as<int>();
+      ta.ci = ctx->ci[c].as<int>();
+      ta.xv = ctx->xv[c].p;
+      ta.tile_p = ctx->tile_p.as<int>();
+      ta.tile_q = ctx->tile_q.as<int>();
+      ta.clus_atom = ctx->clus_atom.as<int>();
+      ta.clus_sys = ctx->clus_sys.as<int>();
+      ta.panel_rp = ctx->panel_rp.as<int>();
+      ta.panel_k = ctx->panel_k.as<int>();
+      ta.panel_e = ctx->panel_e.as<int>();
+      ta.branch = ctx->branch.as<int>();
+      ta.eps = ctx->eps.as<double>();
+      ta.h_rp = ctx->h_rp.as<int>();
+      ta.h_ci = ctx->h_ci.as<int>();
+      ta.h_v = ctx->h_v.as<double>();
+      for (int d = 0; d < D; ++d) {
+        ta.h1_rp[d] = ctx->h1_rp[d].as<int>();
+        ta.h1_ci[d] = ctx->h1_ci[d].as<int>();
+        ta.h1_v[d] = ctx->h1_v[d].as<double>();
+      }
+      ta.stage = ctx->stage.p;
+      ta.kept_ij = ctx->kept_ij.as<int2>();
+      ta.stage_count = cnt + 1;
+      ta.stage_cap = cap;
+      ta.overflow = cnt + 2;
+      ta.bad = ctx->bad.as<int>();
+      ta.partial = ctx->partial.as<double>();
+      ta.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
+      ta.bf16 = kind == K_BF16 ? 1 : 0;
+      ta.wide = kind == K_WIDE ? 1 : 0;
+      ta.shape = shape;
+      ta.skip = ctx->skip;
+      ta.bn = screen ? ctx->bn.as<float>() : nullptr;
+      ta.screened = screen ? ctx->screened.as<unsigned long long>() : nullptr;
+      ta.mlp_skipped = screen ? ctx->screened.as<unsigned long long>() + 1 : nullptr;
+      ta.kl_chunk = ctx->test_kl_chunk;
+      return launch_tile_numeric(st, ctx->cur_prec, ta);
+    };
+    auto rec_post = [&]() {
+      if (any_stopped) {
+        CopyArgs ca{};
+        ca.nb = nb;
+        ca.D = D;
+        ca.rp = ctx->rp[c].as<int>();
+        ca.ci = ctx->ci[c].as<int>();
+        ca.xv = ctx->xv[c].p;
+        ca.sys_of = ctx->sys_of.as<int>();
+        ca.active = ctx->active.as<int>();
+        ca.stage = ctx->stage.p;
+        ca.kept_ij = ctx->kept_ij.as<int2>();
+        ca.stage_count = cnt + 1;
+        ca.stage_cap = cap;
+        ca.overflow = cnt + 2;
+        launch_copy_through(st, ctx->cur_prec, ca, (int)cap_c);
+      }
+      launch_fill_int(st, ctx->rowcnt.as<int>(), 0, nb);
+      launch_fill_int(st, ctx->cursor.as<int>(), 0, nb);
+      CompactArgs cm{};
+      cm.nb = nb;
+      cm.D = D;
+      cm.kept_ij = ctx->kept_ij.as<int2>();
+      cm.rowcnt = ctx->rowcnt.as<int>();
+      cm.cursor = ctx->cursor.as<int>();
+      cm.new_rp = ctx->rp[n].as<int>();
+      cm.sys_of = ctx->sys_of.as<int>();
+      cm.sys_start = ctx->sys_start.as<int>();
+      cm.sys_end = ctx->sys_end.as<int>();
+      cm.max_sys_atoms = ctx->max_sys_atoms;
+      cm.n_kept_dev = cnt + 1;
+      cm.tmp_ci = ctx->tmp_ci.as<int>();
+      cm.tmp_src = ctx->tmp_src.as<int>();
+      cm.new_ci = ctx->ci[n].as<int>();
+      cm.new_src = ctx->new_src.as<int>();
+      launch_compact_count(st, cm, cap);
+      launch_scan(st, nb, ctx->rowcnt.as<int>(), ctx->rp[n].as<int>(), cnt);
+      launch_compact_scatter(st, cm, cap);
+      launch_row_sort(st, cm);
+      launch_gather(st, ctx->cur_prec, (int)cap2, D, ctx->new_src.as<int>(), ctx->stage.p,
+                    ctx->xv[n].p, ctx->rp[n].as<int>() + nb);
+      launch_reduce(st, ctx->nsys, ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>(),
+                    ctx->partial.as<double>(), ctx->scal.as<double>());
+    };
+    // capture of a part sequence into an executable graph; false if refused
+    auto capture = [&](hipGraphExec_t* out, bool with_pre, bool with_num, bool with_post) {
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+      }
+      bool ok = true;
+      if (with_pre) rec_pre();
+      if (with_num) ok = rec_num();
+      if (with_post) rec_post();
+      if (hipGetLastError() != hipSuccess) ok = false;
+      hipGraph_t graph = nullptr;
+      const hipError_t ee = hipStreamEndCapture(st, &graph);
+      if (ee != hipSuccess || !ok || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return false;
+      }
+      const hipError_t ie = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        *out = nullptr;
+        (void)hipGetLastError();
+        return false;
+      }
+      return true;
+    };
+    // one graph for the whole update; when profiling, the products run as a
+    // direct launch between a graph before and a graph after them, so that
+    // stream events can time them
+    if (!ctx->gexec[c] || ctx->gkey[c] != key) {
+      for (hipGraphExec_t* g : {&ctx->gexec[c], &ctx->gexec_post[c]})
+        if (*g) {
+          (void)hipGraphExecDestroy(*g);
+          *g = nullptr;
+        }
+      const bool ok = ctx->profile
+                          ? capture(&ctx->gexec[c], true, false, false) &&
+                                capture(&ctx->gexec_post[c], false, false, true)
+                          : capture(&ctx->gexec[c], true, true, true);
+      if (!ok) return 1;
+      ctx->gkey[c] = key;
+      ctx->graph_captures++;
+    }
+    if (ctx->profile) {
+      HIPCHK(hipEventRecord(ctx->pev[0], st));
+      HIPCHK(hipGraphLaunch(ctx->gexec[c], st));
+      HIPCHK(hipEventRecord(ctx->pev[1], st));
+      HIPCHK(hipEventRecord(ctx->pev[2], st));
+      if (!rec_num()) return TC2_EINVAL;
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipEventRecord(ctx->pev[3], st));
+      HIPCHK(hipEventRecord(ctx->pev[4], st));
+      HIPCHK(hipGraphLaunch(ctx->gexec_post[c], st));
+      HIPCHK(hipEventRecord(ctx->pev[5], st));
+    } else {
+      HIPCHK(hipGraphLaunch(ctx->gexec[c], st));
+    }
+    HIPCHK(hipMemcpyAsync(hcnt, cnt, sizeof(hcnt), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&pairs, ctx->exec_pairs.p, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&nnz_new, ctx->rp[n].as<int>() + nb, 4, hipMemcpyDeviceToHost, st));
+    if (screen) HIPCHK(hipMemcpyAsync(sc, ctx->screened.p, 16, hipMemcpyDeviceToHost, st));
+    scal.resize((size_t)ctx->nsys * NQ);
+    HIPCHK(hipMemcpyAsync(scal.data(), ctx->scal.p, scal.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (ctx->profile) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ctx->pev[0], ctx->pev[1]));
+      ctx->ms_sym += ms;
+      HIPCHK(hipEventElapsedTime(&ms, ctx->pev[2], ctx->pev[3]));
+      ctx->ms_num += ms;
+      ctx->ms_num_kind[kind] += ms;
+      ctx->num_launches++;
+      ctx->launches_kind[kind]++;
+      HIPCHK(hipEventElapsedTime(&ms, ctx->pev[4], ctx->pev[5]));
+      ctx->ms_cmp += ms;
+    }
+    if (!hcnt[2]) break;
+    // stage overflow: the counter still counts every kept block
+    est = std::min<long long>((long long)hcnt[1] * 5 / 4 + 1024, INT32_MAX / 2);
+    if (attempt > 3) return TC2_ENOMEM;
+  }
+  exec_pairs_total += pairs;
+  if (screen) {
+    ctx->screened_total += sc[0];
+    ctx->mlp_total += sc[1];
+  }
+  ctx->kept_prev2 = ctx->kept_prev;
+  ctx->kept_prev = hcnt[1];
+  ctx->stage_cap = std::max<long long>(ctx->stage_cap, (long long)hcnt[1] * 5 / 4 + 1024);
+  ctx->nnz[n] = nnz_new;
+  ctx->cur = n;
+  ctx->graph_updates++;
+  if (ctx->verbose)
+    fprintf(stderr, "tc2 step (graph): kept=%d pairs=%llu new entries=%d captures=%d\n", hcnt[1],
+            pairs, nnz_new, ctx->graph_captures);
+  return TC2_OK;
+}
+
 // energies vector used by the stopping test: E0, E1_d, alpha_d
 void energies(const double* q, int D, double* e) {
   e[0] = q[Q_E0];
@@ -1120,6 +1461,8 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
   }
   ctx->ms_tune = 0.0;
   ctx->prev_out_bound = -1;
+  ctx->kept_prev = ctx->kept_prev2 = 0;
+  ctx->graph_updates = 0;
   for (bool& u : ctx->kind_used) u = false;
   ctx->screened_total = 0;
   ctx->mlp_total = 0;
@@ -1234,7 +1577,20 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
     HIPCHK(hipMemcpyAsync(ctx->branch.p, branch.data(), nsys * 4, hipMemcpyHostToDevice, st));
     ctx->h_active = active;
     ctx->update_index = updates;
-    tc2_status r = step(ctx, st, scal, exec_pairs);
+    tc2_status r = TC2_OK;
+    {
+      const int kind_now = ctx->cur_prec == P_FP64 ? K_FP64
+                           : (ctx->op_bf16 ? K_BF16 : (ctx->wide ? K_WIDE : K_FP32));
+      const bool use_graph = ctx->graph && ctx->graph_ok && ctx->kernel == 0 &&
+                             ctx->log_cap == 0 && ctx->skip != 2 &&
+                             (!ctx->tune || ctx->tuned[kind_now]);
+      int g = 1;
+      if (use_graph) {
+        g = step_graph(ctx, st, scal, exec_pairs);
+        if (g == 1) ctx->graph_ok = false;  // the runtime refused the capture
+      }
+      r = g == 1 ? step(ctx, st, scal, exec_pairs) : (tc2_status)g;
+    }
     if (r != TC2_OK) return r;
     ++updates;
     if (reduced && phase == 0 && ctx->cur_prec == P_FP64 && updates >= ctx->fp64_first) {
@@ -1356,6 +1712,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
       R.ms_numeric_kind[k] = ctx->ms_num_kind[k];
       R.numeric_launches_kind[k] = ctx->launches_kind[k];
     }
+    R.graph_updates = ctx->graph_updates;
     R.ms_compact = ctx->ms_cmp;
     R.numeric_launches = ctx->num_launches;
     for (int k = 0; k < 4; ++k) R.tile_shape[k] = ctx->kind_used[k] ? ctx->shape[k] : -1;

@@ -182,7 +182,10 @@ typedef __attribute__((address_space(3))) void lds_void;
 // W (FP32 values only): the FP32 MFMA product of each column block K is added
 // to FP64 accumulators, so that only the short sum inside one block runs in
 // FP32 and the long sum over K runs in FP64.
-template <typename T, int D, int SP, int TQ, bool BF, bool W>
+// FK: the block size needs all four K-steps of the padded tile (b > 12), so
+// the K-step loop has no exit test and the compiler can overlap the LDS reads
+// of one step with the MFMAs of the previous one.
+template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK>
 __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
   constexpr int PER = (1 + D) * BS;                       // elements per entry
   constexpr int EB = PER * (int)sizeof(T);                // bytes per entry
@@ -198,10 +201,25 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
   __shared__ int2 kl[KLMAX];
   __shared__ int wcount[NW];
   __shared__ int sIA[SP], sJB[TQ];
+  __shared__ unsigned sown[SP];  // row s: bit t set when output (I_s, J_t) is computed
   __shared__ int s_any;
   __shared__ double spart[NW][NQ];
+  __shared__ int s_lb;
 
-  const int lb = (int)blockIdx.x;
+  // One sub-tile per block, or (a.work set) a persistent grid in which every
+  // block takes the next sub-tile from an atomic counter until all are done;
+  // the sub-tile count then comes from the device (tile_rp[nc]).
+  const int total = (a.n_tiles_dev ? *a.n_tiles_dev : a.n_tiles) * SUBS;
+  for (int it = 0;; ++it) {
+  int lb;
+  if (a.work) {
+    if (threadIdx.x == 0) s_lb = atomicAdd(a.work, 1);
+    __syncthreads();
+    lb = s_lb;
+  } else {
+    lb = it == 0 ? (int)blockIdx.x : total;
+  }
+  if (lb >= total) break;
   const int tile = lb / SUBS, sub = lb - tile * SUBS;
   const int ph = sub / (CS / TQ), qh = sub - ph * (CS / TQ);
   const int P = a.tile_p[tile], Q = a.tile_q[tile];
@@ -231,11 +249,11 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
   __syncthreads();
   if (!s_any) {  // e.g. the lower sub-tiles of a diagonal tile: no work, zero sums
     if (t < NQ) a.partial[(size_t)lb * NQ + t] = 0.0;
-    return;
+    continue;
   }
 
   const T* X = (const T*)a.xv;
-  Acc<T> acc[NO][1 + D];
+  Acc<T> acc[W ? 1 : NO][W ? 1 : 1 + D];
   AccW wacc[W ? NO : 1][W ? 1 + D : 1];
 #pragma unroll
   for (int o = 0; o < NO; ++o)
@@ -243,8 +261,8 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
     for (int m = 0; m <= D; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        acc[o][m].v[r] = 0;
         if constexpr (W) wacc[o][m].v[r] = 0.0;
+        else acc[o][m].v[r] = 0;
       }
   int np[NO];
 #pragma unroll
@@ -270,12 +288,22 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
     }
     return e;
   };
-  // copy the blocks of a column group (entries eg, as load_entries) into buffer bb
+  // Copy the blocks of a column group (entries eg, as load_entries) into
+  // buffer bb.  A block that meets no present partner of a computed output in
+  // its column is not copied (marked absent): no product needs it.
   auto issue = [&](int eg, int bb) {
+    const unsigned long long pm = __ballot(eg >= 0);
 #pragma unroll
     for (int gi = 0; gi < KG; ++gi) {
+      const unsigned mA = (unsigned)(pm >> (gi * NE)) & ((1u << SP) - 1u);
+      const unsigned mB = (unsigned)(pm >> (gi * NE + SP)) & ((1u << TQ) - 1u);
+      unsigned colsA = 0;  // columns t with a present A block in an owned row
+#pragma unroll
+      for (int r = 0; r < SP; ++r) colsA |= ((mA >> r) & 1u) ? sown[r] : 0u;
       for (int x = wave; x < NE; x += NW) {
-        const int e = __builtin_amdgcn_readlane(eg, gi * NE + x);
+        int e = __builtin_amdgcn_readlane(eg, gi * NE + x);
+        const bool need = (x < SP) ? (sown[x] & mB) != 0u : ((colsA >> (x - SP)) & 1u) != 0u;
+        if (!need) e = -1;
         if (lane == 0) sflag[bb][gi][x] = e;
         if (e >= 0) {
           const char* src = (const char*)(X + (size_t)e * PER) + lane * 16;
@@ -289,13 +317,23 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
     }
   };
 
-  // common columns of the chunk [base, end) of P's panel with Q's panel -> kl
-  auto build_kl = [&](int base, int end) {
+  // common columns of the chunk [base, end) of P's panel with Q's panel -> kl;
+  // with `useful`, only the columns where some computed output (I_s, J_t)
+  // has both blocks X_{I_s K} and X_{J_t K} present
+  auto build_kl = [&](int base, int end, bool useful) {
     int nm = 0;
     for (int c0 = base; c0 < end; c0 += NT) {
       const int idx = c0 + t;
       int j = -1;
       if (idx < end) j = (P == Q) ? idx - pp0 : bsearch_eq(a.panel_k + pq0, nq, a.panel_k[idx]);
+      if (useful && j >= 0) {
+        unsigned mB = 0u, use = 0u;
+        const int* eb = a.panel_e + (size_t)(pq0 + j) * CS + qh * TQ;
+        for (int u = 0; u < TQ; ++u) mB |= (eb[u] >= 0) ? (1u << u) : 0u;
+        const int* ea = a.panel_e + (size_t)idx * CS + ph * SP;
+        for (int r = 0; r < SP; ++r) use |= (ea[r] >= 0) ? (sown[r] & mB) : 0u;
+        if (!use) j = -1;
+      }
       const bool found = j >= 0;
       const unsigned long long mask = __ballot(found);
       if (lane == 0) wcount[wave] = __popcll(mask);
@@ -336,8 +374,6 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
   // columns of P's panel taken per pass (a smaller chunk can be forced to test
   // the multi-pass path on small inputs)
   const int KLC = (a.kl_chunk > 0 && a.kl_chunk < KLMAX) ? a.kl_chunk : KLMAX;
-  const bool single_chunk = (pp1 - pp0) <= KLC;
-  int nm_kept = -1;
   int my_slot = -1;  // lane o: log slot of output o
   if (a.skip || a.log_cap > 0) {
     constexpr int THF = 4864;  // floats reserved for the network at the start of buf
@@ -366,8 +402,7 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
       for (int m = 0; m <= D; ++m) bsum[o][m] = 0.0;
     }
     for (int base = pp0; base < pp1; base += KLC) {
-      const int nm = build_kl(base, min(pp1, base + KLC));
-      nm_kept = nm;
+      const int nm = build_kl(base, min(pp1, base + KLC), false);
       for (int r0 = 0; r0 < nm; r0 += NSF) {
         const int nr = min(NSF, nm - r0);
         for (int i = t; i < nr * NE; i += NT) {
@@ -488,10 +523,71 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
     for (int o = 0; o < NO; ++o) any_owned |= owned[o];
   }
 
+  // outputs computed by this block, as row masks
+  if (t < SP) sown[t] = 0u;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+      if (owned[o]) atomicOr(&sown[so[o]], 1u << to[o]);
+  }
+  __syncthreads();
+
+  // Products of one column block K (buffer bb, slot gi) for the present
+  // outputs pm (K-steps of 4 up to the block size).
+  auto column = [&](unsigned pm, int bb, int gi) {
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      if (!((pm >> o) & 1u)) continue;
+      const T* xa = &buf[bb][gi][so[o]][0];
+      const T* xb = &buf[bb][gi][SP + to[o]][0];
+      if constexpr (BF) {
+        // bfloat16 operands: one 16x16x16 MFMA per block product
+        const s4 a0 = bf16_frag((const float*)xa, lane), b0 = bf16_frag((const float*)xb, lane);
+        mfma_bf16(acc[o][0], a0, b0);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const s4 a1 = bf16_frag((const float*)xa + (1 + d) * BS, lane);
+          const s4 b1 = bf16_frag((const float*)xb + (1 + d) * BS, lane);
+          mfma_bf16(acc[o][1 + d], a0, b1);
+          mfma_bf16(acc[o][1 + d], a1, b0);
+        }
+      } else {
+        // W: this column's FP32 products go to temporaries, then to the FP64 sums
+        Acc<T> tmp[W ? 1 + D : 1];
+        if constexpr (W) {
+#pragma unroll
+          for (int m = 0; m <= D; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tmp[m].v[r] = 0.f;
+        }
+        Acc<T>* dst = W ? tmp : &acc[W ? 0 : o][0];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          if (!FK && kk >= a.ksteps) break;
+          const T a0 = xa[lane + kk * 64], b0 = xb[lane + kk * 64];
+          mfma(dst[0], a0, b0);
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            const T a1 = xa[(1 + d) * BS + lane + kk * 64], b1 = xb[(1 + d) * BS + lane + kk * 64];
+            mfma(dst[1 + d], a0, b1);
+            mfma(dst[1 + d], a1, b0);
+          }
+        }
+        if constexpr (W) {
+#pragma unroll
+          for (int m = 0; m <= D; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) wacc[o][m].v[r] += (double)tmp[m].v[r];
+        }
+      }
+    }
+  };
+
   for (int base = pp0; base < pp1; base += KLC) {
     // ---- common columns of this chunk of P's panel with Q's panel
     const int end = min(pp1, base + KLC);
-    const int nm = (single_chunk && nm_kept >= 0) ? nm_kept : build_kl(base, end);
+    const int nm = build_kl(base, end, true);
     // ---- pipelined products over the common columns
     const int ngroups = (nm + KG - 1) / KG;
     int e_next = 0;
@@ -511,97 +607,19 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
 #pragma unroll
         for (int gi = 0; gi < KG; ++gi) {
           if (g * KG + gi >= nm) break;
-          bool pres[NO];
+          // outputs with both blocks present in this column, as a wave-uniform
+          // mask: the branches below are scalar, and each present output runs
+          // its products for the column as one straight block
+          unsigned pm = 0u;
 #pragma unroll
           for (int o = 0; o < NO; ++o) {
-            pres[o] = owned[o] && sflag[bb][gi][so[o]] >= 0 && sflag[bb][gi][SP + to[o]] >= 0;
-            np[o] += pres[o] ? 1 : 0;
+            const bool p = owned[o] && sflag[bb][gi][so[o]] >= 0 && sflag[bb][gi][SP + to[o]] >= 0;
+            pm |= p ? (1u << o) : 0u;
           }
-          // Operands of HALF outputs are read from LDS up front (absent
-          // blocks read stale data that no MFMA consumes); the two updates of
-          // each response accumulator are issued in separate passes so that
-          // dependent MFMAs are not back to back.
-          constexpr int HALF = ((sizeof(T) == 8 || BF || W) && D >= 2) ? 2 : 4;
-          if constexpr (BF) {
-            // bfloat16 operands: one 16x16x16 MFMA per block product
+          pm = __builtin_amdgcn_readfirstlane(pm);
 #pragma unroll
-            for (int h = 0; h < NO; h += HALF) {
-              s4 A0[HALF], B0[HALF], A1[HALF][D > 0 ? D : 1], B1[HALF][D > 0 ? D : 1];
-#pragma unroll
-              for (int u = 0; u < HALF; ++u) {
-                const float* xa = (const float*)&buf[bb][gi][so[h + u]][0];
-                const float* xb = (const float*)&buf[bb][gi][SP + to[h + u]][0];
-                A0[u] = bf16_frag(xa, lane);
-                B0[u] = bf16_frag(xb, lane);
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                  A1[u][d] = bf16_frag(xa + (1 + d) * BS, lane);
-                  B1[u][d] = bf16_frag(xb + (1 + d) * BS, lane);
-                }
-              }
-#pragma unroll
-              for (int u = 0; u < HALF; ++u)
-                if (pres[h + u]) mfma_bf16(acc[h + u][0], A0[u], B0[u]);
-#pragma unroll
-              for (int d = 0; d < D; ++d)
-#pragma unroll
-                for (int u = 0; u < HALF; ++u)
-                  if (pres[h + u]) mfma_bf16(acc[h + u][1 + d], A0[u], B1[u][d]);
-#pragma unroll
-              for (int d = 0; d < D; ++d)
-#pragma unroll
-                for (int u = 0; u < HALF; ++u)
-                  if (pres[h + u]) mfma_bf16(acc[h + u][1 + d], A1[u][d], B0[u]);
-            }
-            continue;
-          }
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            if (kk >= a.ksteps) break;
-#pragma unroll
-            for (int h = 0; h < NO; h += HALF) {
-              T A0[HALF], B0[HALF], A1[HALF][D > 0 ? D : 1], B1[HALF][D > 0 ? D : 1];
-#pragma unroll
-              for (int u = 0; u < HALF; ++u) {
-                const T* xa = &buf[bb][gi][so[h + u]][lane + kk * 64];
-                const T* xb = &buf[bb][gi][SP + to[h + u]][lane + kk * 64];
-                A0[u] = xa[0];
-                B0[u] = xb[0];
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                  A1[u][d] = xa[(1 + d) * BS];
-                  B1[u][d] = xb[(1 + d) * BS];
-                }
-              }
-#pragma unroll
-              for (int u = 0; u < HALF; ++u)
-                if (pres[h + u]) mfma(acc[h + u][0], A0[u], B0[u]);
-#pragma unroll
-              for (int d = 0; d < D; ++d)
-#pragma unroll
-                for (int u = 0; u < HALF; ++u)
-                  if (pres[h + u]) mfma(acc[h + u][1 + d], A0[u], B1[u][d]);
-#pragma unroll
-              for (int d = 0; d < D; ++d)
-#pragma unroll
-                for (int u = 0; u < HALF; ++u)
-                  if (pres[h + u]) mfma(acc[h + u][1 + d], A1[u][d], B0[u]);
-            }
-          }
-          if constexpr (W) {
-            // column block K done: its FP32 products join the FP64 sums
-#pragma unroll
-            for (int o = 0; o < NO; ++o) {
-              if (!pres[o]) continue;
-#pragma unroll
-              for (int m = 0; m <= D; ++m)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                  wacc[o][m].v[r] += (double)acc[o][m].v[r];
-                  acc[o][m].v[r] = 0.f;
-                }
-            }
-          }
+          for (int o = 0; o < NO; ++o) np[o] += (int)((pm >> o) & 1u);
+          column(pm, bb, gi);
         }
       }
     }
@@ -642,6 +660,7 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
     for (int w = 0; w < NW; ++w) sum += spart[w][t];
     a.partial[(size_t)lb * NQ + t] = sum;
   }
+  }  // sub-tiles
 }
 
 // ------------------------------------------------------------------ copy-through
@@ -685,8 +704,9 @@ __global__ void k_copy_through(CopyArgs a) {
 // Frobenius norm of every stored block of every matrix (float), one wave per
 // entry; used by the screens.
 template <typename T>
-__global__ void k_block_norms(long long nnz, int D, const T* xv, float* bn) {
+__global__ void k_block_norms(long long nnz, int D, const T* xv, float* bn, const int* nnz_dev) {
   const int lane = threadIdx.x & 63;
+  if (nnz_dev) nnz = min(nnz, (long long)*nnz_dev);
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
   for (long long e = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < nnz;
        e += nwaves) {
@@ -704,13 +724,18 @@ __global__ void k_block_norms(long long nnz, int D, const T* xv, float* bn) {
   }
 }
 
-void launch_block_norms(hipStream_t st, int prec, long long nnz, int D, const void* xv, float* bn) {
+void launch_block_norms(hipStream_t st, int prec, long long nnz, int D, const void* xv, float* bn,
+                        const int* nnz_dev) {
   if (nnz == 0) return;
   // one wave per entry, waves loop over entries beyond 2^24 blocks of 4 waves
   const long long want = (nnz + 3) / 4;
   const unsigned blocks = (unsigned)(want < (1 << 20) ? want : (1 << 20));
-  if (prec == P_FP64) hipLaunchKernelGGL(k_block_norms<double>, dim3(blocks), dim3(256), 0, st, nnz, D, (const double*)xv, bn);
-  else hipLaunchKernelGGL(k_block_norms<float>, dim3(blocks), dim3(256), 0, st, nnz, D, (const float*)xv, bn);
+  if (prec == P_FP64)
+    hipLaunchKernelGGL(k_block_norms<double>, dim3(blocks), dim3(256), 0, st, nnz, D,
+                       (const double*)xv, bn, nnz_dev);
+  else
+    hipLaunchKernelGGL(k_block_norms<float>, dim3(blocks), dim3(256), 0, st, nnz, D,
+                       (const float*)xv, bn, nnz_dev);
 }
 
 // ================================================================== launchers
@@ -755,11 +780,43 @@ const char* tile_shape_name(int shape) {
   return (shape >= 0 && shape < TS_N) ? names[shape] : "?";
 }
 
+// Blocks of a persistent launch: enough to fill every CU at the kernel's
+// occupancy (computed once per instance).
+template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK>
+static unsigned resident_blocks() {
+  static int per_cu = -1, cus = 0;
+  if (per_cu < 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_numeric<T, D, SP, TQ, BF, W, FK>,
+                                                     TQ * 64, 0) != hipSuccess || n < 1) {
+      cus = 256;
+      n = 1;
+    }
+    per_cu = n;
+  }
+  return (unsigned)(per_cu * cus);
+}
+
+template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK>
+static void tile_go_k(hipStream_t st, const TileArgs& a) {
+  unsigned G = (unsigned)a.n_tiles * (unsigned)((CS / SP) * (CS / TQ));
+  if (a.work) {  // persistent: never more blocks than sub-tiles or than fit at once
+    const unsigned R = resident_blocks<T, D, SP, TQ, BF, W, FK>();
+    G = G < R ? G : R;
+  }
+  hipLaunchKernelGGL((k_tile_numeric<T, D, SP, TQ, BF, W, FK>), dim3(G), dim3(TQ * 64), 0, st, a);
+}
+
 template <typename T, int D, bool BF, bool W, int S>
 static void tile_go(hipStream_t st, const TileArgs& a) {
   constexpr int SP = SHAPE_SP[S], TQ = SHAPE_TQ[S];
-  const unsigned G = (unsigned)a.n_tiles * (unsigned)((CS / SP) * (CS / TQ));
-  hipLaunchKernelGGL((k_tile_numeric<T, D, SP, TQ, BF, W>), dim3(G), dim3(TQ * 64), 0, st, a);
+  // bfloat16 products take the whole padded K in one MFMA: no K-step loop
+  if constexpr (!BF) {
+    if (a.ksteps == 4) return tile_go_k<T, D, SP, TQ, BF, W, true>(st, a);
+  }
+  tile_go_k<T, D, SP, TQ, BF, W, false>(st, a);
 }
 
 // false when the shape does not exist for this kind

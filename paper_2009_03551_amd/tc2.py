@@ -44,7 +44,8 @@ class tc2_options(C.Structure):
                 ("profile", C.c_int32), ("numeric_kernel", C.c_int32),
                 ("fp64_first", C.c_int32), ("mlp_weights", C.POINTER(C.c_float)),
                 ("mlp_threshold", C.c_float), ("log_capacity", C.c_int64),
-                ("wide_accumulate", C.c_int32), ("tune", C.c_int32), ("tune_cache", C.c_char_p)]
+                ("wide_accumulate", C.c_int32), ("tune", C.c_int32), ("tune_cache", C.c_char_p),
+                ("graph", C.c_int32)]
 
 
 class tc2_result(C.Structure):
@@ -58,7 +59,7 @@ class tc2_result(C.Structure):
                 ("ms_compact", C.c_double), ("numeric_launches", C.c_int32),
                 ("tile_shape", C.c_int32 * 4), ("ms_tune", C.c_double),
                 ("useful_flops_kind", C.c_double * 4), ("ms_numeric_kind", C.c_double * 4),
-                ("numeric_launches_kind", C.c_int32 * 4),
+                ("numeric_launches_kind", C.c_int32 * 4), ("graph_updates", C.c_int32),
                 ("branches", C.c_char * (TC2_MAX_ITER + 4)),
                 ("X0", tc2_bsr), ("X1", tc2_bsr * 3)]
 
@@ -189,6 +190,7 @@ class Result:
     useful_flops_kind: List[float] = field(default_factory=list)
     ms_numeric_kind: List[float] = field(default_factory=list)
     numeric_launches_kind: List[int] = field(default_factory=list)
+    graph_updates: int = 0
     X0: Optional[BSR] = None
     X1: List[BSR] = field(default_factory=list)
 
@@ -225,7 +227,7 @@ class Solver:
                  profile: bool = False, kernel: str = "tile", use_xyz: bool = True,
                  fp64_first: int = 0, skip: str = "none", mlp_weights=None,
                  mlp_threshold: float = 0.99, log_capacity: int = 0, wide: bool = False,
-                 tune: bool = False, tune_cache: Optional[str] = None):
+                 tune: bool = False, tune_cache: Optional[str] = None, graph: bool = False):
         if isinstance(systems, System):
             systems = [systems]
         self.systems = list(systems)
@@ -263,7 +265,7 @@ class Solver:
                            1 if export else 0, 1 if verbose else 0, 1 if profile else 0,
                            KERNEL[kernel], int(fp64_first), wptr, float(mlp_threshold),
                            int(log_capacity), 1 if wide else 0, 1 if tune else 0,
-                           tune_cache.encode() if tune_cache else None)
+                           tune_cache.encode() if tune_cache else None, 1 if graph else 0)
         self.log_capacity = int(log_capacity)
         self._ctx = C.c_void_p()
         st = lib().tc2_setup(probs, n, C.byref(opts), C.byref(self._ctx))
@@ -288,7 +290,7 @@ class Solver:
                               r.ms_symbolic, r.ms_numeric, r.ms_compact,
                               r.numeric_launches, list(r.tile_shape), r.ms_tune,
                               list(r.useful_flops_kind), list(r.ms_numeric_kind),
-                              list(r.numeric_launches_kind), x0, x1))
+                              list(r.numeric_launches_kind), r.graph_updates, x0, x1))
         return out
 
     def log(self):
