@@ -219,6 +219,9 @@ def main() -> int:
             torch.cuda.synchronize()
             total_ms += (time.perf_counter() - t0) / args.steps * 1e3
             solver.close()
+            if len(units) > 1:
+                log(f"  unit of {len(u)} systems / {sum(x.H.nb for x in u)} atoms: "
+                    f"{(time.perf_counter() - t0) / args.steps:.2f} s/solve")
             last += res[-1]
             per.append(res)
         return total_ms, last, per
@@ -227,6 +230,8 @@ def main() -> int:
         out = []
         for u in units:
             out += T.solve(u, export=True, **kw)
+            if len(units) > 1:
+                log(f"  exported unit of {len(u)} systems")
         return out
 
     def bsr_maxdiff(a, b):
