@@ -230,8 +230,7 @@ def main() -> int:
         out = []
         for u in units:
             out += T.solve(u, export=True, **kw)
-            if len(units) > 1:
-                log(f"  exported unit of {len(u)} systems")
+            log(f"  exported unit of {len(u)} system(s)")
         return out
 
     def bsr_maxdiff(a, b):
@@ -306,10 +305,31 @@ def main() -> int:
     gate = None
     if refs is not None:
         gs = exported(variant)
+        log("gate: comparing block patterns and values")
         dx1 = max(bsr_maxdiff(a, b) for g, f in zip(gs, refs) for a, b in zip(g.X1, f.X1))
         dal = max(abs(x - y) / abs(y) for g, f in zip(gs, refs) for x, y in zip(g.alpha, f.alpha))
         gate = {"max_abs_dX1": dx1, "rel_dalpha": dal, "pass": bool(dx1 < 1e-6 and dal < 1e-6),
                 "against": "plain FP64 GPU path"}
+    # the learned screen against the exact one on the same variant: what it
+    # saves and the error it introduces (the exact-screen run is the judge)
+    mlp_vs_bound = None
+    if args.skip == "mlp":
+        bkw = dict(variant, skip="bound")
+        bkw.pop("mlp_weights")
+        bkw.pop("mlp_threshold")
+        b_ms, b_last, _ = timed(dict(export=False, profile=True, **bkw))
+        b_exec = sum(x.executed_flops for x in b_last)
+        log(f"exact screen alone: {b_ms:.1f} ms/solve, executed {b_exec / 1e12:.3f} TF")
+        ga, gb = exported(variant), exported(bkw)
+        mlp_vs_bound = {
+            "s_per_solve_bound": round(b_ms * 1e-3, 4),
+            "speedup_over_bound": round(b_ms / ms_per_step, 3),
+            "executed_tflop_bound": round(b_exec / 1e12, 4),
+            "executed_saved_frac": round(1.0 - executed / b_exec, 4),
+            "max_abs_dX1": max(bsr_maxdiff(a, b) for g, f in zip(ga, gb) for a, b in zip(g.X1, f.X1)),
+            "rel_dalpha": max(abs(x - y) / abs(y) for g, f in zip(ga, gb)
+                              for x, y in zip(g.alpha, f.alpha))}
+        log(f"mlp vs bound: {mlp_vs_bound}")
     traffic = measured_traffic(kname.split("<")[0], args.workload,
                                ("fp64", "fp32", "bf16", "fp32w")[dom])
     config = {"workload": args.workload, "systems": len(systems), "units": len(units),
@@ -343,6 +363,7 @@ def main() -> int:
             "useful_gflops": round(ref_useful / (ref_ms * 1e-3) / 1e9, 3)},
         "speedup_vs_plain_fp64": None if refs is None else round(ref_ms / ms_per_step, 3),
         "gate": gate,
+        "mlp_vs_bound": mlp_vs_bound,
         "useful_tflop_per_solve": round(useful / 1e12, 4),
         "executed_tflop_per_solve": round(executed / 1e12, 4),
         "roofline": {"bound": "mfma",

@@ -680,7 +680,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   const int nb = ctx->nb, D = ctx->D;
   const size_t tile = (size_t)(1 + D) * BS * prec_bytes(ctx->cur_prec);
   HIPCHK(ctx->counters.reserve(64));
-  int* cnt = ctx->counters.as<int>();  // [0] scan total, [1] stage count, [2] overflow
+  int* cnt = ctx->counters.as<int>();  // [0] scan total, [1] stage count, [2] overflow, [4] work counter
   int hcnt[4];
   const bool tiled = ctx->kernel == 0;
   bool any_stopped = false;
@@ -850,6 +850,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     ta.stage_count = cnt + 1;
     ta.stage_cap = cap;
     ta.shape = shape;
+    ta.work = cnt + 4;  // persistent launch: sub-tiles from a counter zeroed with cnt
     ta.overflow = cnt + 2;
     ta.bad = ctx->bad.as<int>();
     ta.partial = ctx->partial.as<double>();
@@ -893,7 +894,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       if (!tile_shape_available(kind, D, sh)) continue;
       const TileArgs ta = tile_args(cap, sh);
       for (int rep = 0; rep < 2; ++rep) {
-        launch_fill_int(st, cnt, 0, 4);
+        launch_fill_int(st, cnt, 0, 8);
         launch_fill_int(st, ctx->exec_pairs.as<int>(), 0, 2);
         if (screen) launch_fill_int(st, ctx->screened.as<int>(), 0, 4);
         HIPCHK(hipEventRecord(t0, st));
@@ -931,7 +932,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     int cap = (int)std::min<long long>(std::max<long long>(ctx->stage_cap, 1), out_bound > 0 ? out_bound : 1);
     HIPCHK(ctx->stage.reserve((size_t)cap * tile));
     HIPCHK(ctx->kept_ij.reserve((size_t)cap * 8));
-    launch_fill_int(st, cnt, 0, 4);
+    launch_fill_int(st, cnt, 0, 8);
     launch_fill_int(st, ctx->exec_pairs.as<int>(), 0, 2);
     if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[2], st));
     if (!tiled) {

@@ -223,7 +223,13 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
   const int tile = lb / SUBS, sub = lb - tile * SUBS;
   const int ph = sub / (CS / TQ), qh = sub - ph * (CS / TQ);
   const int P = a.tile_p[tile], Q = a.tile_q[tile];
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  // threadIdx-derived values are made opaque per sub-tile, so that the
+  // compiler does not hoist per-lane addresses out of the sub-tile loop and
+  // keep them live across it (register pressure)
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  const int lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform (scalar)
   const int sys = a.clus_sys[P];
   const bool square = a.branch[sys] != 0;
   const double eps = a.eps[sys];
@@ -523,7 +529,11 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
     for (int o = 0; o < NO; ++o) any_owned |= owned[o];
   }
 
-  // outputs computed by this block, as row masks
+  // outputs computed by this wave (bit o) and by this block (row masks)
+  unsigned own_mask = 0u;
+#pragma unroll
+  for (int o = 0; o < NO; ++o) own_mask |= owned[o] ? (1u << o) : 0u;
+  own_mask = __builtin_amdgcn_readfirstlane(own_mask);
   if (t < SP) sown[t] = 0u;
   __syncthreads();
   if (lane == 0) {
@@ -610,13 +620,11 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
           // outputs with both blocks present in this column, as a wave-uniform
           // mask: the branches below are scalar, and each present output runs
           // its products for the column as one straight block
+          const unsigned pe = (unsigned)__ballot(lane < NE && sflag[bb][gi][lane < NE ? lane : 0] >= 0);
           unsigned pm = 0u;
 #pragma unroll
-          for (int o = 0; o < NO; ++o) {
-            const bool p = owned[o] && sflag[bb][gi][so[o]] >= 0 && sflag[bb][gi][SP + to[o]] >= 0;
-            pm |= p ? (1u << o) : 0u;
-          }
-          pm = __builtin_amdgcn_readfirstlane(pm);
+          for (int o = 0; o < NO; ++o) pm |= ((pe >> so[o]) & (pe >> (SP + to[o])) & 1u) << o;
+          pm = __builtin_amdgcn_readfirstlane(pm & own_mask);
 #pragma unroll
           for (int o = 0; o < NO; ++o) np[o] += (int)((pm >> o) & 1u);
           column(pm, bb, gi);
