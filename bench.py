@@ -226,12 +226,19 @@ def main() -> int:
             per.append(res)
         return total_ms, last, per
 
-    def exported(kw):
-        out = []
+    def compare(kw_a, kw_b):
+        """max |dX1| and relative |d alpha| between two variants, unit by unit
+        (only one unit's exported matrices are held at a time)."""
+        dx1 = dal = 0.0
         for u in units:
-            out += T.solve(u, export=True, **kw)
-            log(f"  exported unit of {len(u)} system(s)")
-        return out
+            ga = T.solve(u, export=True, **kw_a)
+            gb = T.solve(u, export=True, **kw_b)
+            dx1 = max([dx1] + [bsr_maxdiff(a, b) for g, f in zip(ga, gb) for a, b in zip(g.X1, f.X1)])
+            dal = max([dal] + [abs(x - y) / abs(y) for g, f in zip(ga, gb)
+                               for x, y in zip(g.alpha, f.alpha)])
+            del ga, gb
+            log(f"  compared unit of {len(u)} system(s): max|dX1| {dx1:.3e} rel|dalpha| {dal:.3e}")
+        return dx1, dal
 
     def bsr_maxdiff(a, b):
         """max |A - B| over the union of two block patterns (no dense copy)."""
@@ -252,14 +259,14 @@ def main() -> int:
                if args.kernel == "tile" else {})
     # plain FP64 path (every candidate block computed): reference for the gate
     # and the speed-up, timed the same way as the chosen variant
-    refs = None
+    ref_kw = dict(precision="fp64", kernel=args.kernel, **tile_kw)
+    ref_ms = None
     if not args.no_reference:
-        refs = exported(dict(precision="fp64", kernel=args.kernel, **tile_kw))
-        ref_ms, ref_last, _ = timed(dict(precision="fp64", export=False, kernel=args.kernel,
-                                         **tile_kw))
+        ref_ms, ref_last, _ = timed(dict(export=False, **ref_kw))
         ref_useful = sum(x.useful_flops for x in ref_last)
-        log(f"plain fp64: {refs[0].status_name} iters={refs[0].iters} {refs[0].branches} "
-            f"alpha={refs[0].alpha} kept={sum(x.kept_blocks for x in refs)} {ref_ms:.1f} ms/solve")
+        r0 = ref_last[0]
+        log(f"plain fp64: {r0.status_name} iters={r0.iters} {r0.branches} alpha={r0.alpha} "
+            f"kept={sum(x.kept_blocks for x in ref_last)} {ref_ms:.1f} ms/solve")
 
     chosen = args.precision
     closing = 0 if chosen == "fp64" else 2
@@ -303,11 +310,9 @@ def main() -> int:
 
     # gate of the chosen variant against the plain FP64 path
     gate = None
-    if refs is not None:
-        gs = exported(variant)
-        log("gate: comparing block patterns and values")
-        dx1 = max(bsr_maxdiff(a, b) for g, f in zip(gs, refs) for a, b in zip(g.X1, f.X1))
-        dal = max(abs(x - y) / abs(y) for g, f in zip(gs, refs) for x, y in zip(g.alpha, f.alpha))
+    if ref_ms is not None:
+        log("gate: chosen variant against the plain FP64 path")
+        dx1, dal = compare(variant, ref_kw)
         gate = {"max_abs_dX1": dx1, "rel_dalpha": dal, "pass": bool(dx1 < 1e-6 and dal < 1e-6),
                 "against": "plain FP64 GPU path"}
     # the learned screen against the exact one on the same variant: what it
@@ -320,15 +325,13 @@ def main() -> int:
         b_ms, b_last, _ = timed(dict(export=False, profile=True, **bkw))
         b_exec = sum(x.executed_flops for x in b_last)
         log(f"exact screen alone: {b_ms:.1f} ms/solve, executed {b_exec / 1e12:.3f} TF")
-        ga, gb = exported(variant), exported(bkw)
+        mdx1, mdal = compare(variant, bkw)
         mlp_vs_bound = {
             "s_per_solve_bound": round(b_ms * 1e-3, 4),
             "speedup_over_bound": round(b_ms / ms_per_step, 3),
             "executed_tflop_bound": round(b_exec / 1e12, 4),
             "executed_saved_frac": round(1.0 - executed / b_exec, 4),
-            "max_abs_dX1": max(bsr_maxdiff(a, b) for g, f in zip(ga, gb) for a, b in zip(g.X1, f.X1)),
-            "rel_dalpha": max(abs(x - y) / abs(y) for g, f in zip(ga, gb)
-                              for x, y in zip(g.alpha, f.alpha))}
+            "max_abs_dX1": mdx1, "rel_dalpha": mdal}
         log(f"mlp vs bound: {mlp_vs_bound}")
     traffic = measured_traffic(kname.split("<")[0], args.workload,
                                ("fp64", "fp32", "bf16", "fp32w")[dom])
@@ -358,10 +361,10 @@ def main() -> int:
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[chosen],
         "data": "synthetic",
         "config": config,
-        "plain_fp64": None if refs is None else {
+        "plain_fp64": None if ref_ms is None else {
             "s_per_solve": round(ref_ms * 1e-3, 4),
             "useful_gflops": round(ref_useful / (ref_ms * 1e-3) / 1e9, 3)},
-        "speedup_vs_plain_fp64": None if refs is None else round(ref_ms / ms_per_step, 3),
+        "speedup_vs_plain_fp64": None if ref_ms is None else round(ref_ms / ms_per_step, 3),
         "gate": gate,
         "mlp_vs_bound": mlp_vs_bound,
         "useful_tflop_per_solve": round(useful / 1e12, 4),

@@ -139,6 +139,8 @@ struct PanelArgs {
   const int* tile_rp;     // nc+1
   int* tile_p;
   int* tile_q;
+  unsigned* tile_bits;    // nc x tile_words: cluster bitmap of pass 0 for pass 1
+  int tile_words;         // (max_sys_clusters + 31) / 32
 };
 
 struct TileArgs {

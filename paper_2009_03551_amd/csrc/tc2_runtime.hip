@@ -150,6 +150,7 @@ struct tc2_ctx {
   long long kept_prev = 0, kept_prev2 = 0;  // kept upper blocks of the last updates
   int graph_updates = 0, graph_captures = 0;
   DBuf panel_cnt, panel_rp, panel_k, panel_e, tile_cnt, tile_rp, tile_pairs, tile_p, tile_q;
+  DBuf tile_bits;                 // cluster bitmaps kept between the two tile passes
   // results
   std::vector<HostBsr> out_x0;
   std::vector<HostBsr> out_x1[MAXD];
@@ -760,6 +761,9 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     pa.tile_cnt = ctx->tile_cnt.as<int>();
     pa.tile_pairs = ctx->tile_pairs.as<long long>();
     pa.tile_rp = ctx->tile_rp.as<int>();
+    pa.tile_words = (ctx->max_sys_clusters + 31) / 32;
+    HIPCHK(ctx->tile_bits.reserve((size_t)std::max(nc, 1) * pa.tile_words * 4));
+    pa.tile_bits = ctx->tile_bits.as<unsigned>();
     launch_panels(st, 0, pa);
     launch_scan(st, nc, ctx->panel_cnt.as<int>(), ctx->panel_rp.as<int>(), cnt);
     HIPCHK(hipMemcpyAsync(hcnt, cnt, 4, hipMemcpyDeviceToHost, st));
@@ -1138,6 +1142,8 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     HIPCHK(ctx->tile_cnt.reserve((size_t)nc * 4));
     HIPCHK(ctx->tile_rp.reserve((size_t)(nc + 1) * 4));
     HIPCHK(ctx->tile_pairs.reserve((size_t)nc * 8));
+    const int tile_words = (ctx->max_sys_clusters + 31) / 32;
+    HIPCHK(ctx->tile_bits.reserve((size_t)std::max(nc, 1) * tile_words * 4));
     HIPCHK(ctx->panel_k.reserve((size_t)std::max<long long>(nnz_c, 1) * 4));
     HIPCHK(ctx->panel_e.reserve((size_t)std::max<long long>(nnz_c, 1) * CS * 4));
     HIPCHK(ctx->tile_p.reserve((size_t)std::max<long long>(ctx->tile_bound, 1) * 4));
@@ -1177,7 +1183,8 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
         (uintptr_t)ctx->counters.p, (uintptr_t)ctx->screened.p, (uintptr_t)ctx->exec_pairs.p,
         (uintptr_t)ctx->rowcnt.p, (uintptr_t)ctx->cursor.p, (uintptr_t)ctx->sys_lo.p,
         (uintptr_t)ctx->sys_hi.p, (uintptr_t)ctx->panel_cnt.p, (uintptr_t)ctx->panel_rp.p,
-        (uintptr_t)ctx->tile_cnt.p, (uintptr_t)ctx->tile_rp.p, (uintptr_t)ctx->tile_pairs.p};
+        (uintptr_t)ctx->tile_cnt.p, (uintptr_t)ctx->tile_rp.p, (uintptr_t)ctx->tile_pairs.p,
+        (uintptr_t)ctx->tile_bits.p};
     // the three parts of the update, as stream work (captured or not)
     auto rec_pre = [&]() {
       PanelArgs pa{};
@@ -1203,6 +1210,8 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       pa.panel_e = ctx->panel_e.as<int>();
       pa.tile_p = ctx->tile_p.as<int>();
       pa.tile_q = ctx->tile_q.as<int>();
+      pa.tile_bits = ctx->tile_bits.as<unsigned>();
+      pa.tile_words = tile_words;
       launch_panels(st, 0, pa);
       launch_scan(st, nc, ctx->panel_cnt.as<int>(), ctx->panel_rp.as<int>(), cnt);
       launch_panels(st, 1, pa);

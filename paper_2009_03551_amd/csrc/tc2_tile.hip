@@ -15,10 +15,27 @@ namespace tc2 {
 
 // ------------------------------------------------------------------ cluster panels
 // Panel of cluster P: sorted union of the columns of its atoms' rows, with the
-// entry index of (I_s, K) for every member s (-1 when absent).
-__global__ __launch_bounds__(256) void k_panels(int pass, PanelArgs a) {
-  extern __shared__ unsigned sbits[];
-  __shared__ int sscan[256];
+// entry index of (I_s, K) for every member s (-1 when absent).  The union is
+// an LDS bitmap over the system's atoms; pass 1 ranks each member entry in it
+// (prefix popcounts), so no search is needed.
+constexpr int PNT = 1024;  // threads of the panel and tile kernels
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* ssc) {
+  const int t = threadIdx.x;
+  ssc[t] = v;
+  __syncthreads();
+  for (int o = 1; o < PNT; o <<= 1) {
+    const int u = (t >= o) ? ssc[t - o] : 0;
+    __syncthreads();
+    ssc[t] += u;
+    __syncthreads();
+  }
+  return ssc[t] - v;  // ssc[PNT-1] holds the total
+}
+
+__global__ __launch_bounds__(PNT) void k_panels(int pass, PanelArgs a) {
+  extern __shared__ unsigned sbits[];  // nwords bits, then nwords prefix counts
+  __shared__ int sscan[PNT];
   const int P = blockIdx.x;
   const int sys = a.clus_sys[P];
   const int t = threadIdx.x;
@@ -28,63 +45,61 @@ __global__ __launch_bounds__(256) void k_panels(int pass, PanelArgs a) {
   }
   const int lo = a.sys_start[sys], nbits = a.sys_end[sys] - lo;
   const int nwords = (nbits + 31) >> 5;
-  for (int w = t; w < nwords; w += blockDim.x) sbits[w] = 0u;
+  unsigned* pre = sbits + nwords;
+  for (int w = t; w < nwords; w += PNT) sbits[w] = 0u;
   __syncthreads();
   for (int s = 0; s < CS; ++s) {
     const int I = a.clus_atom[P * CS + s];
     if (I < 0) continue;
-    for (int e = a.rp[I] + t; e < a.rp[I + 1]; e += blockDim.x) {
+    for (int e = a.rp[I] + t; e < a.rp[I + 1]; e += PNT) {
       const int o = a.ci[e] - lo;
       atomicOr(&sbits[o >> 5], 1u << (o & 31));
     }
   }
   __syncthreads();
-  const int per = (nwords + blockDim.x - 1) / blockDim.x;
+  const int per = (nwords + PNT - 1) / PNT;
   const int w0 = t * per, w1 = min(nwords, w0 + per);
   int cnt = 0;
   for (int w = w0; w < w1; ++w) cnt += __popc(sbits[w]);
-  sscan[t] = cnt;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const int v = (t >= o) ? sscan[t - o] : 0;
-    __syncthreads();
-    sscan[t] += v;
-    __syncthreads();
-  }
+  const int before = block_exclusive_scan(cnt, sscan);
   if (pass == 0) {
-    if (t == 255) a.panel_cnt[P] = sscan[255];
+    if (t == PNT - 1) a.panel_cnt[P] = sscan[PNT - 1];
     return;
   }
-  int pos = a.panel_rp[P] + sscan[t] - cnt;
+  const int base = a.panel_rp[P];
+  int run = before;
   for (int w = w0; w < w1; ++w) {
+    pre[w] = run;
     unsigned x = sbits[w];
     while (x) {
       const int bit = __ffs(x) - 1;
       x &= x - 1;
-      const int K = lo + (w << 5) + bit;
-      a.panel_k[pos] = K;
-      for (int s = 0; s < CS; ++s) {
-        const int I = a.clus_atom[P * CS + s];
-        int e = -1;
-        if (I >= 0) {
-          const int r0 = a.rp[I];
-          const int f = bsearch_eq(a.ci + r0, a.rp[I + 1] - r0, K);
-          e = f >= 0 ? r0 + f : -1;
-        }
-        a.panel_e[(size_t)pos * CS + s] = e;
-      }
-      ++pos;
+      const int pos = base + run++;
+      a.panel_k[pos] = lo + (w << 5) + bit;
+#pragma unroll
+      for (int s = 0; s < CS; ++s) a.panel_e[(size_t)pos * CS + s] = -1;
+    }
+  }
+  __syncthreads();  // ranks in LDS and the -1 fill precede the entry writes
+  for (int s = 0; s < CS; ++s) {
+    const int I = a.clus_atom[P * CS + s];
+    if (I < 0) continue;
+    for (int e = a.rp[I] + t; e < a.rp[I + 1]; e += PNT) {
+      const int o = a.ci[e] - lo, w = o >> 5;
+      const int rank = (int)pre[w] + __popc(sbits[w] & ((1u << (o & 31)) - 1u));
+      a.panel_e[(size_t)(base + rank) * CS + s] = e;
     }
   }
 }
 
 // Tiles of cluster P: the clusters Q >= P holding an atom J with a column K in
-// common with some atom of P (cluster-level symbolic product).  Pass 0 also
-// bounds the number of output blocks of those tiles.
-__global__ __launch_bounds__(256) void k_tiles(int pass, PanelArgs a) {
+// common with some atom of P (cluster-level symbolic product).  Pass 0 builds
+// the cluster bitmap, keeps it in tile_bits and bounds the number of output
+// blocks of the tiles; pass 1 writes the tiles from the kept bitmap.
+__global__ __launch_bounds__(PNT) void k_tiles(int pass, PanelArgs a) {
   extern __shared__ unsigned sbits[];
-  __shared__ int sscan[256];
-  __shared__ long long spairs[256];
+  __shared__ int sscan[PNT];
+  __shared__ long long spairs[PNT];
   const int P = blockIdx.x;
   const int sys = a.clus_sys[P];
   const int t = threadIdx.x;
@@ -97,25 +112,31 @@ __global__ __launch_bounds__(256) void k_tiles(int pass, PanelArgs a) {
   }
   const int nbits = a.csys_end[sys] - P;
   const int nwords = (nbits + 31) >> 5;
-  for (int w = t; w < nwords; w += blockDim.x) sbits[w] = 0u;
-  __syncthreads();
-  const int wave = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
-  for (int idx = a.panel_rp[P] + wave; idx < a.panel_rp[P + 1]; idx += nw) {
-    const int K = a.panel_k[idx];
-    for (int f = a.rp[K] + lane; f < a.rp[K + 1]; f += 64) {
-      const int Q = a.atom_clus[a.ci[f]];
-      if (Q >= P) {
-        const int o = Q - P;
-        atomicOr(&sbits[o >> 5], 1u << (o & 31));
+  unsigned* gbits = a.tile_bits + (size_t)P * a.tile_words;
+  if (pass == 0) {
+    for (int w = t; w < nwords; w += PNT) sbits[w] = 0u;
+    __syncthreads();
+    const int wave = t >> 6, lane = t & 63, nw = PNT >> 6;
+    for (int idx = a.panel_rp[P] + wave; idx < a.panel_rp[P + 1]; idx += nw) {
+      const int K = a.panel_k[idx];
+      for (int f = a.rp[K] + lane; f < a.rp[K + 1]; f += 64) {
+        const int Q = a.atom_clus[a.ci[f]];
+        if (Q >= P) {
+          const int o = Q - P;
+          atomicOr(&sbits[o >> 5], 1u << (o & 31));
+        }
       }
     }
+    __syncthreads();
+    for (int w = t; w < nwords; w += PNT) gbits[w] = sbits[w];
+  } else {
+    for (int w = t; w < nwords; w += PNT) sbits[w] = gbits[w];
+    __syncthreads();
   }
-  __syncthreads();
-  const int per = (nwords + blockDim.x - 1) / blockDim.x;
+  const int per = (nwords + PNT - 1) / PNT;
   const int w0 = t * per, w1 = min(nwords, w0 + per);
   int cnt = 0;
   for (int w = w0; w < w1; ++w) cnt += __popc(sbits[w]);
-  sscan[t] = cnt;
   if (pass == 0) {
     int nP = 0;
     for (int s = 0; s < CS; ++s) nP += a.clus_atom[P * CS + s] >= 0;
@@ -131,11 +152,10 @@ __global__ __launch_bounds__(256) void k_tiles(int pass, PanelArgs a) {
         pairs += (Q == P) ? (long long)nP * (nP + 1) / 2 : (long long)nP * nQ;
       }
     }
+    sscan[t] = cnt;
     spairs[t] = pairs;
-  }
-  __syncthreads();
-  if (pass == 0) {
-    for (int o = 128; o > 0; o >>= 1) {
+    __syncthreads();
+    for (int o = PNT / 2; o > 0; o >>= 1) {
       if (t < o) {
         sscan[t] += sscan[t + o];
         spairs[t] += spairs[t + o];
@@ -148,13 +168,7 @@ __global__ __launch_bounds__(256) void k_tiles(int pass, PanelArgs a) {
     }
     return;
   }
-  for (int o = 1; o < 256; o <<= 1) {
-    const int v = (t >= o) ? sscan[t - o] : 0;
-    __syncthreads();
-    sscan[t] += v;
-    __syncthreads();
-  }
-  int pos = a.tile_rp[P] + sscan[t] - cnt;
+  int pos = a.tile_rp[P] + block_exclusive_scan(cnt, sscan);
   for (int w = w0; w < w1; ++w) {
     unsigned x = sbits[w];
     while (x) {
@@ -749,14 +763,14 @@ void launch_block_norms(hipStream_t st, int prec, long long nnz, int D, const vo
 // ================================================================== launchers
 void launch_panels(hipStream_t st, int pass, const PanelArgs& a) {
   if (a.nc == 0) return;
-  const size_t lds = (size_t)((a.max_sys_atoms + 31) / 32) * 4;
-  hipLaunchKernelGGL(k_panels, dim3(a.nc), dim3(256), lds, st, pass, a);
+  const size_t lds = (size_t)((a.max_sys_atoms + 31) / 32) * 8;  // bitmap + prefix counts
+  hipLaunchKernelGGL(k_panels, dim3(a.nc), dim3(PNT), lds, st, pass, a);
 }
 
 void launch_tiles(hipStream_t st, int pass, const PanelArgs& a) {
   if (a.nc == 0) return;
-  const size_t lds = (size_t)((a.max_sys_clusters + 31) / 32) * 4;
-  hipLaunchKernelGGL(k_tiles, dim3(a.nc), dim3(256), lds, st, pass, a);
+  const size_t lds = (size_t)a.tile_words * 4;
+  hipLaunchKernelGGL(k_tiles, dim3(a.nc), dim3(PNT), lds, st, pass, a);
 }
 
 // Sub-tile shapes (rows of cluster P x columns of cluster Q per workgroup).
