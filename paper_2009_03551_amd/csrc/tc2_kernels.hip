@@ -450,17 +450,30 @@ __global__ __launch_bounds__(256) void k_row_sort(CompactArgs a) {
 template <typename T>
 __global__ void k_gather(long long n, int D, const int* new_src, const T* stage, T* xv,
                          const int* nnz_dev) {
+  // four consecutive elements per thread: one column segment (c, r..r+3) of a
+  // column-major tile, a 4-vector store; the source is the same segment of
+  // the stage (mirrored entry) or four rows of one column (transpose)
+  typedef T T4 __attribute__((ext_vector_type(4)));
   const int per = (1 + D) * BS;
   if (nnz_dev) n = min(n, (long long)*nnz_dev * per);
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
-       idx += (long long)gridDim.x * blockDim.x) {
-    long long e = idx / per;
-    int rem = (int)(idx - e * per);
-    int m = rem / BS, qd = rem - m * BS;
-    int src = new_src[e];
-    int slot = src >> 1;
-    int qs = (src & 1) ? qd : ((qd & 15) * BP + (qd >> 4));
-    xv[idx] = stage[(size_t)slot * per + m * BS + qs];
+  const long long n4 = n >> 2;
+  for (long long i4 = (long long)blockIdx.x * blockDim.x + threadIdx.x; i4 < n4;
+       i4 += (long long)gridDim.x * blockDim.x) {
+    const long long idx = i4 << 2;
+    const long long e = idx / per;
+    const int rem = (int)(idx - e * per);
+    const int m = rem / BS, qd = rem - m * BS;  // qd = c*16 + r, r % 4 == 0
+    const int src = new_src[e];
+    const T* sb = stage + (size_t)(src >> 1) * per + m * BS;
+    T4 v;
+    if (src & 1) {
+      v = *(const T4*)(sb + qd);
+    } else {
+      const int c = qd >> 4, r = qd & 15;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = sb[(r + i) * BP + c];
+    }
+    *(T4*)(xv + idx) = v;
   }
 }
 
@@ -636,10 +649,10 @@ void launch_gather(hipStream_t st, int prec, int nnz, int D, const int* new_src,
   long long n = (long long)nnz * (1 + D) * BS;
   if (n == 0) return;
   if (prec == P_FP64)
-    hipLaunchKernelGGL(k_gather<double>, dim3(sblk(n, 256)), dim3(256), 0, st, n, D, new_src,
+    hipLaunchKernelGGL(k_gather<double>, dim3(sblk(n / 4, 256)), dim3(256), 0, st, n, D, new_src,
                        (const double*)stage, (double*)xv, nnz_dev);
   else
-    hipLaunchKernelGGL(k_gather<float>, dim3(sblk(n, 256)), dim3(256), 0, st, n, D, new_src,
+    hipLaunchKernelGGL(k_gather<float>, dim3(sblk(n / 4, 256)), dim3(256), 0, st, n, D, new_src,
                        (const float*)stage, (float*)xv, nnz_dev);
 }
 

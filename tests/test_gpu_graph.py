@@ -73,3 +73,25 @@ def test_graph_repeated_runs_are_bitwise_identical():
     solver.close()
     same(a, b)
     assert a.graph_updates == a.iters and b.graph_updates == b.iters
+
+
+@pytest.mark.parametrize("case", ["single_atom", "max_iter", "replay", "ragged_chain", "mixed_batch"])
+def test_graph_edge_cases(case):
+    # the graph path on the inputs the parity tests use for edge cases
+    if case == "single_atom":
+        systems, kw = W.config_system("chain64", n=1), {}
+    elif case == "max_iter":
+        s = W.config_system("chain64", n=16)
+        s.max_iter = 3
+        systems, kw = s, {}
+    elif case == "replay":
+        systems, kw = W.config_system("chain64", n=20), dict(replay=["SDSDDSDSDSDS"])
+    elif case == "ragged_chain":
+        systems, kw = W.config_system("chain64", n=23, b=5), {}
+    else:
+        # a trivial system (N_occ = N) next to iterating ones of different sizes
+        a = W.config_system("chain64", n=6)
+        a.n_occ = a.H.n
+        systems, kw = [a, W.config_system("chain64", n=17), W.config_system("chain64", n=30)], {}
+    ref, got = both(systems, **kw)
+    assert any(g.graph_updates > 0 for g in got) or all(r.iters == 0 for r in ref)
