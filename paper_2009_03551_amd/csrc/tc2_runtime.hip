@@ -1101,6 +1101,23 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
 // long as the buffers, sizes and kernel choice it captured are unchanged.
 // Returns TC2_OK, an error, or 1 when the runtime refused the capture (the
 // caller then runs the update without a graph).
+// A graph-mode buffer that cannot be allocated (its bounds are looser than
+// the exact sizes of the update without a graph) switches the context back
+// to updates without graphs; only buffers of the next iterate and work
+// buffers are reserved here, never the current iterate.
+#define GRESERVE(x)                                                      \
+  do {                                                                   \
+    hipError_t e_ = (x);                                                 \
+    if (e_ == hipErrorOutOfMemory) {                                     \
+      (void)hipGetLastError();                                           \
+      for (DBuf* b_ : {&ctx->stage, &ctx->kept_ij, &ctx->tmp_ci, &ctx->tmp_src, \
+                       &ctx->new_src, &ctx->ci[n], &ctx->xv[n]})           \
+        b_->release();                                                   \
+      return 1;                                                          \
+    }                                                                    \
+    if (e_ != hipSuccess) return TC2_EDEVICE;                            \
+  } while (0)
+
 int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
                unsigned long long& exec_pairs_total) {
   const int c = ctx->cur, n = c ^ 1;
@@ -1135,38 +1152,38 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   int nnz_new = 0;
   for (int attempt = 0;; ++attempt) {
     const int cap = (int)est;
-    HIPCHK(ctx->counters.reserve(64));
-    HIPCHK(ctx->exec_pairs.reserve(8));
-    HIPCHK(ctx->panel_cnt.reserve((size_t)nc * 4));
-    HIPCHK(ctx->panel_rp.reserve((size_t)(nc + 1) * 4));
-    HIPCHK(ctx->tile_cnt.reserve((size_t)nc * 4));
-    HIPCHK(ctx->tile_rp.reserve((size_t)(nc + 1) * 4));
-    HIPCHK(ctx->tile_pairs.reserve((size_t)nc * 8));
+    GRESERVE(ctx->counters.reserve(64));
+    GRESERVE(ctx->exec_pairs.reserve(8));
+    GRESERVE(ctx->panel_cnt.reserve((size_t)nc * 4));
+    GRESERVE(ctx->panel_rp.reserve((size_t)(nc + 1) * 4));
+    GRESERVE(ctx->tile_cnt.reserve((size_t)nc * 4));
+    GRESERVE(ctx->tile_rp.reserve((size_t)(nc + 1) * 4));
+    GRESERVE(ctx->tile_pairs.reserve((size_t)nc * 8));
     const int tile_words = (ctx->max_sys_clusters + 31) / 32;
-    HIPCHK(ctx->tile_bits.reserve((size_t)std::max(nc, 1) * tile_words * 4));
-    HIPCHK(ctx->panel_k.reserve((size_t)std::max<long long>(nnz_c, 1) * 4));
-    HIPCHK(ctx->panel_e.reserve((size_t)std::max<long long>(nnz_c, 1) * CS * 4));
-    HIPCHK(ctx->tile_p.reserve((size_t)std::max<long long>(ctx->tile_bound, 1) * 4));
-    HIPCHK(ctx->tile_q.reserve((size_t)std::max<long long>(ctx->tile_bound, 1) * 4));
-    HIPCHK(ctx->partial.reserve((size_t)std::max(ctx->tile_bound * 4, (long long)nb) * NQ * 8));
-    HIPCHK(ctx->sys_lo.reserve((size_t)ctx->nsys * 4));
-    HIPCHK(ctx->sys_hi.reserve((size_t)ctx->nsys * 4));
+    GRESERVE(ctx->tile_bits.reserve((size_t)std::max(nc, 1) * tile_words * 4));
+    GRESERVE(ctx->panel_k.reserve((size_t)std::max<long long>(nnz_c, 1) * 4));
+    GRESERVE(ctx->panel_e.reserve((size_t)std::max<long long>(nnz_c, 1) * CS * 4));
+    GRESERVE(ctx->tile_p.reserve((size_t)std::max<long long>(ctx->tile_bound, 1) * 4));
+    GRESERVE(ctx->tile_q.reserve((size_t)std::max<long long>(ctx->tile_bound, 1) * 4));
+    GRESERVE(ctx->partial.reserve((size_t)std::max(ctx->tile_bound * 4, (long long)nb) * NQ * 8));
+    GRESERVE(ctx->sys_lo.reserve((size_t)ctx->nsys * 4));
+    GRESERVE(ctx->sys_hi.reserve((size_t)ctx->nsys * 4));
     if (screen) {
-      HIPCHK(ctx->bn.reserve((size_t)cap_c * (1 + D) * 4));
-      HIPCHK(ctx->screened.reserve(16));
+      GRESERVE(ctx->bn.reserve((size_t)cap_c * (1 + D) * 4));
+      GRESERVE(ctx->screened.reserve(16));
     }
-    HIPCHK(ctx->stage.reserve((size_t)cap * tile));
-    HIPCHK(ctx->kept_ij.reserve((size_t)cap * 8));
-    HIPCHK(ctx->rowcnt.reserve((size_t)nb * 4));
-    HIPCHK(ctx->cursor.reserve((size_t)nb * 4));
-    HIPCHK(ctx->rp[n].reserve((size_t)(nb + 1) * 4));
+    GRESERVE(ctx->stage.reserve((size_t)cap * tile));
+    GRESERVE(ctx->kept_ij.reserve((size_t)cap * 8));
+    GRESERVE(ctx->rowcnt.reserve((size_t)nb * 4));
+    GRESERVE(ctx->cursor.reserve((size_t)nb * 4));
+    GRESERVE(ctx->rp[n].reserve((size_t)(nb + 1) * 4));
     const size_t cap2 = (size_t)2 * cap;
-    HIPCHK(ctx->tmp_ci.reserve(cap2 * 4));
-    HIPCHK(ctx->tmp_src.reserve(cap2 * 4));
-    HIPCHK(ctx->new_src.reserve(cap2 * 4));
-    HIPCHK(ctx->ci[n].reserve(cap2 * 4));
-    HIPCHK(ctx->xv[n].reserve(cap2 * tile));
-    HIPCHK(ctx->scal.reserve((size_t)ctx->nsys * NQ * 8));
+    GRESERVE(ctx->tmp_ci.reserve(cap2 * 4));
+    GRESERVE(ctx->tmp_src.reserve(cap2 * 4));
+    GRESERVE(ctx->new_src.reserve(cap2 * 4));
+    GRESERVE(ctx->ci[n].reserve(cap2 * 4));
+    GRESERVE(ctx->xv[n].reserve(cap2 * tile));
+    GRESERVE(ctx->scal.reserve((size_t)ctx->nsys * NQ * 8));
     int* cnt = ctx->counters.as<int>();  // [1] stage count [2] overflow [4] work counter
 
     // what the graph captures: everything that would change a launch
