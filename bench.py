@@ -131,6 +131,55 @@ def cpu_baseline(sysm, gpu_iters: int, useful_flops: float, iters_sample: int = 
                       f"(N={sysm.H.n}), {dt:.1f} s each, scaled by {gpu_iters} updates"}
 
 
+def crossover(args) -> int:
+    """Seconds per solve of the linear-scaling path (plain FP64, and the default
+    variant) and of the dense O(N^3) path over a series of system sizes, with
+    the polarizability traces of both (the crossover experiment of Sec. 4)."""
+    import torch
+    from paper_2009_03551_amd import tc2 as T
+    from paper_2009_03551_amd import workloads as W
+
+    stream = torch.cuda.current_stream().cuda_stream
+    if args.crossover == "cube":
+        sizes = [int(x) for x in (args.sizes or "4,5,6,7,8,10,12").split(",")]
+        make = lambda n: W.config_system("cube10", L=n)
+    else:
+        sizes = [int(x) for x in (args.sizes or "256,512,1024,2048").split(",")]
+        make = lambda n: W.config_system("chain64", n=n)
+    variants = {"tc2_fp64": dict(precision="fp64", skip="bound", graph=True),
+                "tc2_default": dict(precision="fp32", wide=True, fp64_first=args.fp64_first,
+                                    closing_fp64=2, skip="bound", graph=True)}
+    for n in sizes:
+        s = make(n)
+        line = {"mode": "crossover", "series": args.crossover, "size": n, "atoms": s.H.nb,
+                "N": s.H.n, "b": s.H.b, "dirs": len(s.H1), "eps": s.eps}
+        for name, kw in variants.items():
+            solver = T.Solver(s, export=False, **kw)
+            for _ in range(args.warmup):
+                solver.run(stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                r = solver.run(stream=stream)[0]
+            torch.cuda.synchronize()
+            line[name + "_s"] = (time.perf_counter() - t0) / args.steps
+            line[name + "_alpha"] = r.alpha[0] if r.alpha else None
+            solver.close()
+        T.dense_response(s, stream=stream)  # warm-up (library kernels, workspace)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d = T.dense_response(s, stream=stream)
+        torch.cuda.synchronize()
+        line.update(dense_s=time.perf_counter() - t0, dense_device_s=d.seconds,
+                    dense_ms_eigh=d.ms_eigh, dense_ms_p0=d.ms_p0, dense_ms_p1=d.ms_p1,
+                    dense_p1_tflops=(d.flops_p1 / (d.ms_p1 * 1e-3) / 1e12) if d.ms_p1 > 0 else None,
+                    dense_alpha=d.alpha[0] if d.alpha else None, gap=d.gap)
+        if d.alpha:
+            line["rel_dalpha_fp64"] = abs(line["tc2_fp64_alpha"] - d.alpha[0]) / abs(d.alpha[0])
+        print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +212,12 @@ def main() -> int:
                     help="skip the plain FP64 runs and the gate (profiling the chosen variant alone)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--crossover", choices=["cube", "chain"], default=None,
+                    help="only time the linear-scaling path against the dense O(N^3) path "
+                         "over a series of sizes (one JSON line per size)")
+    ap.add_argument("--sizes", default=None,
+                    help="crossover sizes: lattice edges (cube) or atom counts (chain), "
+                         "comma-separated")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has "
@@ -180,6 +235,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration, 10)
+    if args.crossover:
+        return crossover(args)
     stream = torch.cuda.current_stream().cuda_stream
 
     # workload -> units: lists of systems solved in one context (one merged

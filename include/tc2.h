@@ -241,6 +241,76 @@ TC2_API tc2_status tc2_mlp_train(const float *x, const float *y, int64_t n,
                                  const tc2_mlp_train_opts *opts, float *theta,
                                  double *loss_per_epoch);
 
+/* ---------------------------------------------------------------------------
+ * Dense O(N^3) density matrix and response (Sec. 2.1, the O(N^3) method): the
+ * reference against which the linear-scaling path is timed in the crossover
+ * experiment of Sec. 4.
+ *
+ * The method, in the orthonormal basis (S = I):
+ *  - H, densified, is diagonalised as H C = C E.
+ *  - P0 = C_occ C_occ^T over the n_occ lowest states.
+ *  - For each direction d, the coefficient response is C1 = C U.  Its
+ *    elements are U_pq = -(C^T H1_d C)_pq / (e_p - e_q) for p != q
+ *    (Eq. cpscf-LCAO) and U_pp = 0.
+ *  - P1_d = sum over occupied i of (C1_i C_i^T + C_i C1_i^T) (Eq. DM1).
+ *
+ * The occupied-occupied terms of P1_d cancel. It is therefore formed as
+ *     G = C_virt^T (H1_d C_occ),   M_ai = G_ai / (e_i - e_a),
+ *     Y = C_virt M,                P1_d = Y C_occ^T + C_occ Y^T.
+ *
+ * Traces are taken over the stored blocks of H and H1_d.
+ *
+ * Device work:
+ *  - rocSOLVER dsyevd for the eigenpairs;
+ *  - rocBLAS for the products (dsyrk, dgemm, dsyr2k);
+ *  - HIP kernels for densifying, the gap scaling, mirroring and the traces.
+ *
+ * The problem must pass the checks of tc2_setup. Its eps_drop, tol, max_iter,
+ * replay and xyz fields are not used.
+ *
+ * Edge cases: n_occ = 0 gives P0 = 0, and n_occ = N gives P0 = I; both give
+ * P1_d = 0 and gap = 0, without computing eigenpairs (eigenvalues is not
+ * written).
+ *
+ * Host buffers in the options are owned by the caller. The device memory is
+ * about 3 N^2 doubles plus the solver's workspace; it is allocated and freed
+ * within the call.
+ *
+ * Errors:
+ *  - TC2_EINVAL: NULL arguments, ranges, N > TC2_DENSE_MAX_N;
+ *  - TC2_ENONSYM, TC2_ENAN: the checks of tc2_setup;
+ *  - TC2_EDEGENERATE: the highest occupied and lowest virtual eigenvalues
+ *    coincide, so P0 is not defined;
+ *  - TC2_EDEVICE: the eigensolver did not converge, or a HIP/ROCm call failed;
+ *  - TC2_ENOMEM.
+ * ------------------------------------------------------------------------- */
+#define TC2_DENSE_MAX_N 40000
+
+typedef struct {
+  int32_t device;          /* HIP device ordinal                                */
+  void *hip_stream;        /* hipStream_t to run on; NULL: a stream of the call */
+  double *p0;              /* NULL, or N*N host doubles receiving P0 (symmetric) */
+  double *p1[3];           /* NULL, or N*N host doubles per direction: P1_d      */
+  double *eigenvalues;     /* NULL, or N host doubles: e, ascending              */
+} tc2_dense_options;
+
+typedef struct {
+  tc2_status status;
+  double e0;               /* Tr(P0 H)                                           */
+  double e1[3];            /* Tr(P1_d H)                                         */
+  double trace_p1h1[3];    /* Tr(P1_d H1_d), the polarizability trace            */
+  double tr_p0;            /* Tr P0 (= n_occ up to rounding)                    */
+  double gap;              /* e_lowest virtual - e_highest occupied              */
+  double seconds;          /* device time from the densified H to the traces     */
+  double ms_eigh;          /* phase times (ms): eigenpairs, P0, all P1_d         */
+  double ms_p0, ms_p1;
+  double flops_p1;         /* nominal flops of the P1 products, all directions  */
+} tc2_dense_result;
+
+TC2_API tc2_status tc2_dense_response(const tc2_problem *problem,
+                                      const tc2_dense_options *opts,
+                                      tc2_dense_result *res);
+
 #ifdef __cplusplus
 }
 #endif

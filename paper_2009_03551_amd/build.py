@@ -8,8 +8,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtc2.so")
-SOURCES = ["tc2_kernels.hip", "tc2_tile.hip", "tc2_mlp.hip", "tc2_runtime.hip"]
+SOURCES = ["tc2_kernels.hip", "tc2_tile.hip", "tc2_mlp.hip", "tc2_runtime.hip", "tc2_dense.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# the dense O(N^3) path: eigenpairs (rocSOLVER) and products (rocBLAS)
+LIBS = ["-lrocsolver", "-lrocblas"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions in the device code
@@ -22,7 +24,7 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source into ``libtc2.so``; returns its path."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *srcs]
+    cmd = [HIPCC, *FLAGS, "-o", tmp, *srcs, *LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -6,6 +6,7 @@
 // one merged kernel sequence per update, and applies the stopping rule of
 // Sec. 2.3 (band-energy change below the tolerance) per system.
 #include "tc2_internal.h"
+#include "tc2_host.h"
 #include "../../include/tc2.h"
 
 #include <algorithm>
@@ -170,38 +171,6 @@ namespace {
 
 size_t prec_bytes(int prec) { return prec == P_FP64 ? 8 : 4; }
 
-tc2_status validate_bsr(const tc2_bsr& m, int nb, int b) {
-  if (m.nb != nb || m.b != b) return TC2_EINVAL;
-  if (!m.row_ptr || (!m.col && m.row_ptr[nb] > 0) || (!m.val && m.row_ptr[nb] > 0)) return TC2_EINVAL;
-  if (m.row_ptr[0] != 0) return TC2_EINVAL;
-  for (int i = 0; i < nb; ++i) {
-    if (m.row_ptr[i + 1] < m.row_ptr[i]) return TC2_EINVAL;
-    for (int64_t p = m.row_ptr[i]; p < m.row_ptr[i + 1]; ++p) {
-      if (m.col[p] < 0 || m.col[p] >= nb) return TC2_EINVAL;
-      if (p > m.row_ptr[i] && m.col[p] <= m.col[p - 1]) return TC2_EINVAL;
-    }
-  }
-  if (m.row_ptr[nb] > (int64_t)0x7fffffff / 2) return TC2_EOVERFLOW;
-  // symmetric pattern
-  for (int i = 0; i < nb; ++i)
-    for (int64_t p = m.row_ptr[i]; p < m.row_ptr[i + 1]; ++p) {
-      int j = m.col[p];
-      const int32_t* b0 = m.col + m.row_ptr[j];
-      const int32_t* b1 = m.col + m.row_ptr[j + 1];
-      if (!std::binary_search(b0, b1, i)) return TC2_ENONSYM;
-    }
-  int64_t nv = m.row_ptr[nb] * (int64_t)b * b;
-  for (int64_t k = 0; k < nv; ++k)
-    if (!std::isfinite(m.val[k])) return TC2_ENAN;
-  return TC2_OK;
-}
-
-bool has_diag(const tc2_bsr& m, int nb) {
-  for (int i = 0; i < nb; ++i)
-    if (!std::binary_search(m.col + m.row_ptr[i], m.col + m.row_ptr[i + 1], i)) return false;
-  return true;
-}
-
 // padded, column-major device image of a batch of BSR matrices (FP64)
 void pack_blocks(const tc2_bsr& m, int b, std::vector<double>& out) {
   int64_t nnz = m.row_ptr[m.nb];
@@ -235,6 +204,55 @@ void merge_pattern(const std::vector<const tc2_bsr*>& ms, const std::vector<SysI
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ host checks
+namespace tc2 {
+
+tc2_status validate_bsr(const tc2_bsr& m, int nb, int b) {
+  if (m.nb != nb || m.b != b) return TC2_EINVAL;
+  if (!m.row_ptr || (!m.col && m.row_ptr[nb] > 0) || (!m.val && m.row_ptr[nb] > 0)) return TC2_EINVAL;
+  if (m.row_ptr[0] != 0) return TC2_EINVAL;
+  for (int i = 0; i < nb; ++i) {
+    if (m.row_ptr[i + 1] < m.row_ptr[i]) return TC2_EINVAL;
+    for (int64_t p = m.row_ptr[i]; p < m.row_ptr[i + 1]; ++p) {
+      if (m.col[p] < 0 || m.col[p] >= nb) return TC2_EINVAL;
+      if (p > m.row_ptr[i] && m.col[p] <= m.col[p - 1]) return TC2_EINVAL;
+    }
+  }
+  if (m.row_ptr[nb] > (int64_t)0x7fffffff / 2) return TC2_EOVERFLOW;
+  // symmetric pattern
+  for (int i = 0; i < nb; ++i)
+    for (int64_t p = m.row_ptr[i]; p < m.row_ptr[i + 1]; ++p) {
+      int j = m.col[p];
+      const int32_t* b0 = m.col + m.row_ptr[j];
+      const int32_t* b1 = m.col + m.row_ptr[j + 1];
+      if (!std::binary_search(b0, b1, i)) return TC2_ENONSYM;
+    }
+  int64_t nv = m.row_ptr[nb] * (int64_t)b * b;
+  for (int64_t k = 0; k < nv; ++k)
+    if (!std::isfinite(m.val[k])) return TC2_ENAN;
+  return TC2_OK;
+}
+
+bool has_diag(const tc2_bsr& m, int nb) {
+  for (int i = 0; i < nb; ++i)
+    if (!std::binary_search(m.col + m.row_ptr[i], m.col + m.row_ptr[i + 1], i)) return false;
+  return true;
+}
+
+tc2_status select_gfx950(int device, std::string* arch) {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TC2_EDEVICE;
+  if (device < 0 || device >= ndev) return TC2_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return TC2_EDEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return TC2_EDEVICE;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TC2_EDEVICE;
+  if (arch) arch->assign(prop.gcnArchName, strcspn(prop.gcnArchName, ":"));
+  return TC2_OK;
+}
+
+}  // namespace tc2
 
 // ====================================================================== ABI
 extern "C" {
@@ -381,17 +399,8 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   }
   if (nb_tot > (1 << 26) || max_atoms > MAX_SYS_BITS) return TC2_EOVERFLOW;
 
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TC2_EDEVICE;
-  if (o->device < 0 || o->device >= ndev) return TC2_EDEVICE;
-  if (hipSetDevice(o->device) != hipSuccess) return TC2_EDEVICE;
   std::string arch;
-  {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, o->device) != hipSuccess) return TC2_EDEVICE;
-    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TC2_EDEVICE;
-    arch.assign(prop.gcnArchName, strcspn(prop.gcnArchName, ":"));
-  }
+  if (tc2_status st = select_gfx950(o->device, &arch); st != TC2_OK) return st;
 
   ctx = new (std::nothrow) tc2_ctx();
   if (!ctx) return TC2_ENOMEM;

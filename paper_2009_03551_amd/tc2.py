@@ -74,6 +74,14 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "paper_2009_03551_amd.build.build()")
+        # PyTorch ships its own HIP runtime and ROCm libraries.  Loaded first, it
+        # provides them to libtc2.so as well, so that one runtime serves the
+        # process; loaded after libtc2.so had brought in the system copies, its
+        # own runtime would find no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         L.tc2_setup.restype = C.c_int
         L.tc2_setup.argtypes = [C.POINTER(tc2_problem), C.c_int32, C.POINTER(tc2_options),
@@ -91,7 +99,8 @@ def lib() -> C.CDLL:
 
 
 EXPORTED = ("tc2_setup", "tc2_run", "tc2_free", "tc2_strerror", "tc2_version",
-            "tc2_mlp_forward", "tc2_mlp_grad", "tc2_mlp_train", "tc2_log_copy")
+            "tc2_mlp_forward", "tc2_mlp_grad", "tc2_mlp_train", "tc2_log_copy",
+            "tc2_dense_response")
 
 MLP_IN, MLP_PARAMS = 8, 4801
 
@@ -336,3 +345,77 @@ def bsr_dense(m: BSR) -> np.ndarray:
             J = int(m.col[p])
             A[I * b:(I + 1) * b, J * b:(J + 1) * b] = m.val[p]
     return A
+
+
+# ---------------------------------------------------------------- dense O(N^3) path
+DENSE_MAX_N = 40000
+
+
+class tc2_dense_options(C.Structure):
+    _fields_ = [("device", C.c_int32), ("hip_stream", C.c_void_p),
+                ("p0", C.POINTER(C.c_double)), ("p1", C.POINTER(C.c_double) * 3),
+                ("eigenvalues", C.POINTER(C.c_double))]
+
+
+class tc2_dense_result(C.Structure):
+    _fields_ = [("status", C.c_int), ("e0", C.c_double), ("e1", C.c_double * 3),
+                ("trace_p1h1", C.c_double * 3), ("tr_p0", C.c_double), ("gap", C.c_double),
+                ("seconds", C.c_double), ("ms_eigh", C.c_double), ("ms_p0", C.c_double),
+                ("ms_p1", C.c_double), ("flops_p1", C.c_double)]
+
+
+@dataclass
+class DenseResult:
+    status: int
+    e0: float
+    e1: List[float]
+    alpha: List[float]          # Tr(P1_d H1_d)
+    tr_p0: float
+    gap: float
+    seconds: float
+    ms_eigh: float
+    ms_p0: float
+    ms_p1: float
+    flops_p1: float
+    P0: Optional[np.ndarray] = None
+    P1: List[np.ndarray] = field(default_factory=list)
+    eigenvalues: Optional[np.ndarray] = None
+
+
+def dense_response(system: System, export: bool = False, device: int = 0,
+                   stream: Optional[int] = None) -> DenseResult:
+    """P0, P1_d and their traces by diagonalisation (``tc2_dense_response``)."""
+    keep: list = []
+    p = tc2_problem()
+    p.H = _c_bsr(system.H, keep)
+    p.n_dir = len(system.H1)
+    for d, h1 in enumerate(system.H1):
+        p.H1[d] = _c_bsr(h1, keep)
+    p.n_occ = int(system.n_occ)
+    p.eps_drop, p.tol, p.max_iter = float(system.eps), float(system.tol), int(system.max_iter)
+    N = system.H.nb * system.H.b
+    D = len(system.H1)
+    o = tc2_dense_options()
+    o.device = int(device)
+    o.hip_stream = C.c_void_p(stream) if stream else None
+    P0 = P1 = ev = None
+    if export:
+        P0 = np.empty((N, N))
+        P1 = [np.empty((N, N)) for _ in range(D)]
+        ev = np.empty(N)
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        o.p0 = dp(P0)
+        for d in range(D):
+            o.p1[d] = dp(P1[d])
+        o.eigenvalues = dp(ev)
+    r = tc2_dense_result()
+    L = lib()
+    L.tc2_dense_response.restype = C.c_int
+    L.tc2_dense_response.argtypes = [C.POINTER(tc2_problem), C.POINTER(tc2_dense_options),
+                                     C.POINTER(tc2_dense_result)]
+    st = L.tc2_dense_response(C.byref(p), C.byref(o), C.byref(r))
+    if st < 0:
+        raise TC2Error(st, "tc2_dense_response")
+    return DenseResult(r.status, r.e0, list(r.e1[:D]), list(r.trace_p1h1[:D]), r.tr_p0, r.gap,
+                       r.seconds, r.ms_eigh, r.ms_p0, r.ms_p1, r.flops_p1, P0,
+                       P1 if P1 is not None else [], ev)

@@ -121,3 +121,55 @@ def test_valid_problem_needs_a_device():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert _setup_status(small()) == -3
+
+
+# ---------------------------------------------------------------- dense O(N^3) path
+def _dense_status(s):
+    try:
+        return T.dense_response(s).status
+    except T.TC2Error as e:
+        return e.status
+
+
+def test_dense_rejects_malformed_input():
+    s = small()
+    s.n_occ = s.H.n + 1
+    assert _dense_status(s) == -1
+    s = small()
+    s.H.val = s.H.val.copy()
+    s.H.val[0, 0, 0] = np.inf
+    assert _dense_status(s) == -6
+    s = small()
+    rp, ci, va = s.H.row_ptr.copy(), s.H.col.copy(), s.H.val.copy()
+    p = int(rp[1]) + list(ci[rp[1]:rp[2]]).index(0)
+    rp[2:] -= 1
+    s.H = W.BSR(s.H.nb, s.H.b, rp, np.delete(ci, p), np.delete(va, p, axis=0))
+    assert _dense_status(s) == -4
+
+
+def test_dense_rejects_too_large_a_matrix():
+    # N = 2501 * 16 > 40000 is refused before any allocation
+    nb, b = 2501, 16
+    rp = np.arange(nb + 1, dtype=np.int64)
+    ci = np.arange(nb, dtype=np.int32)
+    va = np.tile(np.eye(b), (nb, 1, 1))
+    s = small()
+    s.H = W.BSR(nb, b, rp, ci, va)
+    s.H1 = []
+    s.n_occ = 10
+    assert nb * b > T.DENSE_MAX_N
+    assert _dense_status(s) == -1
+
+
+def test_dense_rejects_null_arguments():
+    L = T.lib()
+    L.tc2_dense_response.restype = C.c_int
+    L.tc2_dense_response.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    assert L.tc2_dense_response(None, None, None) == -1
+
+
+def test_dense_valid_problem_needs_a_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert _dense_status(small()) == -3
