@@ -180,6 +180,52 @@ def crossover(args) -> int:
     return 0
 
 
+def lowdin_pipeline(args) -> int:
+    """Seconds of each stage of the non-orthogonal pipeline (Sec. 2.2): S^-1/2
+    and the orthogonal forms, the TC2 / TC2-CPSCF solve on them (the default
+    variant), and the back-transforms P = S^-1/2 X S^-1/2."""
+    import torch
+    from paper_2009_03551_amd import tc2 as T
+    from paper_2009_03551_amd import workloads as W
+
+    stream = torch.cuda.current_stream().cuda_stream
+    s = W.config_system(args.workload)
+    S = W.make_overlap(s, amp=0.2)
+    eps = s.eps
+    line = {"mode": "lowdin", "workload": args.workload, "atoms": s.H.nb, "N": s.H.n,
+            "b": s.H.b, "dirs": len(s.H1), "eps": eps, "S_blocks": int(S.row_ptr[-1])}
+    for _ in range(args.warmup):
+        T.lowdin(S, s.H, s.H1, eps=eps, tol=1e-9, max_iter=40, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = T.lowdin(S, s.H, s.H1, eps=eps, tol=1e-9, max_iter=40, stream=stream)
+    torch.cuda.synchronize()
+    line.update(lowdin_s=time.perf_counter() - t0, lowdin_device_s=g.seconds,
+                ns_status=g.status, ns_updates=g.iters, ns_resid=g.resid,
+                Z_blocks=int(g.Z.row_ptr[-1]), H_orth_blocks=int(g.H.row_ptr[-1]))
+    orth = W.System(H=g.H, H1=g.H1, n_occ=s.n_occ, xyz=s.xyz, eps=eps, tol=s.tol)
+    solver = T.Solver(orth, precision="fp32", wide=True, fp64_first=args.fp64_first,
+                      closing_fp64=2, skip="bound", graph=True)
+    for _ in range(args.warmup):
+        solver.run(stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = solver.run(stream=stream)[0]
+    torch.cuda.synchronize()
+    solver.close()
+    line.update(tc2_s=time.perf_counter() - t0, tc2_status=r.status_name, tc2_updates=r.iters,
+                alpha=r.alpha)
+    t0 = time.perf_counter()
+    P0 = T.congruence(g.Z, r.X0, eps=eps, stream=stream)
+    P1 = [T.congruence(g.Z, x, eps=eps, stream=stream) for x in r.X1]
+    torch.cuda.synchronize()
+    line.update(back_transform_s=time.perf_counter() - t0, P0_blocks=int(P0.row_ptr[-1]),
+                P1_blocks=[int(p.row_ptr[-1]) for p in P1])
+    line["total_s"] = line["lowdin_s"] + line["tc2_s"] + line["back_transform_s"]
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +261,10 @@ def main() -> int:
     ap.add_argument("--crossover", choices=["cube", "chain"], default=None,
                     help="only time the linear-scaling path against the dense O(N^3) path "
                          "over a series of sizes (one JSON line per size)")
+    ap.add_argument("--lowdin", action="store_true",
+                    help="only time the non-orthogonal pipeline on the workload with a synthetic "
+                         "overlap: Loewdin orthogonalisation, the TC2 solve of the orthogonal "
+                         "forms, and the back-transform of X0 and X1 (one JSON line)")
     ap.add_argument("--sizes", default=None,
                     help="crossover sizes: lattice edges (cube) or atom counts (chain), "
                          "comma-separated")
@@ -237,6 +287,8 @@ def main() -> int:
         return copy_calibration(args.copy_calibration, 10)
     if args.crossover:
         return crossover(args)
+    if args.lowdin:
+        return lowdin_pipeline(args)
     stream = torch.cuda.current_stream().cuda_stream
 
     # workload -> units: lists of systems solved in one context (one merged

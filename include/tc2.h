@@ -311,6 +311,80 @@ TC2_API tc2_status tc2_dense_response(const tc2_problem *problem,
                                       const tc2_dense_options *opts,
                                       tc2_dense_result *res);
 
+/* ---------------------------------------------------------------------------
+ * Loewdin orthogonalisation for a non-orthogonal basis (Sec. 2.2).
+ *
+ * The TC2 cycles take the orthogonal forms H_orth = S^-1/2 H S^-1/2 and
+ * H1_orth = S^-1/2 H1_d S^-1/2. Their converged results go back to the
+ * non-orthogonal basis as P = S^-1/2 P_orth S^-1/2. S^-1/2 comes from a
+ * Newton-Schulz iteration of block-sparse products; the paper computes the
+ * square root of S with such an iteration, in linear scaling.
+ *
+ * tc2_lowdin runs the coupled form of the iteration. With lam the Gershgorin
+ * upper bound of S, start from Y = S/lam and Z = I, then repeat:
+ *     M = Z Y;  stop if ||M - I||_F / sqrt(N) < tol;
+ *     T = (3 I - M)/2;  Y <- Y T;  Z <- Z T
+ * At the end S^-1/2 = Z / sqrt(lam).  A stall guard stops the iteration with
+ * TC2_FLOOR_REACHED when an update did not halve that residual: the filter
+ * or rounding, not the iteration, then sets it.
+ *
+ * Every product is atom-block sparse with the block filter of Sec. 2.3: an
+ * off-diagonal block whose Frobenius norm is strictly below eps is dropped.
+ * Products whose exact value is symmetric (Z Y, Y T, Z T, and the outer
+ * product of a congruence) are formed on their upper blocks and mirrored, so
+ * that they are exactly symmetric. This includes the upper scalar triangle
+ * of each diagonal block. A congruence Z X Z is the product (Z X) Z.
+ *
+ * Inputs: host BSR matrices with the layout and checks of tc2_setup. S must
+ * store every diagonal block. S, H, H1_d and X must be symmetric.
+ *
+ * Outputs: BSR matrices in host memory allocated by the library with the
+ * same layout (full symmetric pattern, row-major blocks). The caller frees
+ * each one with tc2_bsr_release. On an error nothing is left allocated.
+ *
+ * Errors:
+ *  - TC2_EINVAL: NULL arguments, ranges, more than 2^18 block rows;
+ *  - TC2_ENONSYM, TC2_ENAN: the checks of tc2_setup, or a non-finite
+ *    residual;
+ *  - TC2_EDEGENERATE: the Gershgorin bound of S is not positive;
+ *  - TC2_EOVERFLOW, TC2_ENOMEM, TC2_EDEVICE.
+ * TC2_NOT_CONVERGED (max_iter updates did not reach tol) and
+ * TC2_FLOOR_REACHED (the stall guard) come with valid outputs.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double eps;              /* block drop threshold of every product, >= 0       */
+  double tol;              /* tc2_lowdin: stop when ||Z Y - I||_F/sqrt(N) < tol  */
+  int32_t max_iter;        /* tc2_lowdin: 1..TC2_MAX_ITER updates                */
+  int32_t device;          /* HIP device ordinal                                */
+  void *hip_stream;        /* hipStream_t to run on; NULL: a stream of the call */
+} tc2_lowdin_options;
+
+typedef struct {
+  tc2_status status;
+  int32_t iters;           /* Newton-Schulz updates performed                   */
+  double resid;            /* ||Z Y - I||_F / sqrt(N) at the last test          */
+  double lambda;           /* the Gershgorin bound S was divided by             */
+  double seconds;          /* device time of the iteration and the transforms   */
+  tc2_bsr Z;               /* S^-1/2                                            */
+  tc2_bsr H;               /* S^-1/2 H S^-1/2                                   */
+  tc2_bsr H1[3];           /* S^-1/2 H1_d S^-1/2, d < n_dir                     */
+} tc2_lowdin_result;
+
+/* S^-1/2 and the orthogonal forms of H and of n_dir (0..3) perturbations. */
+TC2_API tc2_status tc2_lowdin(const tc2_bsr *S, const tc2_bsr *H, int32_t n_dir,
+                              const tc2_bsr *H1, const tc2_lowdin_options *opts,
+                              tc2_lowdin_result *res);
+
+/* out = Z X Z (the back-transform when Z = S^-1/2); opts->eps, device and
+ * hip_stream are used.  seconds, if not NULL, receives the device time. */
+TC2_API tc2_status tc2_congruence(const tc2_bsr *Z, const tc2_bsr *X,
+                                  const tc2_lowdin_options *opts, tc2_bsr *out,
+                                  double *seconds);
+
+/* Free a matrix returned by tc2_lowdin or tc2_congruence and zero it.
+ * NULL-safe. */
+TC2_API void tc2_bsr_release(tc2_bsr *m);
+
 #ifdef __cplusplus
 }
 #endif

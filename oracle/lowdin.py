@@ -18,7 +18,9 @@ same readings on its own):
       M = Z Y,  T = (3 I - M) / 2,  Y <- Y T,  Z <- Z T,
   which takes Y to (S/lam)^1/2 and Z to (S/lam)^-1/2; then S^-1/2 = Z / sqrt(lam).
 * Stopping: before each update, stop when ||Z Y - I||_F / sqrt(N) < tol; at
-  most max_iter updates.
+  most max_iter updates.  Stall guard (as for TC2, a precision floor): after
+  an update, stop when that residual fell by less than half, because the
+  filter or rounding, not the iteration, then sets it.
 * Products whose exact value is symmetric (Z Y, Y T, Z T, and the outer
   product of a congruence) keep the upper blocks of the computed product and
   mirror them, so that the result is exactly symmetric.  The inner product of
@@ -38,6 +40,7 @@ from .tc2_oracle import block_drop
 
 STATUS_OK = 0
 STATUS_NOT_CONVERGED = 1
+STATUS_FLOOR = 2
 
 
 def gershgorin_upper(S: np.ndarray) -> float:
@@ -93,12 +96,17 @@ def newton_schulz_inv_sqrt(S: np.ndarray, b: int, eps: float, tol: float,
     Y = S / lam
     Z = np.eye(N)
     iters = 0
+    prev = None
     while True:
         M = symmetric_product(Z, Y, b, eps)
         resid = float(np.linalg.norm(M - np.eye(N)) / np.sqrt(N))
         if resid < tol:
             status = STATUS_OK
             break
+        if prev is not None and resid > 0.5 * prev:
+            status = STATUS_FLOOR
+            break
+        prev = resid
         if iters == max_iter:
             status = STATUS_NOT_CONVERGED
             break

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtc2.so")
-SOURCES = ["tc2_kernels.hip", "tc2_tile.hip", "tc2_mlp.hip", "tc2_runtime.hip", "tc2_dense.hip"]
+SOURCES = ["tc2_kernels.hip", "tc2_tile.hip", "tc2_mlp.hip", "tc2_runtime.hip", "tc2_dense.hip",
+           "tc2_lowdin.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # the dense O(N^3) path: eigenpairs (rocSOLVER) and products (rocBLAS)
 LIBS = ["-lrocsolver", "-lrocblas"]

@@ -100,7 +100,7 @@ def lib() -> C.CDLL:
 
 EXPORTED = ("tc2_setup", "tc2_run", "tc2_free", "tc2_strerror", "tc2_version",
             "tc2_mlp_forward", "tc2_mlp_grad", "tc2_mlp_train", "tc2_log_copy",
-            "tc2_dense_response")
+            "tc2_dense_response", "tc2_lowdin", "tc2_congruence", "tc2_bsr_release")
 
 MLP_IN, MLP_PARAMS = 8, 4801
 
@@ -419,3 +419,89 @@ def dense_response(system: System, export: bool = False, device: int = 0,
     return DenseResult(r.status, r.e0, list(r.e1[:D]), list(r.trace_p1h1[:D]), r.tr_p0, r.gap,
                        r.seconds, r.ms_eigh, r.ms_p0, r.ms_p1, r.flops_p1, P0,
                        P1 if P1 is not None else [], ev)
+
+
+# ---------------------------------------------------------------- Loewdin orthogonalisation
+class tc2_lowdin_options(C.Structure):
+    _fields_ = [("eps", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("device", C.c_int32), ("hip_stream", C.c_void_p)]
+
+
+class tc2_lowdin_result(C.Structure):
+    _fields_ = [("status", C.c_int), ("iters", C.c_int32), ("resid", C.c_double),
+                ("lam", C.c_double), ("seconds", C.c_double), ("Z", tc2_bsr), ("H", tc2_bsr),
+                ("H1", tc2_bsr * 3)]
+
+
+@dataclass
+class LowdinResult:
+    status: int
+    iters: int
+    resid: float
+    lam: float
+    seconds: float
+    Z: BSR                      # S^-1/2
+    H: BSR                      # S^-1/2 H S^-1/2
+    H1: List[BSR]               # S^-1/2 H1_d S^-1/2
+
+
+def _release(m: tc2_bsr):
+    L = lib()
+    L.tc2_bsr_release.restype = None
+    L.tc2_bsr_release.argtypes = [C.POINTER(tc2_bsr)]
+    L.tc2_bsr_release(C.byref(m))
+
+
+def lowdin(S: BSR, H: BSR, H1: Sequence[BSR] = (), eps: float = 1e-6, tol: float = 1e-9,
+           max_iter: int = 50, device: int = 0, stream: Optional[int] = None) -> LowdinResult:
+    """S^-1/2 by the Newton-Schulz iteration and the orthogonal forms of H and
+    H1_d (``tc2_lowdin``)."""
+    keep: list = []
+    cS, cH = _c_bsr(S, keep), _c_bsr(H, keep)
+    D = len(H1)
+    arr = (tc2_bsr * 3)()
+    for d, h in enumerate(H1):
+        arr[d] = _c_bsr(h, keep)
+    o = tc2_lowdin_options(float(eps), float(tol), int(max_iter), int(device),
+                           C.c_void_p(stream) if stream else None)
+    r = tc2_lowdin_result()
+    L = lib()
+    L.tc2_lowdin.restype = C.c_int
+    L.tc2_lowdin.argtypes = [C.POINTER(tc2_bsr), C.POINTER(tc2_bsr), C.c_int32,
+                             C.POINTER(tc2_bsr), C.POINTER(tc2_lowdin_options),
+                             C.POINTER(tc2_lowdin_result)]
+    st = L.tc2_lowdin(C.byref(cS), C.byref(cH), D, arr, C.byref(o), C.byref(r))
+    if st < 0:
+        raise TC2Error(st, "tc2_lowdin")
+    try:
+        out = LowdinResult(r.status, r.iters, r.resid, r.lam, r.seconds, _py_bsr(r.Z),
+                           _py_bsr(r.H), [_py_bsr(r.H1[d]) for d in range(D)])
+    finally:
+        _release(r.Z)
+        _release(r.H)
+        for d in range(D):
+            _release(r.H1[d])
+    return out
+
+
+def congruence(Z: BSR, X: BSR, eps: float = 1e-6, device: int = 0,
+               stream: Optional[int] = None) -> BSR:
+    """Z X Z with the block filter (``tc2_congruence``): the back-transform of
+    a density matrix when Z = S^-1/2."""
+    keep: list = []
+    cZ, cX = _c_bsr(Z, keep), _c_bsr(X, keep)
+    o = tc2_lowdin_options(float(eps), 1.0, 1, int(device), C.c_void_p(stream) if stream else None)
+    out = tc2_bsr()
+    sec = C.c_double()
+    L = lib()
+    L.tc2_congruence.restype = C.c_int
+    L.tc2_congruence.argtypes = [C.POINTER(tc2_bsr), C.POINTER(tc2_bsr),
+                                 C.POINTER(tc2_lowdin_options), C.POINTER(tc2_bsr),
+                                 C.POINTER(C.c_double)]
+    st = L.tc2_congruence(C.byref(cZ), C.byref(cX), C.byref(o), C.byref(out), C.byref(sec))
+    if st < 0:
+        raise TC2Error(st, "tc2_congruence")
+    try:
+        return _py_bsr(out)
+    finally:
+        _release(out)

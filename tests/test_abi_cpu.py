@@ -173,3 +173,48 @@ def test_dense_valid_problem_needs_a_device():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert _dense_status(small()) == -3
+
+
+# ---------------------------------------------------------------- Loewdin orthogonalisation
+def _lowdin_status(S, H, **kw):
+    try:
+        return T.lowdin(S, H, **kw).status
+    except T.TC2Error as e:
+        return e.status
+
+
+def test_lowdin_rejects_malformed_input():
+    s = small()
+    S = W.make_overlap(s)
+    assert _lowdin_status(S, s.H, eps=-1.0) == -1
+    assert _lowdin_status(S, s.H, tol=0.0) == -1
+    assert _lowdin_status(S, s.H, max_iter=0) == -1
+    bad = W.BSR(S.nb, S.b, S.row_ptr, S.col, S.val.copy())
+    bad.val[0, 0, 0] = np.nan
+    assert _lowdin_status(bad, s.H) == -6
+    other = W.config_system("chain64", n=7)
+    assert _lowdin_status(S, other.H) == -1          # sizes differ
+    # S without its diagonal blocks
+    rows = np.repeat(np.arange(S.nb), np.diff(S.row_ptr))
+    off = rows != S.col
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows[off], minlength=S.nb))]).astype(np.int64)
+    assert _lowdin_status(W.BSR(S.nb, S.b, rp, S.col[off], S.val[off]), s.H) == -4
+
+
+def test_congruence_rejects_mismatched_sizes():
+    a, c = small(), W.config_system("chain64", n=7)
+    with pytest.raises(T.TC2Error) as ex:
+        T.congruence(a.H, c.H)
+    assert ex.value.status == -1
+
+
+def test_lowdin_needs_a_device_and_release_is_null_safe():
+    import torch
+    L = T.lib()
+    L.tc2_bsr_release.restype = None
+    L.tc2_bsr_release.argtypes = [C.c_void_p]
+    L.tc2_bsr_release(None)
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    s = small()
+    assert _lowdin_status(W.make_overlap(s), s.H) == -3

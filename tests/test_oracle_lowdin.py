@@ -109,6 +109,17 @@ def test_products_follow_their_definitions():
     assert np.array_equal(big, full * np.kron(np.eye(nb), np.ones((b, b))))
 
 
+def test_filter_floor_stops_the_iteration():
+    # with a coarse filter the residual levels off above a tiny tolerance
+    s, S, _, _ = problem("cube")
+    r = L.newton_schulz_inv_sqrt(S, s.H.b, 1e-3, 1e-14, 50)
+    assert r.status == L.STATUS_FLOOR and r.iters < 15
+    assert r.resid > 1e-10
+    # without it, quadratic convergence reaches the tolerance first
+    r0 = L.newton_schulz_inv_sqrt(S, s.H.b, 0.0, 1e-12, 50)
+    assert r0.status == L.STATUS_OK and r0.iters < r.iters + 3
+
+
 def test_iteration_limit_reports_not_converged():
     s, S, _, _ = problem("chain")
     r = L.newton_schulz_inv_sqrt(S, s.H.b, 0.0, 1e-14, 1)
