@@ -142,3 +142,101 @@ def lowdin(S: np.ndarray, H: np.ndarray, H1s: Sequence[np.ndarray], b: int, eps:
     Ho = congruence(r.Z, H, b, eps)
     H1o = [congruence(r.Z, h, b, eps) for h in H1s]
     return Lowdin(r.Z, Ho, H1o, r.iters, r.resid, r.lam, r.status)
+
+
+# ---------------------------------------------------------------- perturbed overlap
+# An atomic displacement moves basis functions, so the overlap changes too
+# (S1 != 0) and the response of the orthogonal form gains the derivative Z1 of
+# S^-1/2 (the non-orthogonal response the paper names as the next use of the
+# formalism).  Z1 comes from differentiating every step of the same
+# Newton-Schulz iteration; the orthogonal perturbation and the back-transform
+# follow by the product rule:
+#     H1_orth = Z1 H Z + Z H1 Z + Z H Z1,   P1 = Z1 X0 Z + Z X1 Z + Z X0 Z1.
+# Each derivative is a sum of two products, filtered after the sum; where the
+# sum is symmetric (M1, Y1, Z1, H1_orth, P1) its upper blocks are mirrored.
+
+
+def symmetric_product2(A, B, A2, B2, b: int, eps: float) -> np.ndarray:
+    """A B + A2 B2 for a sum known to be symmetric: upper blocks mirrored,
+    then the block filter."""
+    return symmetric_product(np.hstack([A, A2]), np.vstack([B, B2]), b, eps)
+
+
+def product2(A, B, A2, B2, b: int, eps: float) -> np.ndarray:
+    """A B + A2 B2, each off-diagonal block filtered on its own."""
+    return product(np.hstack([A, A2]), np.vstack([B, B2]), b, eps)
+
+
+@dataclass
+class InvSqrtResponse:
+    Z: np.ndarray               # S^-1/2
+    Z1: List[np.ndarray]        # d S^-1/2 for each S1_d
+    iters: int
+    resid: float
+    lam: float
+    status: int
+
+
+def newton_schulz_response(S: np.ndarray, S1s: Sequence[np.ndarray], b: int, eps: float,
+                           tol: float, max_iter: int) -> InvSqrtResponse:
+    """The coupled Newton-Schulz iteration of newton_schulz_inv_sqrt together
+    with its derivative along each S1_d (same updates, same stopping tests on
+    the unperturbed residual)."""
+    N = S.shape[0]
+    lam = gershgorin_upper(S)
+    Y, Z = S / lam, np.eye(N)
+    Y1 = [s1 / lam for s1 in S1s]
+    Z1 = [np.zeros((N, N)) for _ in S1s]
+    iters, prev = 0, None
+    while True:
+        M = symmetric_product(Z, Y, b, eps)
+        resid = float(np.linalg.norm(M - np.eye(N)) / np.sqrt(N))
+        if resid < tol:
+            status = STATUS_OK
+            break
+        if prev is not None and resid > 0.5 * prev:
+            status = STATUS_FLOOR
+            break
+        prev = resid
+        if iters == max_iter:
+            status = STATUS_NOT_CONVERGED
+            break
+        T = 0.5 * (3.0 * np.eye(N) - M)
+        T1 = [-0.5 * symmetric_product2(z1, Y, Z, y1, b, eps) for z1, y1 in zip(Z1, Y1)]
+        Y1 = [symmetric_product2(y1, T, Y, t1, b, eps) for y1, t1 in zip(Y1, T1)]
+        Z1 = [symmetric_product2(z1, T, Z, t1, b, eps) for z1, t1 in zip(Z1, T1)]
+        Y = symmetric_product(Y, T, b, eps)
+        Z = symmetric_product(Z, T, b, eps)
+        iters += 1
+    return InvSqrtResponse(Z / np.sqrt(lam), [z1 / np.sqrt(lam) for z1 in Z1], iters, resid,
+                           lam, status)
+
+
+def congruence_response(Z, Z1, X, X1, b: int, eps: float) -> np.ndarray:
+    """Z1 X Z + Z X1 Z + Z X Z1 as (Z1 X + Z X1) Z + (Z X) Z1."""
+    Q1 = product2(Z1, X, Z, X1, b, eps)
+    Q = product(Z, X, b, eps)
+    return symmetric_product2(Q1, Z, Q, Z1, b, eps)
+
+
+@dataclass
+class LowdinResponse:
+    Z: np.ndarray
+    Z1: List[np.ndarray]
+    H: np.ndarray
+    H1: List[np.ndarray]        # H1_orth_d = Z1 H Z + Z H1_d Z + Z H Z1
+    iters: int
+    resid: float
+    lam: float
+    status: int
+
+
+def lowdin_response(S, S1s, H, H1s, b: int, eps: float, tol: float,
+                    max_iter: int) -> LowdinResponse:
+    """Orthogonal forms for perturbations that change both H (H1_d) and S
+    (S1_d)."""
+    r = newton_schulz_response(S, S1s, b, eps, tol, max_iter)
+    Ho = congruence(r.Z, H, b, eps)
+    H1o = [congruence_response(r.Z, z1, H, h1, b, eps) for z1, h1 in zip(r.Z1, H1s)]
+    return LowdinResponse(r.Z, r.Z1, Ho, H1o, r.iters, r.resid, r.lam, r.status)
+

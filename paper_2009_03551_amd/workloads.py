@@ -176,6 +176,36 @@ def make_overlap(system: System, amp: float = 0.08, decay: float = 1.5, seed: in
     return _assemble(nb, b, pairs, off, diag)
 
 
+def make_displacement(system: System, atom: int, amp_s: float = 0.05, amp_h: float = 0.2,
+                      decay: float = 1.5, seed: int = 11):
+    """Synthetic first-order matrices (H1, S1) of an atomic displacement: the
+    basis functions of ``atom`` move, so both the Hamiltonian and the overlap
+    change in the block row and column of that atom (blocks decaying with
+    distance; the on-site overlap block does not change).  Returns two BSR
+    matrices with the same symmetric pattern."""
+    H, xyz = system.H, system.xyz
+    nb, b = H.nb, H.b
+    rng = np.random.default_rng(seed)
+    nbrs = [int(j) for j in H.col[H.row_ptr[atom]:H.row_ptr[atom + 1]] if j != atom]
+    pairs = np.array([(min(atom, j), max(atom, j)) for j in nbrs], dtype=np.int64).reshape(-1, 2)
+    r = np.linalg.norm(xyz[pairs[:, 0]] - xyz[pairs[:, 1]], axis=1) if len(pairs) else np.zeros(0)
+    w = np.exp(-r / decay)[:, None, None]
+    s_off = rng.uniform(-amp_s, amp_s, size=(len(pairs), b, b)) * w
+    h_off = rng.uniform(-amp_h, amp_h, size=(len(pairs), b, b)) * w
+    g = rng.uniform(-amp_h, amp_h, size=(b, b))
+    h_diag = np.zeros((nb, b, b))
+    h_diag[atom] = 0.5 * (g + g.T)
+    s_diag = np.zeros((nb, b, b))
+
+    def only(bsr):  # keep the blocks in the row or column of the atom
+        rows = np.repeat(np.arange(nb), np.diff(bsr.row_ptr))
+        keep = (rows == atom) | (bsr.col == atom)
+        rp = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=nb))])
+        return BSR(nb, b, rp.astype(np.int64), bsr.col[keep], bsr.val[keep])
+
+    return only(_assemble(nb, b, pairs, h_off, h_diag)), only(_assemble(nb, b, pairs, s_off, s_diag))
+
+
 # Named workloads.  Readings of what the paper leaves open (lattice spacing,
 # occupation for b = 13, tolerances) are fixed here and listed in the design
 # notes.

@@ -124,3 +124,59 @@ def test_iteration_limit_reports_not_converged():
     s, S, _, _ = problem("chain")
     r = L.newton_schulz_inv_sqrt(S, s.H.b, 0.0, 1e-14, 1)
     assert r.status == L.STATUS_NOT_CONVERGED and r.iters == 1
+
+
+# ---------------------------------------------------------------- perturbed overlap (displacement)
+def displaced(name="chain"):
+    s, S, H, _ = problem(name)
+    atom = s.H.nb // 2
+    H1b, S1b = W.make_displacement(s, atom)
+    return s, S, H, dense(H1b), dense(S1b)
+
+
+def test_derivative_of_the_inverse_square_root():
+    s, S, H, H1, S1 = displaced("cube")
+    r = L.newton_schulz_response(S, [S1], s.H.b, 0.0, 1e-14, 50)
+    assert r.status == L.STATUS_OK
+    h = 1e-5
+    fd = (inv_sqrt(S + h * S1) - inv_sqrt(S - h * S1)) / (2 * h)
+    np.testing.assert_allclose(r.Z1[0], fd, atol=1e-8)
+    # d(Z S Z) = 0
+    Z, Z1 = r.Z, r.Z1[0]
+    np.testing.assert_allclose(Z1 @ S @ Z + Z @ S1 @ Z + Z @ S @ Z1, 0.0, atol=1e-11)
+    assert np.array_equal(Z1, Z1.T)
+
+
+def test_orthogonal_perturbation_is_the_derivative_of_the_orthogonal_form():
+    s, S, H, H1, S1 = displaced("chain")
+    o = L.lowdin_response(S, [S1], H, [H1], s.H.b, 0.0, 1e-14, 50)
+    h = 1e-5
+    orth = lambda x: inv_sqrt(S + x * S1) @ (H + x * H1) @ inv_sqrt(S + x * S1)
+    np.testing.assert_allclose(o.H1[0], (orth(h) - orth(-h)) / (2 * h), atol=1e-8)
+
+
+def test_displacement_response_is_the_derivative_of_the_generalised_projector():
+    # P1 = Z1 X0 Z + Z X1 Z + Z X0 Z1 with X0, X1 the orthogonal projector and
+    # its response to H1_orth, against finite differences of the projector of
+    # H C = S C E when both H and S move
+    s, S, H, H1, S1 = displaced("chain")
+    b = s.H.b
+    o = L.lowdin_response(S, [S1], H, [H1], b, 0.0, 1e-14, 50)
+    X0 = E.exact_projector(o.H, s.n_occ)
+    X1 = E.exact_response(o.H, o.H1[0], s.n_occ)
+    P1 = L.congruence_response(o.Z, o.Z1[0], X0, X1, b, 0.0)
+    h = 1e-5
+    fd = (generalised_projector(H + h * H1, S + h * S1, s.n_occ)
+          - generalised_projector(H - h * H1, S - h * S1, s.n_occ)) / (2 * h)
+    np.testing.assert_allclose(P1, fd, atol=1e-7)
+    assert np.abs(P1).max() > 1e-3                   # the check has something to check
+
+
+def test_unchanged_overlap_reduces_to_the_field_case():
+    s, S, H, H1, _ = displaced("chain")
+    z = np.zeros_like(S)
+    o = L.lowdin_response(S, [z], H, [H1], s.H.b, 1e-8, 1e-12, 50)
+    f = L.lowdin(S, H, [H1], s.H.b, 1e-8, 1e-12, 50)
+    assert np.array_equal(o.Z1[0], z)
+    np.testing.assert_allclose(o.H1[0], f.H1[0], atol=1e-14)
+    assert np.array_equal(o.Z, f.Z) and o.iters == f.iters
