@@ -381,8 +381,61 @@ TC2_API tc2_status tc2_congruence(const tc2_bsr *Z, const tc2_bsr *X,
                                   const tc2_lowdin_options *opts, tc2_bsr *out,
                                   double *seconds);
 
-/* Free a matrix returned by tc2_lowdin or tc2_congruence and zero it.
- * NULL-safe. */
+/* ---------------------------------------------------------------------------
+ * Perturbations that move the basis: an atomic displacement changes the
+ * overlap as well (S1_d != 0). The paper names this as the next use of the
+ * formalism, after the field perturbation.
+ *
+ * Differentiating P = Z X Z with Z = S^-1/2 gives
+ *     H1_orth = Z1 H Z + Z H1_d Z + Z H Z1,
+ *     P1      = Z1 X0 Z + Z X1 Z + Z X0 Z1.
+ * Here Z1 is the derivative of S^-1/2 along S1_d. X0 and X1 are the TC2 /
+ * TC2-CPSCF results on H_orth and H1_orth.
+ *
+ * tc2_lowdin_response runs the iteration of tc2_lowdin together with its
+ * derivative along each S1_d:
+ *     M1 = Z1 Y + Z Y1;  T1 = -M1/2;
+ *     Y1 <- Y1 T + Y T1;  Z1 <- Z1 T + Z T1;
+ * starting from Y1 = S1_d/lam and Z1 = 0. The updates and stopping tests are
+ * those of tc2_lowdin, on the unperturbed residual. At the end
+ * Z1 = Z1/sqrt(lam).
+ *
+ * Each derivative is a sum of two products, filtered after the sum. A sum
+ * whose exact value is symmetric is mirrored from its upper blocks, as in
+ * tc2_lowdin.
+ *
+ * tc2_congruence_response forms P1 as (Z1 X0 + Z X1) Z + (Z X0) Z1.
+ *
+ * S1_d and H1_d must be symmetric BSR matrices with the layout of H; they
+ * need not store diagonal blocks. Errors and output ownership are those of
+ * tc2_lowdin and tc2_congruence. S1 may be NULL only when n_dir = 0.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  tc2_status status;
+  int32_t iters;           /* Newton-Schulz updates performed                   */
+  double resid;            /* ||Z Y - I||_F / sqrt(N) at the last test          */
+  double lambda;           /* the Gershgorin bound S was divided by             */
+  double seconds;          /* device time of the iteration and the transforms   */
+  tc2_bsr Z;               /* S^-1/2                                            */
+  tc2_bsr H;               /* S^-1/2 H S^-1/2                                   */
+  tc2_bsr Z1[3];           /* derivative of S^-1/2 along S1_d                   */
+  tc2_bsr H1[3];           /* Z1 H Z + Z H1_d Z + Z H Z1                        */
+} tc2_lowdin_response_result;
+
+TC2_API tc2_status tc2_lowdin_response(const tc2_bsr *S, const tc2_bsr *H, int32_t n_dir,
+                                       const tc2_bsr *H1, const tc2_bsr *S1,
+                                       const tc2_lowdin_options *opts,
+                                       tc2_lowdin_response_result *res);
+
+/* out = Z1 X Z + Z X1 Z + Z X Z1 (the back-transform of a response when the
+ * overlap moves). */
+TC2_API tc2_status tc2_congruence_response(const tc2_bsr *Z, const tc2_bsr *Z1,
+                                           const tc2_bsr *X, const tc2_bsr *X1,
+                                           const tc2_lowdin_options *opts, tc2_bsr *out,
+                                           double *seconds);
+
+/* Free a matrix returned by tc2_lowdin, tc2_lowdin_response, tc2_congruence
+ * or tc2_congruence_response and zero it.  NULL-safe. */
 TC2_API void tc2_bsr_release(tc2_bsr *m);
 
 #ifdef __cplusplus

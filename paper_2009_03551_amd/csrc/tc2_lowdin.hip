@@ -53,24 +53,37 @@ __global__ void k_unpack(long long n, int b, const double* v, double* val) {
   }
 }
 
-// Pattern of C = A B, one workgroup per row I: the union over K in row I of A
-// of row K of B (only J >= I when `upper`).  Pass 0 counts the columns of
-// each row; pass 1 writes them, ascending, from C_rp.
-__global__ __launch_bounds__(GT) void k_gp_symbolic(int pass, int nb, const int* Arp,
-                                                    const int* Aci, const int* Brp,
-                                                    const int* Bci, int upper, int* cnt,
-                                                    const int* Crp, int* Cci) {
+// Operands of C = A B (+ A2 B2): row pointers, columns and values of A and B,
+// and of the optional second pair (np = 1 or 2).
+struct Pairs {
+  int np;
+  const int* arp[2];
+  const int* aci[2];
+  const double* av[2];
+  const int* brp[2];
+  const int* bci[2];
+  const double* bv[2];
+};
+
+// Pattern of C, one workgroup per row I: the union, over the pairs and over K
+// in row I of A, of row K of B (only J >= I when `upper`).  Pass 0 counts the
+// columns of each row; pass 1 writes them, ascending, from C_rp.
+__global__ __launch_bounds__(GT) void k_gp_symbolic(int pass, int nb, Pairs g, int upper,
+                                                    int* cnt, const int* Crp, int* Cci) {
   extern __shared__ unsigned bits[];
   __shared__ int ssum[GT];
   const int I = blockIdx.x, t = threadIdx.x;
   const int nwords = (nb + 31) >> 5;
   for (int w = t; w < nwords; w += GT) bits[w] = 0u;
   __syncthreads();
-  for (int p = Arp[I]; p < Arp[I + 1]; ++p) {
-    const int K = Aci[p];
-    for (int q = Brp[K] + t; q < Brp[K + 1]; q += GT) {
-      const int J = Bci[q];
-      if (!upper || J >= I) atomicOr(&bits[J >> 5], 1u << (J & 31));
+  for (int k = 0; k < g.np; ++k) {
+    const int *Arp = g.arp[k], *Aci = g.aci[k], *Brp = g.brp[k], *Bci = g.bci[k];
+    for (int p = Arp[I]; p < Arp[I + 1]; ++p) {
+      const int K = Aci[p];
+      for (int q = Brp[K] + t; q < Brp[K + 1]; q += GT) {
+        const int J = Bci[q];
+        if (!upper || J >= I) atomicOr(&bits[J >> 5], 1u << (J & 31));
+      }
     }
   }
   __syncthreads();
@@ -101,40 +114,45 @@ __global__ __launch_bounds__(GT) void k_gp_symbolic(int pass, int nb, const int*
   }
 }
 
-// Numeric blocks of the candidate entries of C (one wave per entry): the sum
-// over common columns K of A_IK B_JK^T, then (sym) the upper scalar triangle
-// of a diagonal block mirrored onto its lower one, the Frobenius norm and the
-// keep flag (diagonal blocks are always kept).
+// Numeric blocks of the candidate entries of C (one wave per entry): the sum,
+// over the pairs and the columns K common to row I of A and row J of B, of
+// A_IK B_JK^T; then (sym) the upper scalar triangle of a diagonal block
+// mirrored onto its lower one, the Frobenius norm and the keep flag (diagonal
+// blocks are always kept).
 __global__ __launch_bounds__(256) void k_gp_numeric(long long nnz, const int* Crow, const int* Cci,
-                                                    const int* Arp, const int* Aci,
-                                                    const double* Av, const int* Brp,
-                                                    const int* Bci, const double* Bv, int sym,
-                                                    double eps, double* Cv, int* keep) {
+                                                    Pairs g, int sym, double eps, double* Cv,
+                                                    int* keep) {
   __shared__ double stage[4][BS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long nw = (long long)gridDim.x * 4;
   for (long long e = (long long)blockIdx.x * 4 + wave; e < nnz; e += nw) {
     const int I = Crow[e], J = Cci[e];
-    const int a0 = Arp[I], a1 = Arp[I + 1];
-    const int b0 = Brp[J], nbj = Brp[J + 1] - b0;
     Acc<double> acc;
     acc.v = d4{0.0, 0.0, 0.0, 0.0};
-    for (int c0 = a0; c0 < a1; c0 += 64) {
-      const int p = c0 + lane;
-      int q = -1;
-      if (p < a1) {
-        const int f = bsearch_eq(Bci + b0, nbj, Aci[p]);
-        q = f >= 0 ? b0 + f : -1;
-      }
-      unsigned long long m = __ballot(q >= 0);
-      while (m) {
-        const int l = __ffsll((long long)m) - 1;
-        m &= m - 1;
-        const long long pp = __builtin_amdgcn_readlane(p, l);
-        const long long qq = __builtin_amdgcn_readlane(q, l);
+    for (int k = 0; k < g.np; ++k) {
+      const int* Aci = g.aci[k];
+      const int* Bci = g.bci[k];
+      const double* Av = g.av[k];
+      const double* Bv = g.bv[k];
+      const int a0 = g.arp[k][I], a1 = g.arp[k][I + 1];
+      const int b0 = g.brp[k][J], nbj = g.brp[k][J + 1] - b0;
+      for (int c0 = a0; c0 < a1; c0 += 64) {
+        const int p = c0 + lane;
+        int q = -1;
+        if (p < a1) {
+          const int f = bsearch_eq(Bci + b0, nbj, Aci[p]);
+          q = f >= 0 ? b0 + f : -1;
+        }
+        unsigned long long m = __ballot(q >= 0);
+        while (m) {
+          const int l = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const long long pp = __builtin_amdgcn_readlane(p, l);
+          const long long qq = __builtin_amdgcn_readlane(q, l);
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-          mfma(acc, Av[pp * BS + lane + 64 * kk], Bv[qq * BS + lane + 64 * kk]);
+          for (int kk = 0; kk < 4; ++kk)
+            mfma(acc, Av[pp * BS + lane + 64 * kk], Bv[qq * BS + lane + 64 * kk]);
+        }
       }
     }
     double* st = stage[wave];
@@ -337,14 +355,28 @@ tc2_status copy_scaled(const GMat& a, double s, hipStream_t st, GMat& m) {
   return TC2_OK;
 }
 
-// C = A B with the block filter; sym: upper blocks computed and mirrored.
-tc2_status product(Ctx& x, const GMat& A, const GMat& B, bool sym, double eps, GMat& C) {
+// C = A B (+ A2 B2) with the block filter applied to the sum; sym: upper
+// blocks computed and mirrored.
+tc2_status product(Ctx& x, const GMat& A, const GMat& B, bool sym, double eps, GMat& C,
+                   const GMat* A2 = nullptr, const GMat* B2 = nullptr) {
   hipStream_t st = x.st;
   const int nb = A.nb;
+  Pairs g{};
+  g.np = A2 ? 2 : 1;
+  const GMat* as[2] = {&A, A2};
+  const GMat* bs[2] = {&B, B2};
+  for (int k = 0; k < g.np; ++k) {
+    g.arp[k] = as[k]->drp.i();
+    g.aci[k] = as[k]->dci.i();
+    g.av[k] = as[k]->v.d();
+    g.brp[k] = bs[k]->drp.i();
+    g.bci[k] = bs[k]->dci.i();
+    g.bv[k] = bs[k]->v.d();
+  }
   const size_t shm = (size_t)((nb + 31) >> 5) * sizeof(unsigned);
   LCHK(x.cnt.alloc((size_t)nb * sizeof(int)));
-  hipLaunchKernelGGL(k_gp_symbolic, dim3(nb), dim3(GT), shm, st, 0, nb, A.drp.i(), A.dci.i(),
-                     B.drp.i(), B.dci.i(), sym ? 1 : 0, x.cnt.i(), nullptr, nullptr);
+  hipLaunchKernelGGL(k_gp_symbolic, dim3(nb), dim3(GT), shm, st, 0, nb, g, sym ? 1 : 0,
+                     x.cnt.i(), nullptr, nullptr);
   LCHK(hipGetLastError());
   x.hcnt.resize((size_t)nb);
   LCHK(hipMemcpyAsync(x.hcnt.data(), x.cnt.p, (size_t)nb * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -363,8 +395,8 @@ tc2_status product(Ctx& x, const GMat& A, const GMat& B, bool sym, double eps, G
   LCHK(hipMemcpyAsync(cand.drp.p, cand.rp.data(), cand.rp.size() * sizeof(int),
                       hipMemcpyHostToDevice, st));
   LCHK(cand.dci.alloc((size_t)tot * sizeof(int)));
-  hipLaunchKernelGGL(k_gp_symbolic, dim3(nb), dim3(GT), shm, st, 1, nb, A.drp.i(), A.dci.i(),
-                     B.drp.i(), B.dci.i(), sym ? 1 : 0, nullptr, cand.drp.i(), cand.dci.i());
+  hipLaunchKernelGGL(k_gp_symbolic, dim3(nb), dim3(GT), shm, st, 1, nb, g, sym ? 1 : 0, nullptr,
+                     cand.drp.i(), cand.dci.i());
   LCHK(hipGetLastError());
   cand.ci.resize((size_t)tot);
   if (tot)
@@ -382,8 +414,8 @@ tc2_status product(Ctx& x, const GMat& A, const GMat& B, bool sym, double eps, G
   LCHK(x.keep.alloc((size_t)tot * sizeof(int)));
   if (tot) {
     hipLaunchKernelGGL(k_gp_numeric, dim3(grid_for(tot, 4)), dim3(256), 0, st, tot,
-                       cand.drow.i(), cand.dci.i(), A.drp.i(), A.dci.i(), A.v.d(), B.drp.i(),
-                       B.dci.i(), B.v.d(), sym ? 1 : 0, eps, cand.v.d(), x.keep.i());
+                       cand.drow.i(), cand.dci.i(), g, sym ? 1 : 0, eps, cand.v.d(),
+                       x.keep.i());
     LCHK(hipGetLastError());
   }
   std::vector<int> keep((size_t)tot);
@@ -534,8 +566,38 @@ struct Events {
   }
 };
 
-tc2_status lowdin_impl(const tc2_bsr* S, const tc2_bsr* H, int32_t n_dir, const tc2_bsr* H1,
-                       const tc2_lowdin_options* o, tc2_lowdin_result* r) {
+// The zero matrix (empty pattern).
+tc2_status zero(int nb, int b, hipStream_t st, GMat& m) {
+  m.nb = nb;
+  m.b = b;
+  m.rp.assign((size_t)nb + 1, 0);
+  m.ci.clear();
+  if (tc2_status s = upload_pattern(m, st); s != TC2_OK) return s;
+  LCHK(m.v.alloc(0));
+  return TC2_OK;
+}
+
+tc2_status scale(GMat& m, double s, hipStream_t st) {
+  if (m.nnz() == 0) return TC2_OK;
+  hipLaunchKernelGGL(k_affine, dim3(grid_for(m.nnz() * BS)), dim3(256), 0, st, m.nnz(), m.b,
+                     m.drow.i(), m.dci.i(), s, 0.0, m.v.d());
+  LCHK(hipGetLastError());
+  return TC2_OK;
+}
+
+// Where tc2_lowdin and tc2_lowdin_response put their outputs.
+struct LowdinOut {
+  int32_t* iters;
+  double *resid, *lambda, *seconds;
+  tc2_bsr *Z, *H, *H1, *Z1;  // Z1: NULL for a field perturbation
+};
+
+// S^-1/2 by the coupled Newton-Schulz iteration and, with S1, its derivative
+// along each S1_d (the same updates differentiated: M1 = Z1 Y + Z Y1,
+// T1 = -M1/2, Y1 <- Y1 T + Y T1, Z1 <- Z1 T + Z T1); then the orthogonal forms
+// Z H Z and, per direction, Z H1_d Z or (with S1) Z1 H Z + Z H1_d Z + Z H Z1.
+tc2_status lowdin_core(const tc2_bsr* S, const tc2_bsr* H, int32_t n_dir, const tc2_bsr* H1,
+                       const tc2_bsr* S1, const tc2_lowdin_options* o, LowdinOut out) {
   if (!S || !H || (n_dir > 0 && !H1) || n_dir < 0 || n_dir > 3) return TC2_EINVAL;
   if (tc2_status s = check_opts(o, true); s != TC2_OK) return s;
   const int nb = S->nb, b = S->b;
@@ -543,8 +605,11 @@ tc2_status lowdin_impl(const tc2_bsr* S, const tc2_bsr* H, int32_t n_dir, const 
   if (tc2_status s = validate_bsr(*S, nb, b); s != TC2_OK) return s;
   if (!has_diag(*S, nb)) return TC2_ENONSYM;
   if (tc2_status s = validate_bsr(*H, nb, b); s != TC2_OK) return s;
-  for (int d = 0; d < n_dir; ++d)
+  for (int d = 0; d < n_dir; ++d) {
     if (tc2_status s = validate_bsr(H1[d], nb, b); s != TC2_OK) return s;
+    if (S1)
+      if (tc2_status s = validate_bsr(S1[d], nb, b); s != TC2_OK) return s;
+  }
   // Gershgorin upper bound of S over its scalar rows
   double lam = 0.0;
   for (int i = 0; i < nb; ++i)
@@ -558,20 +623,27 @@ tc2_status lowdin_impl(const tc2_bsr* S, const tc2_bsr* H, int32_t n_dir, const 
       lam = std::max(lam, c + rad);
     }
   if (!(lam > 0.0)) return TC2_EDEGENERATE;
-  r->lambda = lam;
+  *out.lambda = lam;
+  const int nd = S1 ? n_dir : 0;  // derivative directions
 
   Ctx x;
   if (tc2_status s = start(o, x); s != TC2_OK) return s;
   Events ev;
   LCHK(hipEventCreate(&ev.a));
   LCHK(hipEventCreate(&ev.b));
-  GMat gS, gH;
+  GMat gS, gH, gS1[3];
   if (tc2_status s = from_bsr(*S, x.st, gS); s != TC2_OK) return s;
   if (tc2_status s = from_bsr(*H, x.st, gH); s != TC2_OK) return s;
+  for (int d = 0; d < nd; ++d)
+    if (tc2_status s = from_bsr(S1[d], x.st, gS1[d]); s != TC2_OK) return s;
   LCHK(hipEventRecord(ev.a, x.st));
-  GMat Y, Z;
+  GMat Y, Z, Y1[3], Z1[3];
   if (tc2_status s = copy_scaled(gS, 1.0 / lam, x.st, Y); s != TC2_OK) return s;
   if (tc2_status s = identity(nb, b, x.st, Z); s != TC2_OK) return s;
+  for (int d = 0; d < nd; ++d) {
+    if (tc2_status s = copy_scaled(gS1[d], 1.0 / lam, x.st, Y1[d]); s != TC2_OK) return s;
+    if (tc2_status s = zero(nb, b, x.st, Z1[d]); s != TC2_OK) return s;
+  }
   const double sqN = std::sqrt((double)nb * b);
   tc2_status status = TC2_OK;
   int iters = 0;
@@ -581,16 +653,16 @@ tc2_status lowdin_impl(const tc2_bsr* S, const tc2_bsr* H, int32_t n_dir, const 
     if (tc2_status s = product(x, Z, Y, true, o->eps, M); s != TC2_OK) return s;
     double res = 0.0;
     if (tc2_status s = resid_norm(x, M, &res); s != TC2_OK) return s;
-    r->resid = res / sqN;
-    if (!std::isfinite(r->resid)) return TC2_ENAN;
-    if (r->resid < o->tol) break;
+    *out.resid = res / sqN;
+    if (!std::isfinite(*out.resid)) return TC2_ENAN;
+    if (*out.resid < o->tol) break;
     // stall guard: the last update did not halve the residual, so the filter
     // or rounding sets it now
-    if (prev >= 0.0 && r->resid > 0.5 * prev) {
+    if (prev >= 0.0 && *out.resid > 0.5 * prev) {
       status = TC2_FLOOR_REACHED;
       break;
     }
-    prev = r->resid;
+    prev = *out.resid;
     if (iters == o->max_iter) {
       status = TC2_NOT_CONVERGED;
       break;
@@ -599,6 +671,15 @@ tc2_status lowdin_impl(const tc2_bsr* S, const tc2_bsr* H, int32_t n_dir, const 
     hipLaunchKernelGGL(k_affine, dim3(grid_for(M.nnz() * BS)), dim3(256), 0, x.st, M.nnz(), b,
                        M.drow.i(), M.dci.i(), -0.5, 1.5, M.v.d());
     LCHK(hipGetLastError());
+    for (int d = 0; d < nd; ++d) {
+      GMat T1, Y1n, Z1n;  // T1 = -(Z1 Y + Z Y1)/2 from the current iterates
+      if (tc2_status s = product(x, Z1[d], Y, true, o->eps, T1, &Z, &Y1[d]); s != TC2_OK) return s;
+      if (tc2_status s = scale(T1, -0.5, x.st); s != TC2_OK) return s;
+      if (tc2_status s = product(x, Y1[d], M, true, o->eps, Y1n, &Y, &T1); s != TC2_OK) return s;
+      if (tc2_status s = product(x, Z1[d], M, true, o->eps, Z1n, &Z, &T1); s != TC2_OK) return s;
+      Y1[d] = std::move(Y1n);
+      Z1[d] = std::move(Z1n);
+    }
     GMat Y2, Z2;
     if (tc2_status s = product(x, Y, M, true, o->eps, Y2); s != TC2_OK) return s;
     if (tc2_status s = product(x, Z, M, true, o->eps, Z2); s != TC2_OK) return s;
@@ -606,55 +687,77 @@ tc2_status lowdin_impl(const tc2_bsr* S, const tc2_bsr* H, int32_t n_dir, const 
     Z = std::move(Z2);
     ++iters;
   }
-  r->iters = iters;
-  // S^-1/2 = Z / sqrt(lam)
-  hipLaunchKernelGGL(k_affine, dim3(grid_for(Z.nnz() * BS)), dim3(256), 0, x.st, Z.nnz(), b,
-                     Z.drow.i(), Z.dci.i(), 1.0 / std::sqrt(lam), 0.0, Z.v.d());
-  LCHK(hipGetLastError());
-  // orthogonal forms Z H Z and Z H1_d Z
-  GMat Ho, H1o[3];
-  {
-    GMat Q;
-    if (tc2_status s = product(x, Z, gH, false, o->eps, Q); s != TC2_OK) return s;
-    if (tc2_status s = product(x, Q, Z, true, o->eps, Ho); s != TC2_OK) return s;
-  }
+  *out.iters = iters;
+  // S^-1/2 = Z / sqrt(lam), and its derivatives
+  const double r = 1.0 / std::sqrt(lam);
+  if (tc2_status s = scale(Z, r, x.st); s != TC2_OK) return s;
+  for (int d = 0; d < nd; ++d)
+    if (tc2_status s = scale(Z1[d], r, x.st); s != TC2_OK) return s;
+  // orthogonal forms
+  GMat Q, Ho, H1o[3];
+  if (tc2_status s = product(x, Z, gH, false, o->eps, Q); s != TC2_OK) return s;
+  if (tc2_status s = product(x, Q, Z, true, o->eps, Ho); s != TC2_OK) return s;
   for (int d = 0; d < n_dir; ++d) {
-    GMat g, Q;
+    GMat g, Q1;
     if (tc2_status s = from_bsr(H1[d], x.st, g); s != TC2_OK) return s;
-    if (tc2_status s = product(x, Z, g, false, o->eps, Q); s != TC2_OK) return s;
-    if (tc2_status s = product(x, Q, Z, true, o->eps, H1o[d]); s != TC2_OK) return s;
+    if (!S1) {  // Z H1 Z
+      if (tc2_status s = product(x, Z, g, false, o->eps, Q1); s != TC2_OK) return s;
+      if (tc2_status s = product(x, Q1, Z, true, o->eps, H1o[d]); s != TC2_OK) return s;
+    } else {  // (Z1 H + Z H1) Z + (Z H) Z1
+      if (tc2_status s = product(x, Z1[d], gH, false, o->eps, Q1, &Z, &g); s != TC2_OK) return s;
+      if (tc2_status s = product(x, Q1, Z, true, o->eps, H1o[d], &Q, &Z1[d]); s != TC2_OK)
+        return s;
+    }
   }
   LCHK(hipEventRecord(ev.b, x.st));
   LCHK(hipEventSynchronize(ev.b));
   float ms = 0.f;
   LCHK(hipEventElapsedTime(&ms, ev.a, ev.b));
-  r->seconds = ms * 1e-3;
-  if (tc2_status s = to_host(x, Z, &r->Z); s != TC2_OK) return s;
-  if (tc2_status s = to_host(x, Ho, &r->H); s != TC2_OK) return s;
-  for (int d = 0; d < n_dir; ++d)
-    if (tc2_status s = to_host(x, H1o[d], &r->H1[d]); s != TC2_OK) return s;
+  *out.seconds = ms * 1e-3;
+  if (tc2_status s = to_host(x, Z, out.Z); s != TC2_OK) return s;
+  if (tc2_status s = to_host(x, Ho, out.H); s != TC2_OK) return s;
+  for (int d = 0; d < n_dir; ++d) {
+    if (tc2_status s = to_host(x, H1o[d], &out.H1[d]); s != TC2_OK) return s;
+    if (S1)
+      if (tc2_status s = to_host(x, Z1[d], &out.Z1[d]); s != TC2_OK) return s;
+  }
   return status;
 }
 
-tc2_status congruence_impl(const tc2_bsr* Zh, const tc2_bsr* Xh, const tc2_lowdin_options* o,
-                           tc2_bsr* out, double* seconds) {
-  if (!Zh || !Xh || !out) return TC2_EINVAL;
+// Z X Z, or (with Z1 and X1) Z1 X Z + Z X1 Z + Z X Z1 = (Z1 X + Z X1) Z + (Z X) Z1.
+tc2_status congruence_impl(const tc2_bsr* Zh, const tc2_bsr* Xh, const tc2_bsr* Z1h,
+                           const tc2_bsr* X1h, const tc2_lowdin_options* o, tc2_bsr* out,
+                           double* seconds) {
+  if (!Zh || !Xh || !out || (!Z1h) != (!X1h)) return TC2_EINVAL;
   if (tc2_status s = check_opts(o, false); s != TC2_OK) return s;
   const int nb = Zh->nb, b = Zh->b;
   if (nb < 1 || b < 1 || b > BP || nb > MAX_NB) return TC2_EINVAL;
   if (tc2_status s = validate_bsr(*Zh, nb, b); s != TC2_OK) return s;
   if (tc2_status s = validate_bsr(*Xh, nb, b); s != TC2_OK) return s;
+  if (Z1h) {
+    if (tc2_status s = validate_bsr(*Z1h, nb, b); s != TC2_OK) return s;
+    if (tc2_status s = validate_bsr(*X1h, nb, b); s != TC2_OK) return s;
+  }
   Ctx x;
   if (tc2_status s = start(o, x); s != TC2_OK) return s;
   Events ev;
   LCHK(hipEventCreate(&ev.a));
   LCHK(hipEventCreate(&ev.b));
-  GMat Z, X, Q, C;
+  GMat Z, X, Z1, X1, Q, Q1, C;
   if (tc2_status s = from_bsr(*Zh, x.st, Z); s != TC2_OK) return s;
   if (tc2_status s = from_bsr(*Xh, x.st, X); s != TC2_OK) return s;
+  if (Z1h) {
+    if (tc2_status s = from_bsr(*Z1h, x.st, Z1); s != TC2_OK) return s;
+    if (tc2_status s = from_bsr(*X1h, x.st, X1); s != TC2_OK) return s;
+  }
   LCHK(hipEventRecord(ev.a, x.st));
   if (tc2_status s = product(x, Z, X, false, o->eps, Q); s != TC2_OK) return s;
-  if (tc2_status s = product(x, Q, Z, true, o->eps, C); s != TC2_OK) return s;
+  if (!Z1h) {
+    if (tc2_status s = product(x, Q, Z, true, o->eps, C); s != TC2_OK) return s;
+  } else {
+    if (tc2_status s = product(x, Z1, X, false, o->eps, Q1, &Z, &X1); s != TC2_OK) return s;
+    if (tc2_status s = product(x, Q1, Z, true, o->eps, C, &Q, &Z1); s != TC2_OK) return s;
+  }
   LCHK(hipEventRecord(ev.b, x.st));
   LCHK(hipEventSynchronize(ev.b));
   float ms = 0.f;
@@ -672,7 +775,9 @@ extern "C" TC2_API tc2_status tc2_lowdin(const tc2_bsr* S, const tc2_bsr* H, int
   std::memset(res, 0, sizeof(*res));
   tc2_status s;
   try {
-    s = lowdin_impl(S, H, n_dir, H1, opts, res);
+    s = lowdin_core(S, H, n_dir, H1, nullptr, opts,
+                    LowdinOut{&res->iters, &res->resid, &res->lambda, &res->seconds, &res->Z,
+                              &res->H, res->H1, nullptr});
   } catch (...) {
     s = TC2_ENOMEM;
   }
@@ -685,6 +790,35 @@ extern "C" TC2_API tc2_status tc2_lowdin(const tc2_bsr* S, const tc2_bsr* H, int
   return s;
 }
 
+extern "C" TC2_API tc2_status tc2_lowdin_response(const tc2_bsr* S, const tc2_bsr* H,
+                                                  int32_t n_dir, const tc2_bsr* H1,
+                                                  const tc2_bsr* S1,
+                                                  const tc2_lowdin_options* opts,
+                                                  tc2_lowdin_response_result* res) {
+  if (!res) return TC2_EINVAL;
+  std::memset(res, 0, sizeof(*res));
+  tc2_status s;
+  if (n_dir > 0 && !S1) {
+    s = TC2_EINVAL;
+  } else {
+    try {
+      s = lowdin_core(S, H, n_dir, H1, n_dir > 0 ? S1 : nullptr, opts,
+                      LowdinOut{&res->iters, &res->resid, &res->lambda, &res->seconds, &res->Z,
+                                &res->H, res->H1, res->Z1});
+    } catch (...) {
+      s = TC2_ENOMEM;
+    }
+  }
+  if (s < 0) {
+    release(&res->Z);
+    release(&res->H);
+    for (tc2_bsr& m : res->H1) release(&m);
+    for (tc2_bsr& m : res->Z1) release(&m);
+  }
+  res->status = s;
+  return s;
+}
+
 extern "C" TC2_API tc2_status tc2_congruence(const tc2_bsr* Z, const tc2_bsr* X,
                                              const tc2_lowdin_options* opts, tc2_bsr* out,
                                              double* seconds) {
@@ -692,9 +826,29 @@ extern "C" TC2_API tc2_status tc2_congruence(const tc2_bsr* Z, const tc2_bsr* X,
   std::memset(out, 0, sizeof(*out));
   tc2_status s;
   try {
-    s = congruence_impl(Z, X, opts, out, seconds);
+    s = congruence_impl(Z, X, nullptr, nullptr, opts, out, seconds);
   } catch (...) {
     s = TC2_ENOMEM;
+  }
+  if (s < 0) release(out);
+  return s;
+}
+
+extern "C" TC2_API tc2_status tc2_congruence_response(const tc2_bsr* Z, const tc2_bsr* Z1,
+                                                      const tc2_bsr* X, const tc2_bsr* X1,
+                                                      const tc2_lowdin_options* opts,
+                                                      tc2_bsr* out, double* seconds) {
+  if (!out) return TC2_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  tc2_status s;
+  if (!Z1 || !X1) {
+    s = TC2_EINVAL;
+  } else {
+    try {
+      s = congruence_impl(Z, X, Z1, X1, opts, out, seconds);
+    } catch (...) {
+      s = TC2_ENOMEM;
+    }
   }
   if (s < 0) release(out);
   return s;

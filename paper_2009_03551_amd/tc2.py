@@ -100,7 +100,8 @@ def lib() -> C.CDLL:
 
 EXPORTED = ("tc2_setup", "tc2_run", "tc2_free", "tc2_strerror", "tc2_version",
             "tc2_mlp_forward", "tc2_mlp_grad", "tc2_mlp_train", "tc2_log_copy",
-            "tc2_dense_response", "tc2_lowdin", "tc2_congruence", "tc2_bsr_release")
+            "tc2_dense_response", "tc2_lowdin", "tc2_congruence", "tc2_bsr_release",
+            "tc2_lowdin_response", "tc2_congruence_response")
 
 MLP_IN, MLP_PARAMS = 8, 4801
 
@@ -501,6 +502,86 @@ def congruence(Z: BSR, X: BSR, eps: float = 1e-6, device: int = 0,
     st = L.tc2_congruence(C.byref(cZ), C.byref(cX), C.byref(o), C.byref(out), C.byref(sec))
     if st < 0:
         raise TC2Error(st, "tc2_congruence")
+    try:
+        return _py_bsr(out)
+    finally:
+        _release(out)
+
+
+# ---------------------------------------------------------------- moving overlap (displacements)
+class tc2_lowdin_response_result(C.Structure):
+    _fields_ = [("status", C.c_int), ("iters", C.c_int32), ("resid", C.c_double),
+                ("lam", C.c_double), ("seconds", C.c_double), ("Z", tc2_bsr), ("H", tc2_bsr),
+                ("Z1", tc2_bsr * 3), ("H1", tc2_bsr * 3)]
+
+
+@dataclass
+class LowdinResponseResult:
+    status: int
+    iters: int
+    resid: float
+    lam: float
+    seconds: float
+    Z: BSR                      # S^-1/2
+    H: BSR                      # S^-1/2 H S^-1/2
+    Z1: List[BSR]               # derivative of S^-1/2 along S1_d
+    H1: List[BSR]               # Z1 H Z + Z H1_d Z + Z H Z1
+
+
+def lowdin_response(S: BSR, H: BSR, H1: Sequence[BSR], S1: Sequence[BSR], eps: float = 1e-6,
+                    tol: float = 1e-9, max_iter: int = 50, device: int = 0,
+                    stream: Optional[int] = None) -> LowdinResponseResult:
+    """S^-1/2, its derivatives along S1_d, and the orthogonal forms of H and of
+    perturbations that move the overlap (``tc2_lowdin_response``)."""
+    keep: list = []
+    cS, cH = _c_bsr(S, keep), _c_bsr(H, keep)
+    D = len(H1)
+    assert len(S1) == D
+    a1, s1 = (tc2_bsr * 3)(), (tc2_bsr * 3)()
+    for d in range(D):
+        a1[d] = _c_bsr(H1[d], keep)
+        s1[d] = _c_bsr(S1[d], keep)
+    o = tc2_lowdin_options(float(eps), float(tol), int(max_iter), int(device),
+                           C.c_void_p(stream) if stream else None)
+    r = tc2_lowdin_response_result()
+    L = lib()
+    L.tc2_lowdin_response.restype = C.c_int
+    L.tc2_lowdin_response.argtypes = [C.POINTER(tc2_bsr), C.POINTER(tc2_bsr), C.c_int32,
+                                      C.POINTER(tc2_bsr), C.POINTER(tc2_bsr),
+                                      C.POINTER(tc2_lowdin_options),
+                                      C.POINTER(tc2_lowdin_response_result)]
+    st = L.tc2_lowdin_response(C.byref(cS), C.byref(cH), D, a1, s1, C.byref(o), C.byref(r))
+    if st < 0:
+        raise TC2Error(st, "tc2_lowdin_response")
+    try:
+        out = LowdinResponseResult(r.status, r.iters, r.resid, r.lam, r.seconds, _py_bsr(r.Z),
+                                   _py_bsr(r.H), [_py_bsr(r.Z1[d]) for d in range(D)],
+                                   [_py_bsr(r.H1[d]) for d in range(D)])
+    finally:
+        _release(r.Z)
+        _release(r.H)
+        for d in range(D):
+            _release(r.Z1[d])
+            _release(r.H1[d])
+    return out
+
+
+def congruence_response(Z: BSR, Z1: BSR, X: BSR, X1: BSR, eps: float = 1e-6, device: int = 0,
+                        stream: Optional[int] = None) -> BSR:
+    """Z1 X Z + Z X1 Z + Z X Z1 (``tc2_congruence_response``)."""
+    keep: list = []
+    cZ, cZ1, cX, cX1 = (_c_bsr(m, keep) for m in (Z, Z1, X, X1))
+    o = tc2_lowdin_options(float(eps), 1.0, 1, int(device), C.c_void_p(stream) if stream else None)
+    out = tc2_bsr()
+    sec = C.c_double()
+    L = lib()
+    L.tc2_congruence_response.restype = C.c_int
+    L.tc2_congruence_response.argtypes = [C.POINTER(tc2_bsr)] * 4 + [
+        C.POINTER(tc2_lowdin_options), C.POINTER(tc2_bsr), C.POINTER(C.c_double)]
+    st = L.tc2_congruence_response(C.byref(cZ), C.byref(cZ1), C.byref(cX), C.byref(cX1),
+                                   C.byref(o), C.byref(out), C.byref(sec))
+    if st < 0:
+        raise TC2Error(st, "tc2_congruence_response")
     try:
         return _py_bsr(out)
     finally:

@@ -166,3 +166,77 @@ def test_lowdin_cube10_full_size():
         for J, blk in out.items():
             want = np.eye(b) if J == I else np.zeros((b, b))
             assert np.abs(blk - want).max() < 1e-4, (I, J)
+
+
+# ---------------------------------------------------------------- moving overlap (displacements)
+def displaced(case):
+    s = CASES[case]()
+    S = W.make_overlap(s, amp=0.2)
+    H1, S1 = W.make_displacement(s, atom=s.H.nb // 2)
+    return s, S, H1, S1
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-6])
+@pytest.mark.parametrize("case", ["chain", "ragged_b5", "cube_b13"])
+def test_lowdin_response_matches_oracle(case, eps):
+    s, S, H1, S1 = displaced(case)
+    b = s.H.b
+    tol, max_iter, want_status = (1e-10, 40, 0) if eps == 0.0 else (1e-14, 3, 1)
+    g = T.lowdin_response(S, s.H, [H1], [S1], eps=eps, tol=tol, max_iter=max_iter)
+    o = L.lowdin_response(dense(S), [dense(S1)], dense(s.H), [dense(H1)], b, eps, tol, max_iter)
+    print(f"  {case} eps={eps}: iters {g.iters} Z1 blocks {g.Z1[0].row_ptr[-1]} "
+          f"H1_orth blocks {g.H1[0].row_ptr[-1]} {g.seconds * 1e3:.1f} ms", flush=True)
+    assert g.status == want_status and o.status == want_status and g.iters == o.iters
+    for got, want in [(g.Z, o.Z), (g.H, o.H), (g.Z1[0], o.Z1[0]), (g.H1[0], o.H1[0])]:
+        Gd = dense(got)
+        assert np.array_equal(Gd, Gd.T)
+        assert np.array_equal(block_pattern(Gd, b), block_pattern(want, b))
+        assert np.abs(Gd - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
+
+
+def test_field_case_of_the_response_entry_is_unchanged():
+    # S1 = 0: the same Z and H1_orth as tc2_lowdin, and Z1 = 0
+    s, S, H1, S1 = displaced("chain")
+    z = W.BSR(S1.nb, S1.b, np.zeros(S1.nb + 1, dtype=np.int64), np.zeros(0, dtype=np.int32),
+              np.zeros((0, S1.b, S1.b)))
+    g = T.lowdin_response(S, s.H, [H1], [z], eps=1e-6)
+    f = T.lowdin(S, s.H, [H1], eps=1e-6)
+    assert g.Z1[0].row_ptr[-1] == 0
+    assert np.array_equal(dense(g.Z), dense(f.Z)) and np.array_equal(dense(g.H1[0]), dense(f.H1[0]))
+
+
+def test_congruence_response_matches_oracle():
+    s, S, H1, S1 = displaced("cube_b13")
+    g = T.lowdin_response(S, s.H, [H1], [S1], eps=1e-7)
+    X, X1 = s.H, H1                                  # any symmetric pair
+    got = dense(T.congruence_response(g.Z, g.Z1[0], X, X1, eps=1e-7))
+    want = L.congruence_response(dense(g.Z), dense(g.Z1[0]), dense(X), dense(X1), s.H.b, 1e-7)
+    assert np.array_equal(got, got.T)
+    assert np.array_equal(block_pattern(got, s.H.b), block_pattern(want, s.H.b))
+    assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+
+
+def test_displacement_pipeline_reaches_the_generalised_response():
+    # Loewdin with the overlap derivative -> TC2 / TC2-CPSCF on H_orth and
+    # H1_orth -> three-term back-transform, all on the GPU, against finite
+    # differences of the projector of H C = S C E when H and S both move
+    s, S, H1, S1 = displaced("cube_b13")
+    eps = 1e-10
+    g = T.lowdin_response(S, s.H, [H1], [S1], eps=eps, tol=1e-9, max_iter=20)
+    orth = W.System(H=g.H, H1=g.H1, n_occ=s.n_occ, xyz=s.xyz, eps=eps, tol=1e-11)
+    r = T.solve(orth, precision="fp64")[0]
+    assert r.status >= 0
+    P1 = dense(T.congruence_response(g.Z, g.Z1[0], r.X0, r.X1[0], eps=eps))
+    H, Sd, H1d, S1d = dense(s.H), dense(S), dense(H1), dense(S1)
+
+    def proj(x):
+        e, C = scipy.linalg.eigh(H + x * H1d, Sd + x * S1d)
+        Co = C[:, :s.n_occ]
+        return Co @ Co.T
+    h = 1e-5
+    fd = (proj(h) - proj(-h)) / (2 * h)
+    d1 = np.abs(P1 - fd).max()
+    print(f"  displacement: max|dP1| {d1:.2e} (max|P1| {np.abs(fd).max():.2e}; NS {g.iters}, "
+          f"TC2 {r.iters} updates)", flush=True)
+    assert np.abs(fd).max() > 1e-3
+    assert d1 < 1e-6
