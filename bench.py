@@ -192,13 +192,26 @@ def lowdin_pipeline(args) -> int:
     s = W.config_system(args.workload)
     S = W.make_overlap(s, amp=0.2)
     eps = s.eps
-    line = {"mode": "lowdin", "workload": args.workload, "atoms": s.H.nb, "N": s.H.n,
-            "b": s.H.b, "dirs": len(s.H1), "eps": eps, "S_blocks": int(S.row_ptr[-1])}
+    disp = args.displacement
+    if disp:  # one displacement of the central atom instead of the field directions
+        H1d, S1d = W.make_displacement(s, atom=s.H.nb // 2)
+        H1s, S1s = [H1d], [S1d]
+    else:
+        H1s, S1s = s.H1, None
+    line = {"mode": "lowdin_displacement" if disp else "lowdin", "workload": args.workload,
+            "atoms": s.H.nb, "N": s.H.n, "b": s.H.b, "dirs": len(H1s), "eps": eps,
+            "S_blocks": int(S.row_ptr[-1])}
+
+    def orthogonalise():
+        if disp:
+            return T.lowdin_response(S, s.H, H1s, S1s, eps=eps, tol=1e-9, max_iter=40,
+                                     stream=stream)
+        return T.lowdin(S, s.H, H1s, eps=eps, tol=1e-9, max_iter=40, stream=stream)
     for _ in range(args.warmup):
-        T.lowdin(S, s.H, s.H1, eps=eps, tol=1e-9, max_iter=40, stream=stream)
+        orthogonalise()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    g = T.lowdin(S, s.H, s.H1, eps=eps, tol=1e-9, max_iter=40, stream=stream)
+    g = orthogonalise()
     torch.cuda.synchronize()
     line.update(lowdin_s=time.perf_counter() - t0, lowdin_device_s=g.seconds,
                 ns_status=g.status, ns_updates=g.iters, ns_resid=g.resid,
@@ -214,10 +227,15 @@ def lowdin_pipeline(args) -> int:
     torch.cuda.synchronize()
     solver.close()
     line.update(tc2_s=time.perf_counter() - t0, tc2_status=r.status_name, tc2_updates=r.iters,
-                alpha=r.alpha)
+                trace_x1h1=r.alpha)
     t0 = time.perf_counter()
     P0 = T.congruence(g.Z, r.X0, eps=eps, stream=stream)
-    P1 = [T.congruence(g.Z, x, eps=eps, stream=stream) for x in r.X1]
+    if disp:
+        P1 = [T.congruence_response(g.Z, z1, r.X0, x, eps=eps, stream=stream)
+              for z1, x in zip(g.Z1, r.X1)]
+        line["Z1_blocks"] = [int(z.row_ptr[-1]) for z in g.Z1]
+    else:
+        P1 = [T.congruence(g.Z, x, eps=eps, stream=stream) for x in r.X1]
     torch.cuda.synchronize()
     line.update(back_transform_s=time.perf_counter() - t0, P0_blocks=int(P0.row_ptr[-1]),
                 P1_blocks=[int(p.row_ptr[-1]) for p in P1])
@@ -265,6 +283,10 @@ def main() -> int:
                     help="only time the non-orthogonal pipeline on the workload with a synthetic "
                          "overlap: Loewdin orthogonalisation, the TC2 solve of the orthogonal "
                          "forms, and the back-transform of X0 and X1 (one JSON line)")
+    ap.add_argument("--displacement", action="store_true",
+                    help="with --lowdin: the perturbation is a displacement of the central atom, "
+                         "which moves the overlap too (derivative of S^-1/2, three-term "
+                         "back-transform)")
     ap.add_argument("--sizes", default=None,
                     help="crossover sizes: lattice edges (cube) or atom counts (chain), "
                          "comma-separated")
