@@ -292,7 +292,7 @@ def main() -> int:
                          "comma-separated")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this library has "
               "no multi-GPU path", file=sys.stderr)
         return 2
 
@@ -447,7 +447,7 @@ def main() -> int:
         gate = {"max_abs_dX1": dx1, "rel_dalpha": dal, "pass": bool(dx1 < 1e-6 and dal < 1e-6),
                 "against": "plain FP64 GPU path"}
     # the learned screen against the exact one on the same variant: what it
-    # saves and the error it introduces (the exact-screen run is the judge)
+    # saves and the error it introduces (measured against the exact-screen run)
     mlp_vs_bound = None
     if args.skip == "mlp":
         bkw = dict(variant, skip="bound")

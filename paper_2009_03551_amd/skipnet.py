@@ -6,8 +6,8 @@
 2. ``train`` fits the network on the device with the library's own forward,
    gradient and Adam kernels (``tc2_mlp_train``).
 3. Solves with ``skip="mlp"`` then skip the candidates whose predicted drop
-   probability exceeds the threshold; the exact-screen run of the same input is
-   the judge of the error this introduces.
+   probability exceeds the threshold; the error this introduces is measured
+   against the exact-screen run of the same input.
 """
 from __future__ import annotations
 

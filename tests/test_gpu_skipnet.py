@@ -1,6 +1,6 @@
 """Learned block skip: logged training data, GPU-trained network, and what it
 gains over the exact norm-bound screen on a system it was not trained on.
-The exact-screen solve is the judge of the error the network introduces."""
+The error the network introduces is measured against the exact-screen solve."""
 import numpy as np
 import pytest
 
