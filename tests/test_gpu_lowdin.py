@@ -31,6 +31,8 @@ CASES = {
     "ragged_b5": lambda: W.config_system("chain64", n=11, b=5),
     "cube_b13": lambda: W.config_system("cube10", L=4),
     "three_dirs": lambda: W.config_system("cube20", L=3),
+    "b16": lambda: W.config_system("chain64", n=9, b=16, occ=6),
+    "b2": lambda: W.config_system("chain64", n=9, b=2, occ=1),
 }
 
 

@@ -68,6 +68,30 @@ def test_cube_b13_fp64(kernel):
     compare(s, g, o)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("b,occ", [(16, 6), (2, 1)])
+def test_block_size_extremes(kernel, b, occ):
+    # b = 16 fills the MFMA tile with no padding (four full K-steps); b = 2
+    # uses one ragged K-step of a mostly empty tile
+    s = W.config_system("chain64", n=29, b=b, occ=occ, eps=1e-6, seed=23)
+    g, o = run_both(s, kernel=kernel)
+    compare(s, g, o)
+
+
+@pytest.mark.parametrize("b,occ", [(16, 6), (2, 1)])
+def test_block_size_extremes_fp32_wide(b, occ):
+    from oracle import exact as E
+    s = W.config_system("chain64", n=29, b=b, occ=occ, eps=1e-9, seed=23)
+    g = T.solve(s, precision="fp32", wide=True, closing_fp64=2, fp64_first=2)[0]
+    H = O.bsr_to_dense(s.H.nb, s.H.b, s.H.row_ptr, s.H.col, s.H.val)
+    H1 = O.bsr_to_dense(s.H1[0].nb, b, s.H1[0].row_ptr, s.H1[0].col, s.H1[0].val)
+    dx1 = np.abs(T.bsr_dense(g.X1[0]) - E.exact_response(H, H1, s.n_occ)).max()
+    dal = abs(g.alpha[0] - E.exact_alpha(H, H1, s.n_occ)) / abs(E.exact_alpha(H, H1, s.n_occ))
+    print(f"  b={b}: {g.status_name} it={g.iters} max|dX1| {dx1:.2e} rel|dalpha| {dal:.2e}",
+          flush=True)
+    assert g.status >= 0 and dx1 < 1e-6 and dal < 1e-6
+
+
 def test_cube_clusters_without_positions():
     # clusters taken in index order when no positions are given
     s = W.config_system("cube10", L=4)
