@@ -98,6 +98,62 @@ def copy_calibration(mib: int, reps: int) -> int:
     return 0
 
 
+def peak_probe() -> int:
+    """Attainable peaks on this device, beside the published ones: dense FP32
+    and FP64 GEMMs of 8192^3 through the vendor BLAS (torch.matmul), and a
+    4 GiB device copy.  One JSON line."""
+    import torch
+    out = {"mode": "peak_probe", "device": torch.cuda.get_device_name(0)}
+    torch.backends.cuda.matmul.allow_tf32 = False
+    for name, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        n = 8192
+        a = torch.randn(n, n, dtype=dt, device="cuda")
+        b = torch.randn(n, n, dtype=dt, device="cuda")
+        for _ in range(3):
+            torch.matmul(a, b)
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            torch.matmul(a, b)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / reps
+        out[f"gemm_{name}_tflops"] = round(2.0 * n ** 3 / dt_s / 1e12, 1)
+        del a, b
+    n = (4 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt_s = (time.perf_counter() - t0) / reps
+    out["copy_GBps_read_plus_write"] = round(2 * n * 4 / dt_s / 1e9, 1)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def measured_peaks():
+    """Attainable peaks from the committed probe summary, or None."""
+    path = os.path.join(ROOT, "profiles", "peaks_measured.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                try:
+                    vals[k.strip()] = float(v.strip().strip("`"))
+                except ValueError:
+                    pass
+    return vals or None
+
+
 def cpu_baseline(sysm, gpu_iters: int, useful_flops: float, iters_sample: int = 1) -> dict:
     """The FP64 oracle on the host cores: ``iters_sample`` full-size TC2 updates
     (dense products, block drop, band energies) timed, scaled to a whole solve
@@ -276,6 +332,8 @@ def main() -> int:
                     help="skip the plain FP64 runs and the gate (profiling the chosen variant alone)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--peak-probe", action="store_true",
+                    help="only measure attainable peaks (FP32 and FP64 GEMMs, a device copy)")
     ap.add_argument("--crossover", choices=["cube", "chain"], default=None,
                     help="only time the linear-scaling path against the dense O(N^3) path "
                          "over a series of sizes (one JSON line per size)")
@@ -307,6 +365,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration, 10)
+    if args.peak_probe:
+        return peak_probe()
     if args.crossover:
         return crossover(args)
     if args.lowdin:
@@ -435,6 +495,10 @@ def main() -> int:
     dom_flops = sum(x.useful_flops_kind[dom] for x in last)
     achieved = dom_flops / (ms_kind[dom] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[("fp64", "fp32", "bf16", "fp32")[dom]]
+    # attainable peak of the same dtype from the committed GEMM probe (bf16
+    # was not probed)
+    pm = measured_peaks() or {}
+    pk_meas = pm.get({0: "gemm_fp64_tflops", 1: "gemm_fp32_tflops", 3: "gemm_fp32_tflops"}.get(dom, ""))
     kname = kernel_name(args.kernel, dom, len(sysm.H1), r.tile_shape[dom], sysm.H.b)
     log(f"{chosen}: {ms_per_step:.1f} ms/solve, numeric {ms_num:.1f} ms in {launches} launches, "
         f"useful {useful / 1e12:.3f} TF, executed {executed / 1e12:.3f} TF")
@@ -504,6 +568,8 @@ def main() -> int:
                      "kernel": kname, "achieved": round(achieved, 3),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": traffic,
+                     "peak_measured": pk_meas,
+                     "frac_of_measured": (round(achieved / pk_meas, 4) if pk_meas else None),
                      "launches_per_solve": dom_launches,
                      "avg_launch_ms": round(ms_kind[dom] / max(dom_launches, 1), 4),
                      "useful_tflop_per_solve": round(dom_flops / 1e12, 4),
