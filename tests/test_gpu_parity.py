@@ -69,6 +69,15 @@ def test_cube_b13_fp64(kernel):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
+def test_purification_without_directions(kernel):
+    # D = 0: X0 alone (TC2 without the response)
+    s = W.config_system("cube10", L=4, n_dir=0)
+    g, o = run_both(s, kernel=kernel)
+    assert g.X1 == [] and g.alpha == []
+    compare(s, g, o)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("b,occ", [(16, 6), (2, 1)])
 def test_block_size_extremes(kernel, b, occ):
     # b = 16 fills the MFMA tile with no padding (four full K-steps); b = 2
