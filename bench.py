@@ -221,6 +221,10 @@ def crossover(args) -> int:
             line[name + "_s"] = (time.perf_counter() - t0) / args.steps
             line[name + "_alpha"] = r.alpha[0] if r.alpha else None
             solver.close()
+        if s.H.n > T.DENSE_MAX_N or args.no_dense:
+            line["dense_s"] = None  # beyond the dense path's size limit, or not asked for
+            print(json.dumps(line), flush=True)
+            continue
         T.dense_response(s, stream=stream)  # warm-up (library kernels, workspace)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -345,6 +349,8 @@ def main() -> int:
                     help="with --lowdin: the perturbation is a displacement of the central atom, "
                          "which moves the overlap too (derivative of S^-1/2, three-term "
                          "back-transform)")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="crossover: time the linear-scaling path only")
     ap.add_argument("--sizes", default=None,
                     help="crossover sizes: lattice edges (cube) or atom counts (chain), "
                          "comma-separated")
