@@ -569,6 +569,7 @@ def main() -> int:
         "gate": gate,
         "mlp_vs_bound": mlp_vs_bound,
         "useful_tflop_per_solve": round(useful / 1e12, 4),
+        "nominal_tflop_per_solve": round(sum(x.nominal_flops for x in last) / 1e12, 4),
         "executed_tflop_per_solve": round(executed / 1e12, 4),
         "roofline": {"bound": "mfma",
                      "kernel": kname, "achieved": round(achieved, 3),

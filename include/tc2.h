@@ -160,6 +160,10 @@ typedef struct {
   double ms_numeric_kind[4];
   int32_t numeric_launches_kind[4];
   int32_t graph_updates;   /* updates run as a captured graph                   */
+  double nominal_flops;    /* 2 b^3 (1 + 2D) per block triple of the full products
+                              on each update's input pattern (sum over rows K of
+                              m_K^2): the work of full sparse products, as the
+                              paper counts it, against useful_flops            */
   char branches[TC2_MAX_ITER + 4]; /* 'S'/'D' per update, NUL-terminated        */
   /* Library-owned host copies (valid until the next tc2_run or tc2_free) when
      export_matrices = 1; same layout as the inputs.  Otherwise zeroed. */

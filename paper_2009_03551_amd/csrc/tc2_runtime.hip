@@ -73,7 +73,23 @@ struct SysState {
   tc2_status status = TC2_OK;
   double trip = 0;
   double trip_kind[4] = {0, 0, 0, 0};  // the same, per kernel kind
+  double nominal = 0;                  // full-product block triples (sum of m_K^2)
 };
+
+// Block triples (I, K, J) of the full product X X on the current pattern, per
+// active system: the sum over rows K of m_K^2, m_K the stored blocks of row K
+// (the pattern is symmetric).  This is the nominal count of a full sparse
+// product, as the paper accounts the work of an update, against which the
+// kept-output count of the kernels is the useful one.
+__global__ void k_nominal(int nb, const int* rp, const int* sys_of, const int* active,
+                          unsigned long long* acc) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
+    const int s = sys_of[i];
+    if (!active[s]) continue;
+    const unsigned long long m = (unsigned long long)(rp[i + 1] - rp[i]);
+    atomicAdd(&acc[s], m * m);
+  }
+}
 
 }  // namespace
 
@@ -124,6 +140,7 @@ struct tc2_ctx {
   bool kind_used[4] = {false, false, false, false};
   int skip = 0;                   // 1: exact norm-bound screen, 2: + skip network
   DBuf bn, screened;              // block norms, skip counters [exact, network]
+  DBuf nominal;                   // per system: sum over rows K of m_K^2, this update
   unsigned long long screened_total = 0, mlp_total = 0;
   DBuf mlp;                       // skip network parameters
   float mlp_z = 0.f;              // logit of the skip threshold
@@ -470,6 +487,7 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   if ((st = upload(ctx, ctx->eps, eps)) != TC2_OK) return fail(st);
   std::vector<int> zeros(np, 0);
   if ((st = upload(ctx, ctx->active, zeros)) != TC2_OK) return fail(st);
+  if (ctx->nominal.reserve((size_t)np * 8) != hipSuccess) return fail(TC2_ENOMEM);
   if ((st = upload(ctx, ctx->branch, zeros)) != TC2_OK) return fail(st);
   if ((st = upload(ctx, ctx->bad, zeros)) != TC2_OK) return fail(st);
   if (ctx->emin.reserve(np * 8) || ctx->emax.reserve(np * 8)) return fail(TC2_ENOMEM);
@@ -680,6 +698,17 @@ tc2_status measure(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal) {
   return TC2_OK;
 }
 
+// Zero the per-system nominal counters and count this update's full-product
+// triples on the pattern rp (stream work; also recorded into update graphs).
+tc2_status count_nominal(tc2_ctx* ctx, hipStream_t st, const int* rp) {
+  launch_fill_int(st, ctx->nominal.as<int>(), 0, 2LL * ctx->nsys);
+  const unsigned g = (unsigned)std::min(65535, (ctx->nb + 255) / 256);
+  hipLaunchKernelGGL(k_nominal, dim3(g), dim3(256), 0, st, ctx->nb, rp, ctx->sys_of.as<int>(),
+                     ctx->active.as<int>(), ctx->nominal.as<unsigned long long>());
+  HIPCHK(hipGetLastError());
+  return TC2_OK;
+}
+
 // One update of every active system: candidates (atom-level symbolic product
 // or cluster panels + tiles), numeric products with the fused epilogue,
 // copy-through of stopped systems, compaction into the next pattern.  Leaves
@@ -697,6 +726,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   for (int s = 0; s < ctx->nsys; ++s) any_stopped |= !ctx->h_active[s];
 
   if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[0], st));
+  if (tc2_status r = count_nominal(ctx, st, ctx->rp[c].as<int>()); r != TC2_OK) return r;
   int n_work = 0;          // work items (atom path) or tile blocks (tiled path)
   long long out_bound = 0; // upper bound of computed output blocks
   const int kind = ctx->cur_prec == P_FP64 ? K_FP64
@@ -1210,9 +1240,10 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
         (uintptr_t)ctx->rowcnt.p, (uintptr_t)ctx->cursor.p, (uintptr_t)ctx->sys_lo.p,
         (uintptr_t)ctx->sys_hi.p, (uintptr_t)ctx->panel_cnt.p, (uintptr_t)ctx->panel_rp.p,
         (uintptr_t)ctx->tile_cnt.p, (uintptr_t)ctx->tile_rp.p, (uintptr_t)ctx->tile_pairs.p,
-        (uintptr_t)ctx->tile_bits.p};
+        (uintptr_t)ctx->tile_bits.p, (uintptr_t)ctx->nominal.p};
     // the three parts of the update, as stream work (captured or not)
     auto rec_pre = [&]() {
+      (void)count_nominal(ctx, st, ctx->rp[c].as<int>());
       PanelArgs pa{};
       pa.nc = nc;
       pa.rp = ctx->rp[c].as<int>();
@@ -1520,6 +1551,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
   HIPCHK(hipMemcpyAsync(emax.data(), ctx->emax.p, nsys * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   std::vector<int> mode(nsys), active(nsys, 0), branch(nsys, 0), bad(nsys, 0);
+  std::vector<unsigned long long> nominal(nsys, 0);
   for (int s = 0; s < nsys; ++s) {
     mode[s] = ctx->sys[s].mode;
     ss[s].status = TC2_OK;
@@ -1634,6 +1666,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
       if (r != TC2_OK) return r;
     }
     HIPCHK(hipMemcpyAsync(bad.data(), ctx->bad.p, nsys * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(nominal.data(), ctx->nominal.p, nsys * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int s = 0; s < nsys; ++s) {
       if (!ss[s].active) continue;
@@ -1643,6 +1676,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
       S.k++;
       S.trip += q[Q_TRIP];
       S.trip_kind[ctx->last_kind] += q[Q_TRIP];
+      S.nominal += (double)nominal[s];
       double cur[1 + 2 * MAXD];
       energies(q, D, cur);
       const double iota = q[Q_TR0] - q[Q_FRO0];
@@ -1739,6 +1773,7 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
     R.emax = emax[s];
     R.seconds = ms * 1e-3;
     R.useful_flops = ss[s].trip * b3 * (1 + 2 * D);
+    R.nominal_flops = ss[s].nominal * b3 * (1 + 2 * D);
     R.executed_flops = (s == 0) ? (double)exec_pairs * (1 + 2 * D) * 2.0 * BP * BP * kst : 0.0;
     strncpy(R.branches, ss[s].branches.c_str(), TC2_MAX_ITER + 3);
     R.ms_symbolic = ctx->ms_sym;

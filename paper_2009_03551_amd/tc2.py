@@ -60,6 +60,7 @@ class tc2_result(C.Structure):
                 ("tile_shape", C.c_int32 * 4), ("ms_tune", C.c_double),
                 ("useful_flops_kind", C.c_double * 4), ("ms_numeric_kind", C.c_double * 4),
                 ("numeric_launches_kind", C.c_int32 * 4), ("graph_updates", C.c_int32),
+                ("nominal_flops", C.c_double),
                 ("branches", C.c_char * (TC2_MAX_ITER + 4)),
                 ("X0", tc2_bsr), ("X1", tc2_bsr * 3)]
 
@@ -203,6 +204,7 @@ class Result:
     graph_updates: int = 0
     X0: Optional[BSR] = None
     X1: List[BSR] = field(default_factory=list)
+    nominal_flops: float = 0.0
 
     @property
     def status_name(self) -> str:
@@ -300,7 +302,8 @@ class Solver:
                               r.ms_symbolic, r.ms_numeric, r.ms_compact,
                               r.numeric_launches, list(r.tile_shape), r.ms_tune,
                               list(r.useful_flops_kind), list(r.ms_numeric_kind),
-                              list(r.numeric_launches_kind), r.graph_updates, x0, x1))
+                              list(r.numeric_launches_kind), r.graph_updates, x0, x1,
+                              r.nominal_flops))
         return out
 
     def log(self):

@@ -228,3 +228,32 @@ def test_forced_stage_overflow(knob, dirs):
     s = W.config_system("cube20", L=4, n_dir=dirs, eps=1e-6)
     g, o = run_both(s)
     compare(s, g, o)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_nominal_flops_count_full_product_triples(kernel):
+    # nominal flops: 2 b^3 (1 + 2D) per block triple (I, K, J) of the full
+    # products on each update's input pattern, i.e. the sum over rows K of
+    # m_K^2 for the union block pattern of X0 and X1 (an integer count, exact)
+    s = W.config_system("cube10", L=4)
+    g = T.solve(s, kernel=kernel)[0]
+    b, D = s.H.b, len(s.H1)
+    H = O.bsr_to_dense(s.H.nb, b, s.H.row_ptr, s.H.col, s.H.val)
+    H1 = [O.bsr_to_dense(m.nb, b, m.row_ptr, m.col, m.val) for m in s.H1]
+    emin, emax = O.gershgorin(H)
+    X0, X1 = O.tc2_init(H, H1, emin, emax)
+    nb = s.H.nb
+    total = 0
+    for br in g.branches:
+        blocks = [X.reshape(nb, b, nb, b) for X in [X0] + X1]
+        pat = np.zeros((nb, nb), dtype=bool)
+        for B in blocks:
+            pat |= np.abs(B).sum(axis=(1, 3)) > 0
+        total += int((pat.sum(axis=1) ** 2).sum())
+        X0, X1 = O.tc2_step(X0, X1, br == "S")
+        X0 = O.block_drop(X0, b, s.eps)
+        X1 = [O.block_drop(x, b, s.eps) for x in X1]
+    want = total * 2.0 * b ** 3 * (1 + 2 * D)
+    print(f"  nominal {g.nominal_flops:.6e} oracle {want:.6e} useful {g.useful_flops:.6e}", flush=True)
+    assert g.nominal_flops == want
+    assert g.nominal_flops > g.useful_flops
