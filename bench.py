@@ -385,14 +385,7 @@ def main() -> int:
     if args.workload.startswith("batch"):
         n_sys = int(args.workload[5:] or 32)
         systems = W.batch_systems(n_sys=n_sys)
-        units, cur, acc = [], [], 0
-        for sy in systems:
-            if cur and acc + sy.H.nb > args.group_atoms:
-                units.append(cur)
-                cur, acc = [], 0
-            cur.append(sy)
-            acc += sy.H.nb
-        units.append(cur)
+        units = W.pack_units(systems, args.group_atoms)
     else:
         systems = [W.config_system(args.workload)]
         units = [systems]

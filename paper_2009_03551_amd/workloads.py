@@ -238,6 +238,24 @@ def config_system(name: str, **override) -> System:
                        name=name)
 
 
+def pack_units(systems: Sequence[System], max_atoms: int) -> List[List[System]]:
+    """Consecutive systems packed into units of at most ``max_atoms`` atoms
+    (a single larger system forms a unit of its own), so that the iterates
+    of one unit fit in device memory."""
+    units: List[List[System]] = []
+    cur: List[System] = []
+    acc = 0
+    for sy in systems:
+        if cur and acc + sy.H.nb > max_atoms:
+            units.append(cur)
+            cur, acc = [], 0
+        cur.append(sy)
+        acc += sy.H.nb
+    if cur:
+        units.append(cur)
+    return units
+
+
 def batch_systems(n_sys: int = 32, lo: int = 200, hi: int = 4000, seed: int = 4,
                   b: int = 13, n_dir: int = 3, eps: float = 1e-6,
                   tol: float = 1e-9, spacing: float = 2.5,

@@ -8,6 +8,15 @@ scalars, and a seeded sample of 32 blocks of X0 and X1.
 cube20 (8000 atoms, N = 104000, three directions): too large for the dense
 oracle; checked through properties that hold at any size (trace and
 idempotency of X0, traceless response, vanishing Tr(X1 H)).
+
+cube30 (27000 atoms, N = 351000, three directions, eps 1e-5) and one unit of
+the batch of 32 systems (seven systems, 14517 atoms, three directions,
+eps 1e-6) run in the variant the benchmark times and are checked through the
+same properties.  The truncation bounds how well they hold: each dropped
+block has Frobenius norm below eps, and the errors of Tr X0, of the
+idempotency and of Tr X1 at convergence are of the order N eps^2 (measured:
+at most 1.4 N eps^2 on these workloads).  The bound used is 20 N eps^2, and
+for Tr(X1 H) the same bound times the width of the Gershgorin interval.
 """
 import json
 import os
@@ -98,3 +107,54 @@ def test_cube20_invariants_three_directions():
         assert r.alpha[d] < 0
     # the three directions are equivalent on a cube up to the random couplings
     assert max(r.alpha) / min(r.alpha) > 0.9
+
+
+# the variant the benchmark times: FP32 products with FP64 sums, 4 leading
+# FP64 updates, the closing FP64 pair, the exact screen, updates as graphs
+BENCH_VARIANT = dict(precision="fp32", wide=True, fp64_first=4, closing_fp64=2, skip="bound",
+                     graph=True)
+
+
+def check_invariants(s, r):
+    n = s.H.nb * s.H.b
+    tau = 20.0 * n * s.eps ** 2
+    print(f"  {s.name}: {r.status_name} it={r.iters} tr-Nocc={r.tr_x0 - s.n_occ:.2e} "
+          f"idem={r.idem_err:.2e} trX1={[f'{x:.1e}' for x in r.tr_x1]} "
+          f"trX1H={[f'{x:.1e}' for x in r.e1]} alpha={[f'{x:.4e}' for x in r.alpha]} "
+          f"(bound {tau:.1e})", flush=True)
+    assert r.status in (0, 2)
+    assert abs(r.tr_x0 - s.n_occ) < tau
+    assert abs(r.idem_err) < tau
+    for d in range(len(s.H1)):
+        assert abs(r.tr_x1[d]) < tau
+        assert abs(r.e1[d]) < tau * (r.emax - r.emin)
+        assert r.alpha[d] < 0
+
+
+def test_cube30_invariants_in_the_benchmarked_variant():
+    s = W.config_system("cube30")
+    r = T.solve(s, export=False, **BENCH_VARIANT)[0]
+    print(f"  cube30: {r.seconds:.1f} s", flush=True)
+    check_invariants(s, r)
+    # the three directions are equivalent on a cube up to the random couplings
+    assert max(r.alpha) / min(r.alpha) > 0.99
+
+
+def test_batch32_unit_invariants_in_the_benchmarked_variant():
+    units = W.pack_units(W.batch_systems(n_sys=32), 16000)
+    u = units[2]
+    assert len(u) == 7 and sum(x.H.nb for x in u) == 14517
+    rs = T.solve(u, export=False, **BENCH_VARIANT)
+    print(f"  batch32 unit 2: {len(u)} systems, {rs[0].seconds:.1f} s", flush=True)
+    for s, r in zip(u, rs):
+        check_invariants(s, r)
+    # the polarisability is extensive: per atom, the systems of one recipe agree
+    per_atom = [np.mean(r.alpha) / s.H.nb for s, r in zip(u, rs)]
+    assert max(per_atom) / min(per_atom) < 1.1
+    # a system solved inside the batch and alone gives the same result
+    k = min(range(len(u)), key=lambda i: u[i].H.nb)
+    alone = T.solve(u[k], export=False, **BENCH_VARIANT)[0]
+    assert alone.iters == rs[k].iters and alone.branches == rs[k].branches
+    for x, y in zip(alone.alpha, rs[k].alpha):
+        assert abs(x - y) <= 1e-12 * abs(y)
+    assert abs(alone.tr_x0 - rs[k].tr_x0) <= 1e-12 * u[k].n_occ
