@@ -330,6 +330,9 @@ def main() -> int:
                          "numeric launch (tiled kernel)")
     ap.add_argument("--group-atoms", type=int, default=16000,
                     help="batch workloads: most atoms per context")
+    ap.add_argument("--units", default=None,
+                    help="batch workloads: comma-separated indices of the units to run "
+                         "(default: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=1)
     ap.add_argument("--no-reference", action="store_true",
@@ -386,6 +389,13 @@ def main() -> int:
         n_sys = int(args.workload[5:] or 32)
         systems = W.batch_systems(n_sys=n_sys)
         units = W.pack_units(systems, args.group_atoms)
+        if args.units:
+            pick = [int(x) for x in args.units.split(",")]
+            if any(not 0 <= i < len(units) for i in pick):
+                log(f"--units: indices must lie in 0..{len(units) - 1}")
+                return 2
+            units = [units[i] for i in pick]
+            systems = [sy for un in units for sy in un]
     else:
         systems = [W.config_system(args.workload)]
         units = [systems]
@@ -538,6 +548,8 @@ def main() -> int:
               "tile_shape": r.tile_shape, "graph_updates": r.graph_updates,
               "screened_blocks": sum(res[-1][0].screened_blocks for res in per),
               "mlp_skipped_blocks": sum(res[-1][0].mlp_skipped_blocks for res in per)}
+    if args.units:
+        config["unit_indices"] = [int(x) for x in args.units.split(",")]
     if len(systems) > 1:
         config["iters_range"] = [min(x.iters for x in last), max(x.iters for x in last)]
     out = {
