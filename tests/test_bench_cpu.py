@@ -1,0 +1,49 @@
+"""The benchmark's bookkeeping against the committed profile summaries (CPU
+only): the kernel name it looks up is the one the kernel trace records, the
+traffic and peak summaries parse, and the traffic figure belongs to the
+current kernel sources."""
+import os
+import re
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def test_kernel_names_match_the_kernel_trace():
+    with open(os.path.join(PROFILES, "k_tile_numeric_cube10_fp32w.txt")) as f:
+        text = f.read()
+    # default variant on cube10: b = 13 (full K-steps), one direction, 8 x 8 sub-tiles
+    wide = bench.kernel_name("tile", 3, 1, 0, 13)
+    fp64 = bench.kernel_name("tile", 0, 1, 0, 13)
+    assert f"tc2::{wide}(tc2::TileArgs)" in text
+    assert f"tc2::{fp64}(tc2::TileArgs)" in text
+    assert bench.kernel_name("block", 0, 2, -1, 8) == "k_numeric<double, 2>"
+
+
+def test_traffic_summary_belongs_to_the_current_sources():
+    path = os.path.join(PROFILES, "k_tile_numeric_cube10_fp32w_traffic.md")
+    with open(path) as f:
+        recorded = re.search(r"kernel_source_sha256_16: `([0-9a-f]{16})`", f.read()).group(1)
+    traffic = bench.measured_traffic("k_tile_numeric", "cube10", "fp32w")
+    if recorded == bench.kernel_source_hash():
+        assert traffic is not None and 1e9 < traffic < 1e12
+    else:  # the kernels changed since the counters were taken: reported as unknown
+        assert traffic is None
+
+
+def test_trace_summary_records_the_same_source_hash_as_the_traffic_summary():
+    with open(os.path.join(PROFILES, "k_tile_numeric_cube10_fp32w.txt")) as f:
+        trace = re.search(r"sha256\[:16\] = ([0-9a-f]{16})", f.read()).group(1)
+    with open(os.path.join(PROFILES, "k_tile_numeric_cube10_fp32w_traffic.md")) as f:
+        traffic = re.search(r"kernel_source_sha256_16: `([0-9a-f]{16})`", f.read()).group(1)
+    assert trace == traffic
+
+
+def test_measured_peaks_parse():
+    peaks = bench.measured_peaks()
+    assert peaks is not None
+    assert 0 < peaks["gemm_fp32_tflops"] <= bench.PEAK_TFLOPS["fp32"]
+    assert 0 < peaks["gemm_fp64_tflops"] <= bench.PEAK_TFLOPS["fp64"]
+    assert 0 < peaks["copy_GBps_read_plus_write"] <= bench.HBM_PEAK_GBS
