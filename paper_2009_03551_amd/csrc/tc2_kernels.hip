@@ -478,22 +478,36 @@ __global__ void k_gather(long long n, int D, const int* new_src, const T* stage,
 }
 
 // ------------------------------------------------------------------ reductions
-// Per system, the partial sums of its work items in a fixed order.
-__global__ __launch_bounds__(256) void k_reduce(const int* lo, const int* hi,
-                                                const double* partial, double* scal) {
-  __shared__ double sh[256];
+// Per system, the partial sums of its work items in a fixed order.  Thread t
+// adds the items t, t + RT, ... in one pass (the NQ sums of an item are
+// contiguous, so a wave reads consecutive memory); the wave sums follow a
+// fixed butterfly and the waves are added in wave order.
+constexpr int RT = 1024;
+__global__ __launch_bounds__(RT) void k_reduce(const int* lo, const int* hi,
+                                               const double* partial, double* scal) {
+  __shared__ double sh[RT / 64][NQ];
   const int s = blockIdx.x;
-  for (int k = 0; k < NQ; ++k) {
-    double v = 0.0;
-    for (int i = lo[s] + threadIdx.x; i < hi[s]; i += 256) v += partial[(size_t)i * NQ + k];
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) scal[s * NQ + k] = sh[0];
-    __syncthreads();
+  const int t = threadIdx.x, w = t >> 6;
+  double v[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) v[k] = 0.0;
+  const int end = hi[s];
+  for (int i = lo[s] + t; i < end; i += RT) {
+    const double* p = partial + (size_t)i * NQ;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) v[k] += p[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) v[k] = wave_sum(v[k]);
+  if ((t & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) sh[w][k] = v[k];
+  }
+  __syncthreads();
+  if (t < NQ) {
+    double acc = 0.0;
+    for (int j = 0; j < RT / 64; ++j) acc += sh[j][t];
+    scal[s * NQ + t] = acc;
   }
 }
 
@@ -658,7 +672,7 @@ void launch_gather(hipStream_t st, int prec, int nnz, int D, const int* new_src,
 
 void launch_reduce(hipStream_t st, int nsys, const int* lo, const int* hi,
                    const double* partial, double* scal) {
-  hipLaunchKernelGGL(k_reduce, dim3(nsys), dim3(256), 0, st, lo, hi, partial, scal);
+  hipLaunchKernelGGL(k_reduce, dim3(nsys), dim3(RT), 0, st, lo, hi, partial, scal);
 }
 
 void launch_export(hipStream_t st, int prec, int nnz, int D, int m, int b, const void* xv,
