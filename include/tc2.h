@@ -126,8 +126,9 @@ typedef struct {
                               captured hipGraph (persistent numeric launch, no
                               size read back within the update), replayed while
                               its buffers suffice.  Not with skip = 2, logging,
-                              or an update that is being tuned (those updates
-                              run without a graph); results are identical      */
+                              an update that is being tuned, or the closing
+                              FP64 pair (those updates run without a graph);
+                              results are identical                            */
 } tc2_options;
 
 typedef struct {

@@ -656,7 +656,15 @@ tc2_status convert_iterate(tc2_ctx* ctx, hipStream_t st, int to_prec) {
   int c = ctx->cur;
   long long n = (long long)ctx->nnz[c] * (1 + ctx->D) * BS;
   DBuf& dst = ctx->xv[c ^ 1];
-  HIPCHK(dst.reserve((size_t)n * prec_bytes(to_prec)));
+  const size_t need = (size_t)n * prec_bytes(to_prec);
+  // the stage holds nothing between updates: when it is large enough, take
+  // it instead of growing the destination (freeing and allocating tens of GB
+  // waits for the driver to clear the freed memory)
+  if (dst.cap < need && ctx->stage.cap >= need) {
+    std::swap(dst.p, ctx->stage.p);  // fields only: a DBuf frees its memory when destroyed
+    std::swap(dst.cap, ctx->stage.cap);
+  }
+  HIPCHK(dst.reserve(need));
   launch_convert(st, ctx->cur_prec, to_prec, n, ctx->xv[c].p, dst.p);
   // move the pattern along
   HIPCHK(ctx->rp[c ^ 1].reserve((size_t)(ctx->nb + 1) * 4));
@@ -1649,8 +1657,12 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
     {
       const int kind_now = ctx->cur_prec == P_FP64 ? K_FP64
                            : (ctx->op_bf16 ? K_BF16 : (ctx->wide ? K_WIDE : K_FP32));
+      // the closing pair runs as direct launches: two updates gain nothing
+      // from a captured graph, and sizing their FP64 buffers exactly (not by
+      // the graph's bounds) lets them fit in the buffers the reduced stage
+      // already holds
       const bool use_graph = ctx->graph && ctx->graph_ok && ctx->kernel == 0 &&
-                             ctx->log_cap == 0 && ctx->skip != 2 &&
+                             ctx->log_cap == 0 && ctx->skip != 2 && phase == 0 &&
                              (!ctx->tune || ctx->tuned[kind_now]);
       int g = 1;
       if (use_graph) {
