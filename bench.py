@@ -431,8 +431,11 @@ def main() -> int:
         (only one unit's exported matrices are held at a time)."""
         dx1 = dal = 0.0
         for u in units:
+            log(f"  exporting unit of {len(u)} system(s): first variant ...")
             ga = T.solve(u, export=True, **kw_a)
+            log("  ... second variant ...")
             gb = T.solve(u, export=True, **kw_b)
+            log("  ... comparing X1")
             dx1 = max([dx1] + [bsr_maxdiff(a, b) for g, f in zip(ga, gb) for a, b in zip(g.X1, f.X1)])
             dal = max([dal] + [abs(x - y) / abs(y) for g, f in zip(ga, gb)
                                for x, y in zip(g.alpha, f.alpha)])
