@@ -656,15 +656,7 @@ tc2_status convert_iterate(tc2_ctx* ctx, hipStream_t st, int to_prec) {
   int c = ctx->cur;
   long long n = (long long)ctx->nnz[c] * (1 + ctx->D) * BS;
   DBuf& dst = ctx->xv[c ^ 1];
-  const size_t need = (size_t)n * prec_bytes(to_prec);
-  // the stage holds nothing between updates: when it is large enough, take
-  // it instead of growing the destination (freeing and allocating tens of GB
-  // waits for the driver to clear the freed memory)
-  if (dst.cap < need && ctx->stage.cap >= need) {
-    std::swap(dst.p, ctx->stage.p);  // fields only: a DBuf frees its memory when destroyed
-    std::swap(dst.cap, ctx->stage.cap);
-  }
-  HIPCHK(dst.reserve(need));
+  HIPCHK(dst.reserve((size_t)n * prec_bytes(to_prec)));
   launch_convert(st, ctx->cur_prec, to_prec, n, ctx->xv[c].p, dst.p);
   // move the pattern along
   HIPCHK(ctx->rp[c ^ 1].reserve((size_t)(ctx->nb + 1) * 4));
