@@ -47,3 +47,17 @@ def test_measured_peaks_parse():
     assert 0 < peaks["gemm_fp32_tflops"] <= bench.PEAK_TFLOPS["fp32"]
     assert 0 < peaks["gemm_fp64_tflops"] <= bench.PEAK_TFLOPS["fp64"]
     assert 0 < peaks["copy_GBps_read_plus_write"] <= bench.HBM_PEAK_GBS
+
+
+def test_pack_units_keeps_order_and_bounds():
+    from paper_2009_03551_amd import workloads as W
+
+    class Sys:  # only the atom count matters for packing
+        def __init__(self, nb):
+            self.H = type("H", (), {"nb": nb})()
+
+    sizes = [5, 7, 3, 20, 2, 2, 9]
+    units = W.pack_units([Sys(n) for n in sizes], 12)
+    assert [[s.H.nb for s in u] for u in units] == [[5, 7], [3], [20], [2, 2], [9]]
+    assert all(sum(s.H.nb for s in u) <= 12 or len(u) == 1 for u in units)
+    assert W.pack_units([], 12) == []
