@@ -47,6 +47,29 @@ struct DBuf {
   template <typename T> T* as() const { return (T*)p; }
 };
 
+// Page-locked host memory for the small per-update transfers: copies to and
+// from it are plain DMAs, where pageable memory goes through staging copies.
+struct HostPin {
+  void* p = nullptr;
+  size_t cap = 0;
+  ~HostPin() {
+    if (p) (void)hipHostFree(p);
+  }
+  hipError_t reserve(size_t n) {
+    if (n <= cap && p) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipHostMalloc(&p, n, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    cap = n;
+    return hipSuccess;
+  }
+};
+
 struct HostBsr {
   std::vector<int64_t> row_ptr;
   std::vector<int32_t> col;
@@ -124,6 +147,8 @@ struct tc2_ctx {
   // work buffers
   DBuf cand_cnt, cand_rp, cand_ci, item_cnt, item_rp, item_row, item_c0, partial;
   DBuf stage, kept_ij, counters, exec_pairs, rowcnt, cursor, tmp_ci, tmp_src, new_src;
+  HostPin pin_graph;              // per-update readback of the graph path
+  HostPin pin_loop;               // active / branch flags in, bad / nominal out
   DBuf sys_lo, sys_hi, scal, rowlo, rowhi, xfer;
   long long stage_cap = 0;
   int kernel = 0;                 // 0 tiled, 1 one wave per block
@@ -1223,6 +1248,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     GRESERVE(ctx->ci[n].reserve(cap2 * 4));
     GRESERVE(ctx->xv[n].reserve(cap2 * tile));
     GRESERVE(ctx->scal.reserve((size_t)ctx->nsys * NQ * 8));
+    GRESERVE(ctx->pin_graph.reserve(64 + (size_t)ctx->nsys * NQ * 8));
     int* cnt = ctx->counters.as<int>();  // [1] stage count [2] overflow [4] work counter
 
     // what the graph captures: everything that would change a launch
@@ -1432,13 +1458,21 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     } else {
       HIPCHK(hipGraphLaunch(ctx->gexec[c], st));
     }
-    HIPCHK(hipMemcpyAsync(hcnt, cnt, sizeof(hcnt), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&pairs, ctx->exec_pairs.p, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&nnz_new, ctx->rp[n].as<int>() + nb, 4, hipMemcpyDeviceToHost, st));
-    if (screen) HIPCHK(hipMemcpyAsync(sc, ctx->screened.p, 16, hipMemcpyDeviceToHost, st));
+    // counters, pairs, new entries, screen counts and scalars, read back
+    // through page-locked memory: [hcnt 32 B | pairs 8 | nnz_new 8 | sc 16 | scal]
     scal.resize((size_t)ctx->nsys * NQ);
-    HIPCHK(hipMemcpyAsync(scal.data(), ctx->scal.p, scal.size() * 8, hipMemcpyDeviceToHost, st));
+    char* pin = (char*)ctx->pin_graph.p;
+    HIPCHK(hipMemcpyAsync(pin, cnt, sizeof(hcnt), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pin + 32, ctx->exec_pairs.p, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pin + 40, ctx->rp[n].as<int>() + nb, 4, hipMemcpyDeviceToHost, st));
+    if (screen) HIPCHK(hipMemcpyAsync(pin + 48, ctx->screened.p, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pin + 64, ctx->scal.p, scal.size() * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    memcpy(hcnt, pin, sizeof(hcnt));
+    memcpy(&pairs, pin + 32, 8);
+    memcpy(&nnz_new, pin + 40, 4);
+    if (screen) memcpy(sc, pin + 48, 16);
+    memcpy(scal.data(), pin + 64, scal.size() * 8);
     if (ctx->profile) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, ctx->pev[0], ctx->pev[1]));
@@ -1552,6 +1586,8 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
   HIPCHK(hipStreamSynchronize(st));
   std::vector<int> mode(nsys), active(nsys, 0), branch(nsys, 0), bad(nsys, 0);
   std::vector<unsigned long long> nominal(nsys, 0);
+  const size_t pin_nominal = ((size_t)nsys * 12 + 7) / 8 * 8;  // after three int arrays
+  HIPCHK(ctx->pin_loop.reserve(pin_nominal + (size_t)nsys * 8));
   for (int s = 0; s < nsys; ++s) {
     mode[s] = ctx->sys[s].mode;
     ss[s].status = TC2_OK;
@@ -1641,8 +1677,14 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
       }
       break;
     }
-    HIPCHK(hipMemcpyAsync(ctx->active.p, active.data(), nsys * 4, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ctx->branch.p, branch.data(), nsys * 4, hipMemcpyHostToDevice, st));
+    // flags in and status out through page-locked memory (the previous
+    // update's stream synchronisation guarantees its copies have completed):
+    // [active | branch | bad] ints, then nominal counts
+    char* pin = (char*)ctx->pin_loop.p;
+    memcpy(pin, active.data(), nsys * 4);
+    memcpy(pin + (size_t)nsys * 4, branch.data(), nsys * 4);
+    HIPCHK(hipMemcpyAsync(ctx->active.p, pin, nsys * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctx->branch.p, pin + (size_t)nsys * 4, nsys * 4, hipMemcpyHostToDevice, st));
     ctx->h_active = active;
     ctx->update_index = updates;
     tc2_status r = TC2_OK;
@@ -1669,9 +1711,11 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
       r = convert_iterate(ctx, st, P_FP32);
       if (r != TC2_OK) return r;
     }
-    HIPCHK(hipMemcpyAsync(bad.data(), ctx->bad.p, nsys * 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(nominal.data(), ctx->nominal.p, nsys * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pin + (size_t)nsys * 8, ctx->bad.p, nsys * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pin + pin_nominal, ctx->nominal.p, nsys * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    memcpy(bad.data(), pin + (size_t)nsys * 8, nsys * 4);
+    memcpy(nominal.data(), pin + pin_nominal, nsys * 8);
     for (int s = 0; s < nsys; ++s) {
       if (!ss[s].active) continue;
       SysState& S = ss[s];
