@@ -23,7 +23,12 @@ same readings on its own):
   filter or rounding, not the iteration, then sets it.
 * Products whose exact value is symmetric (Z Y, Y T, Z T, and the outer
   product of a congruence) keep the upper blocks of the computed product and
-  mirror them, so that the result is exactly symmetric.  The inner product of
+  mirror them, so that the result is exactly symmetric.  Without the filter
+  these products are symmetric up to rounding; with it, Z and Y are only
+  approximately functions of S and the computed product is symmetric up to
+  what the filter removed.  The part the mirror discards is pinned below
+  eps per element (per product and on the final S^-1/2, against the plain
+  product of every step: ``mirror=False``).  The inner product of
   a congruence, Q = Z X, is not symmetric and is kept whole.
 * Filter: after every product, an off-diagonal block whose Frobenius norm is
   strictly below eps is zeroed (for a symmetric product, with its mirror).
@@ -89,8 +94,15 @@ class InvSqrt:
 
 
 def newton_schulz_inv_sqrt(S: np.ndarray, b: int, eps: float, tol: float,
-                           max_iter: int) -> InvSqrt:
-    """S^-1/2 by the coupled Newton-Schulz iteration with the block filter."""
+                           max_iter: int, mirror: bool = True) -> InvSqrt:
+    """S^-1/2 by the coupled Newton-Schulz iteration with the block filter.
+
+    ``mirror=False`` forms every product plainly (``product``: each block of
+    the computed product filtered on its own, nothing mirrored).  Under the
+    filter Z and Y are no longer exact functions of S, so Z Y is symmetric
+    only up to what the filter removed; the tests bound the difference
+    between the two readings by eps."""
+    sym = symmetric_product if mirror else product
     N = S.shape[0]
     lam = gershgorin_upper(S)
     Y = S / lam
@@ -98,7 +110,7 @@ def newton_schulz_inv_sqrt(S: np.ndarray, b: int, eps: float, tol: float,
     iters = 0
     prev = None
     while True:
-        M = symmetric_product(Z, Y, b, eps)
+        M = sym(Z, Y, b, eps)
         resid = float(np.linalg.norm(M - np.eye(N)) / np.sqrt(N))
         if resid < tol:
             status = STATUS_OK
@@ -111,8 +123,8 @@ def newton_schulz_inv_sqrt(S: np.ndarray, b: int, eps: float, tol: float,
             status = STATUS_NOT_CONVERGED
             break
         T = 0.5 * (3.0 * np.eye(N) - M)
-        Y = symmetric_product(Y, T, b, eps)
-        Z = symmetric_product(Z, T, b, eps)
+        Y = sym(Y, T, b, eps)
+        Z = sym(Z, T, b, eps)
         iters += 1
     return InvSqrt(Z / np.sqrt(lam), iters, resid, lam, status)
 

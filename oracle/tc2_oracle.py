@@ -112,6 +112,34 @@ def band_energies(X0, X1s, H, H1s):
     return E0, E1, al
 
 
+def stopping_rule(k: int, prev, cur, iotas: Sequence[float], tol: float,
+                  stall_guard: bool = True) -> Optional[int]:
+    """Stopping decision after update k (k = 1, 2, ...), from the scalars of
+    the previous and the current iterate.
+
+    ``prev`` and ``cur`` are (E0, [E1_d], [alpha_d]) as returned by
+    band_energies; ``iotas`` holds iota_1 .. iota_k, iota = Tr X0 - ||X0||_F^2.
+
+    * Convergence (tolerance test of Sec. 2.3 on the band energies of
+      Sec. 2.2): k >= 2 and every one of |dE0|, |dE1_d|, |d alpha_d| is below
+      tol -> STATUS_OK.  alpha_d takes part because E1_d = Tr(X1_d H) tends to
+      0 for every response, converged or not.
+    * Stall guard (precision floor of the recursion in finite precision):
+      k >= 3, |iota_k| < 1 and |iota_k| >= |iota_{k-2}| -> STATUS_FLOOR.  The
+      comparison skips one update because the two branches alternate near the
+      fixed point and iota falls over pairs of updates, not every update.
+    * Otherwise None (continue)."""
+    d = [abs(cur[0] - prev[0])]
+    d += [abs(a - c) for a, c in zip(cur[1], prev[1])]
+    d += [abs(a - c) for a, c in zip(cur[2], prev[2])]
+    if k >= 2 and max(d) < tol:
+        return STATUS_OK
+    if stall_guard and k >= 3 and abs(iotas[k - 1]) < 1.0 and \
+            abs(iotas[k - 1]) >= abs(iotas[k - 3]):
+        return STATUS_FLOOR
+    return None
+
+
 @dataclass
 class OracleResult:
     X0: np.ndarray
@@ -171,16 +199,9 @@ def tc2_solve(H: np.ndarray, H1s: Sequence[np.ndarray], n_occ: int, b: int,
                                 E0=cur[0], E1=list(cur[1]), alpha=list(cur[2]),
                                 iota=iota))
         if replay is None:
-            d = [abs(cur[0] - prev[0])]
-            d += [abs(a - c) for a, c in zip(cur[1], prev[1])]
-            d += [abs(a - c) for a, c in zip(cur[2], prev[2])]
-            if k >= 2 and max(d) < tol:
-                status = STATUS_OK
-                prev = cur
-                break
-            if stall_guard and k >= 3 and abs(iotas[-1]) < 1.0 and \
-                    abs(iotas[-1]) >= abs(iotas[-3]):
-                status = STATUS_FLOOR
+            stop = stopping_rule(k, prev, cur, iotas, tol, stall_guard)
+            if stop is not None:
+                status = stop
                 prev = cur
                 break
         prev = cur

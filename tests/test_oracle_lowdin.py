@@ -180,3 +180,70 @@ def test_unchanged_overlap_reduces_to_the_field_case():
     assert np.array_equal(o.Z1[0], z)
     np.testing.assert_allclose(o.H1[0], f.H1[0], atol=1e-14)
     assert np.array_equal(o.Z, f.Z) and o.iters == f.iters
+
+
+# ---------------------------------------------------------------- the mirrored symmetric products
+def _ns_products(S, b, eps, iters=12):
+    """Newton-Schulz iterates (mirrored reading) and, for every product of
+    the iteration, the plain computed product A @ B next to the mirrored one."""
+    N = S.shape[0]
+    lam = L.gershgorin_upper(S)
+    Y, Z = S / lam, np.eye(N)
+    pairs = []
+    prev = None
+    for _ in range(iters):
+        M = L.symmetric_product(Z, Y, b, eps)
+        pairs.append((Z @ Y, M))
+        resid = np.linalg.norm(M - np.eye(N)) / np.sqrt(N)
+        if resid < 1e-13 or (prev is not None and resid > 0.5 * prev):
+            break
+        prev = resid
+        T = 0.5 * (3.0 * np.eye(N) - M)
+        Yn, Zn = L.symmetric_product(Y, T, b, eps), L.symmetric_product(Z, T, b, eps)
+        pairs += [(Y @ T, Yn), (Z @ T, Zn)]
+        Y, Z = Yn, Zn
+    return pairs
+
+
+@pytest.mark.parametrize("name", ["chain", "cube"])
+def test_mirrored_products_are_plain_products_at_eps_zero(name):
+    # without the filter the products of the iteration are exact functions of
+    # S, symmetric up to rounding: mirroring the upper blocks discards only that
+    s, S, _, _ = problem(name)
+    for C, Cm in _ns_products(S, s.H.b, 0.0):
+        assert np.abs(C - C.T).max() < 1e-14
+        assert np.abs(C - Cm).max() < 1e-14
+
+
+@pytest.mark.parametrize("name", ["chain", "cube"])
+@pytest.mark.parametrize("eps", [1e-8, 1e-6, 1e-4])
+def test_mirror_discards_less_than_eps(name, eps):
+    # with the filter: Z = f(S) + E_Z and Y = g(S) + E_Y, where f(S), g(S)
+    # commute and E_Z, E_Y hold what the filter removed (blocks of norm < eps,
+    # sparse in every block row).  Z Y - (Z Y)^T = [Z, Y] = [E_Z, g] + [f, E_Y]
+    # + [E_Z, E_Y] then stays of the order of eps, and the mirror keeps the
+    # upper half of the product: off the upper blocks it moves each element
+    # by |C - C^T|.  Within the filter's own resolution (below eps) the
+    # mirrored product is the plain product of the iteration.
+    s, S, _, _ = problem(name)
+    worst = 0.0
+    for C, Cm in _ns_products(S, s.H.b, eps):
+        Cf = L.product(C, np.eye(C.shape[0]), s.H.b, eps)   # plain product, filtered
+        worst = max(worst, np.abs(C - C.T).max())
+        # mirrored vs plain: differences only where the blocks differ by the
+        # asymmetry, or where one reading dropped a block near eps
+        assert np.abs(Cf - Cm).max() < eps
+    assert worst < eps
+
+
+@pytest.mark.parametrize("name", ["chain", "cube"])
+@pytest.mark.parametrize("eps", [1e-6, 1e-4])
+def test_mirrored_inverse_square_root_is_the_plain_one_within_eps(name, eps):
+    # the whole iteration, every product plain (no mirror, each block filtered
+    # on its own) against the mirrored reading used by the library
+    s, S, _, _ = problem(name)
+    a = L.newton_schulz_inv_sqrt(S, s.H.b, eps, 1e-12, 40)
+    p = L.newton_schulz_inv_sqrt(S, s.H.b, eps, 1e-12, 40, mirror=False)
+    assert a.iters == p.iters and a.status == p.status
+    assert np.abs(a.Z - p.Z).max() < eps
+    assert np.abs(p.Z - p.Z.T).max() < eps        # the plain result is symmetric within eps

@@ -303,3 +303,92 @@ def test_band_energies_hand():
     assert E0 == 3.0 - 2.0 - 2.0 + 1.0          # Tr(X0 H)
     assert E1 == [0.0 - 1.0 - 1.0 - 2.0]        # Tr(X1 H)
     assert al == [0.5]                          # Tr(X1 H1)
+
+
+# ---------------------------------------------------------------- stopping rule (Sec. 2.3 tolerance, stall guard)
+def _e(E0, E1, al):
+    """Scalars of one iterate in the form band_energies returns."""
+    return (E0, list(E1), list(al))
+
+
+def test_convergence_needs_two_updates():
+    # a change far below tol after the first update does not stop it: the
+    # first update compares with the unfiltered initial matrices
+    prev, cur = _e(1.0, [0.0], [-3.0]), _e(1.0, [0.0], [-3.0])
+    assert O.stopping_rule(1, prev, cur, [0.5], 1e-9) is None
+    assert O.stopping_rule(2, prev, cur, [0.5, 0.4], 1e-9) == O.STATUS_OK
+
+
+def test_convergence_is_strict_and_absolute():
+    tol = 1e-6
+    prev = _e(-100.0, [0.25], [-7.0])
+    falling = [0.5, 0.4, 0.3, 0.2, 0.1]   # the stall guard stays quiet
+    assert O.stopping_rule(5, prev, _e(-100.0 + 0.5e-6, [0.25], [-7.0]), falling, tol) == O.STATUS_OK
+    # |dE0| == tol (exactly representable) is not below tol
+    assert O.stopping_rule(5, prev, _e(-100.0 + 2.0 ** -20, [0.25], [-7.0]), falling,
+                           2.0 ** -20) is None
+
+
+def test_alpha_change_alone_blocks_convergence():
+    # E0 and Tr(X1 H) unchanged, the polarizability trace still moving
+    tol = 1e-9
+    prev = _e(-12.5, [1e-12], [-40.0])
+    cur = _e(-12.5, [1e-12], [-40.0 + 3e-9])
+    assert O.stopping_rule(6, prev, cur, [0.9, 0.8, 0.7, 0.6, 0.5, 0.4], tol) is None
+    # ... and only alpha: the same change in a second direction's alpha
+    prev2 = _e(-12.5, [0.0, 0.0], [-40.0, -41.0])
+    cur2 = _e(-12.5, [0.0, 0.0], [-40.0, -41.0 - 2e-9])
+    assert O.stopping_rule(6, prev2, cur2, [0.9, 0.8, 0.7, 0.6, 0.5, 0.4], tol) is None
+    # a change of E1_d alone blocks it too
+    cur3 = _e(-12.5, [0.0, 5e-9], [-40.0, -41.0])
+    assert O.stopping_rule(6, prev2, cur3, [0.9, 0.8, 0.7, 0.6, 0.5, 0.4], tol) is None
+
+
+def _guard(iotas):
+    """Stall-guard decision after the last of ``iotas``, with energies that
+    keep moving (so the convergence test cannot stop it)."""
+    k = len(iotas)
+    return O.stopping_rule(k, _e(0.0, [], []), _e(1.0, [], []), iotas, 1e-9)
+
+
+def test_stall_guard_compares_with_two_updates_back():
+    # |iota_3| >= |iota_1| while |iota_3| < |iota_2|: fires (k-2), where a
+    # comparison with k-1 would not
+    assert _guard([0.3, 0.6, 0.4]) == O.STATUS_FLOOR
+    # |iota_3| < |iota_1| while |iota_3| >= |iota_2|: does not fire, where a
+    # comparison with k-1 would
+    assert _guard([0.5, 0.3, 0.4]) is None
+    # equality fires (>=); signs do not matter (absolute values)
+    assert _guard([0.5, 0.1, -0.5]) == O.STATUS_FLOOR
+
+
+def test_stall_guard_needs_small_iota_and_three_updates():
+    # |iota| >= 1: far from idempotent, no floor yet
+    assert _guard([2.0, 1.5, 2.5]) is None
+    assert _guard([1.0, 0.5, 1.0]) is None
+    # fewer than three updates: nothing two updates back
+    assert _guard([0.3, 0.6]) is None
+    # a later index uses the right pair: iota_5 against iota_3 only
+    assert _guard([0.01, 0.9, 0.2, 0.1, 0.15]) is None     # 0.15 < 0.2
+    assert _guard([0.9, 0.01, 0.2, 0.1, 0.25]) == O.STATUS_FLOOR
+
+
+def test_convergence_is_tested_before_the_guard():
+    # both would stop: the tolerance test decides (status OK)
+    prev = cur = _e(0.5, [0.0], [-1.0])
+    assert O.stopping_rule(3, prev, cur, [0.3, 0.6, 0.4], 1e-9) == O.STATUS_OK
+
+
+def test_solve_stops_where_the_rule_first_fires():
+    # with an unreachable tolerance the guard alone stops the solve: at the
+    # first update k >= 3 with |iota_k| < 1 and |iota_k| >= |iota_{k-2}|
+    s = W.config_system("chain64", n=24)
+    r = O.solve_system(s, tol=1e-300, keep_history=True, max_iter=80)
+    io = [abs(h["iota"]) for h in r.history]
+    first = next(k for k in range(3, len(io) + 1)
+                 if io[k - 1] < 1.0 and io[k - 1] >= io[k - 3])
+    assert r.status == O.STATUS_FLOOR
+    assert r.iters == first == len(io) == 23
+    # on this run a guard comparing with k-1 would stop one update earlier
+    k1 = next(k for k in range(3, len(io) + 1) if io[k - 1] < 1.0 and io[k - 1] >= io[k - 2])
+    assert k1 == 22
