@@ -1,16 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the TC2 + response solve on one MI355X.
 
-One step = one complete solve (``tc2_run``): Gershgorin bounds, initial
-matrices, every TC2 / TC2-CPSCF update (symbolic pattern, MFMA block
-products, drop, reductions, branch) until the stopping rule, with the inputs
-already resident in HBM (uploaded by ``tc2_setup`` before timing).
+One step = one TC2 / TC2-CPSCF update (symbolic pattern, MFMA block
+products, drop, reductions and the branch of the next update) of the chosen
+precision variant, on the workload's systems with the inputs already
+resident in HBM (uploaded by ``tc2_setup`` before timing).  Steps run back to
+back through ``tc2_advance``: a solve that finishes within the timed steps
+is followed by the next one from H, so K steps are K updates of the solve
+sequence.  Batch workloads (many systems in memory-sized units) take one
+step = one solve of every unit.
 
-Prints one JSON line.  ``value`` is useful GFLOP/s of the chosen precision
-variant (2 b^3 per block triple landing on a kept output block, times the
-1 + 2D block products of an update); ``ms_per_step`` is seconds per solve in
-ms.  The plain FP64 path is run too and the chosen variant is gated against
-it (max |dX1| < 1e-6, relative |d alpha| < 1e-6).
+Prints one JSON line.  ``value`` is useful GFLOP/s over the timed steps (the
+exact count of useful block products, 2 b^3 each: X0 X0 on X0's stored
+blocks and kept outputs, X0 X1_d + X1_d X0 on their own operands and X1_d's
+kept outputs); ``ms_per_step`` is the time per update; ``s_per_solve`` is
+the device time of a complete solve of the same variant.  The plain FP64
+path is timed once and the chosen variant is gated against it on the device
+(max |dX1| < 1e-6, relative |d alpha| < 1e-6).
 """
 from __future__ import annotations
 
@@ -154,10 +160,10 @@ def measured_peaks():
     return vals or None
 
 
-def cpu_baseline(sysm, gpu_iters: int, useful_flops: float, iters_sample: int = 1) -> dict:
-    """The FP64 oracle on the host cores: ``iters_sample`` full-size TC2 updates
-    (dense products, block drop, band energies) timed, scaled to a whole solve
-    by the GPU's update count."""
+def cpu_baseline_dense(sysm, gpu_iters: int, useful_flops: float, iters_sample: int = 1) -> dict:
+    """The dense FP64 oracle on the host cores: ``iters_sample`` full-size TC2
+    updates (dense products, block drop, band energies) timed, scaled to a
+    whole solve by the GPU's update count (systems with N <= 20000)."""
     import numpy as np
     from oracle import tc2_oracle as O
     try:
@@ -185,6 +191,29 @@ def cpu_baseline(sysm, gpu_iters: int, useful_flops: float, iters_sample: int = 
             "s_per_solve": round(solve_s, 2),
             "sample": f"{iters_sample} dense FP64 oracle update(s) at full size "
                       f"(N={sysm.H.n}), {dt:.1f} s each, scaled by {gpu_iters} updates"}
+
+
+def cpu_baseline_bsr(name: str, sysm, useful_flops: float) -> dict:
+    """The block-list FP64 oracle on the host (plain numpy, one thread): the
+    first three updates of the workload (every row of X_1, the rows of X_2 that
+    sampled rows of X_3 need, three sampled rows of X_3), timed.  Its rate of
+    block products (each 2 b^3 flops, counting every product it forms) turns
+    the useful flops of one solve into an extrapolated solve time."""
+    from oracle import bsr_oracle as B
+    nb = sysm.H.nb
+    rows = sorted({0, nb // 2 + 7 if nb > 20 else nb // 2, nb - 1})
+    B.PRODUCTS[0] = 0
+    t0 = time.perf_counter()
+    B.leading_updates(sysm.H, sysm.H1, sysm.n_occ, sysm.eps, rows, 3)
+    dt = time.perf_counter() - t0
+    prods = B.PRODUCTS[0]
+    rate = prods * 2.0 * sysm.H.b ** 3 / dt
+    return {"value": round(rate / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "s_per_solve": round(useful_flops / rate, 1), "extrapolated": True,
+            "sample": f"block-list FP64 oracle (numpy, one thread), first 3 updates of {name} "
+                      f"(all rows of X1, {len(rows)} sampled rows of X3 and the rows of X2 they "
+                      f"need): {prods} block products in {dt:.1f} s; a solve of "
+                      f"{useful_flops / 1e12:.1f} useful TFLOP extrapolated at that rate"}
 
 
 def crossover(args) -> int:
@@ -304,15 +333,45 @@ def lowdin_pipeline(args) -> int:
     return 0
 
 
+def snapshot(solver, D: int, chunk: int = 1 << 20):
+    """Rows, columns and the X1_d values of the current iterate of a context,
+    exported to host memory in chunks (the reference side of the gate)."""
+    import numpy as np
+    n = solver.iterate_size()
+    b = solver.systems[0].H.b
+    rows = np.empty(n, dtype=np.int32)
+    cols = np.empty(n, dtype=np.int32)
+    vals = [np.empty((n, b, b)) for _ in range(D)]
+    for f in range(0, n, chunk):
+        c = min(chunk, n - f)
+        r, k, _ = solver.export_entries(1, f, c, values=False)
+        rows[f:f + c], cols[f:f + c] = r, k
+        for d in range(D):
+            vals[d][f:f + c] = solver.export_entries(1 + d, f, c)[2]
+    return rows, cols, vals
+
+
+def gate(solver, snap, res, ref_res, name: str) -> dict:
+    """max |dX1| over the union of the patterns (on the device) and relative
+    |d alpha| of the chosen variant's last solve against a reference."""
+    rows, cols, vals = snap
+    dx1 = max([solver.compare_entries(1 + d, rows, cols, v) for d, v in enumerate(vals)] + [0.0])
+    dal = max([abs(x - y) / abs(y) for g, f in zip(res, ref_res) for x, y in zip(g.alpha, f.alpha)]
+              + [0.0])
+    return {"max_abs_dX1": dx1, "rel_dalpha": dal, "pass": bool(dx1 < 1e-6 and dal < 1e-6),
+            "against": name}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cube10")
-    # default: the fastest variant that passes the gate on this workload (FP32
-    # block products summed in FP64 over the column blocks, 4 leading FP64
-    # updates, exact screen, closing FP64 pair, updates as captured graphs)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed steps: TC2 updates (single-system workloads) or solves (batches)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="cube30")
+    # default: the fastest variant that passes the gate (FP32 block products
+    # summed in FP64 over the column blocks, 4 leading FP64 updates, exact
+    # screen, closing FP64 pair, updates as captured graphs)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--kernel", default="tile", choices=["tile", "block"])
     ap.add_argument("--skip", default="bound", choices=["none", "bound", "mlp"],
@@ -323,7 +382,7 @@ def main() -> int:
     ap.add_argument("--wide", type=int, default=1, choices=[0, 1],
                     help="FP32 stages: FP64 sums of the per-block FP32 products")
     ap.add_argument("--tune", action="store_true",
-                    help="autotune the sub-tile shapes (timed in the warm-up solve)")
+                    help="autotune the sub-tile shapes (timed in the warm-up)")
     ap.add_argument("--tune-cache", default=None, help="tuned-shape cache file (read and appended)")
     ap.add_argument("--graph", type=int, default=1, choices=[0, 1],
                     help="run each update as one captured hipGraph with a persistent "
@@ -333,10 +392,11 @@ def main() -> int:
     ap.add_argument("--units", default=None,
                     help="batch workloads: comma-separated indices of the units to run "
                          "(default: all)")
+    ap.add_argument("--metrics-log", default=None,
+                    help="JSONL file of per-update scalars of the chosen variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=1)
     ap.add_argument("--no-reference", action="store_true",
-                    help="skip the plain FP64 runs and the gate (profiling the chosen variant alone)")
+                    help="skip the plain FP64 run and the gate (profiling the chosen variant alone)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--peak-probe", action="store_true",
@@ -385,7 +445,8 @@ def main() -> int:
     # workload -> units: lists of systems solved in one context (one merged
     # launch per update).  A batch is packed into units of at most
     # --group-atoms atoms so that each unit's iterates fit in HBM.
-    if args.workload.startswith("batch"):
+    batch = args.workload.startswith("batch")
+    if batch:
         n_sys = int(args.workload[5:] or 32)
         systems = W.batch_systems(n_sys=n_sys)
         units = W.pack_units(systems, args.group_atoms)
@@ -400,82 +461,24 @@ def main() -> int:
         systems = [W.config_system(args.workload)]
         units = [systems]
     sysm = systems[0]
+    D = len(sysm.H1)
     n_atoms = sum(sy.H.nb for sy in systems)
     log(f"workload {args.workload}: {len(systems)} system(s) in {len(units)} unit(s), atoms="
-        f"{n_atoms} b={sysm.H.b} N={sum(sy.H.n for sy in systems)} dirs={len(sysm.H1)} "
+        f"{n_atoms} b={sysm.H.b} N={sum(sy.H.n for sy in systems)} dirs={D} "
         f"eps={sysm.eps} tol={sysm.tol}")
-
-    def timed(kw):
-        """Seconds per solve of all units (each unit: warm-up, then timed solves)
-        and the results of the last timed solve of every system."""
-        total_ms, last, per = 0.0, [], []
-        for u in units:
-            solver = T.Solver(u, **kw)
-            for _ in range(args.warmup):
-                solver.run(stream=stream)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            res = [solver.run(stream=stream) for _ in range(args.steps)]
-            torch.cuda.synchronize()
-            total_ms += (time.perf_counter() - t0) / args.steps * 1e3
-            solver.close()
-            if len(units) > 1:
-                log(f"  unit of {len(u)} systems / {sum(x.H.nb for x in u)} atoms: "
-                    f"{(time.perf_counter() - t0) / args.steps:.2f} s/solve")
-            last += res[-1]
-            per.append(res)
-        return total_ms, last, per
-
-    def compare(kw_a, kw_b):
-        """max |dX1| and relative |d alpha| between two variants, unit by unit
-        (only one unit's exported matrices are held at a time)."""
-        dx1 = dal = 0.0
-        for u in units:
-            log(f"  exporting unit of {len(u)} system(s): first variant ...")
-            ga = T.solve(u, export=True, **kw_a)
-            log("  ... second variant ...")
-            gb = T.solve(u, export=True, **kw_b)
-            log("  ... comparing X1")
-            dx1 = max([dx1] + [bsr_maxdiff(a, b) for g, f in zip(ga, gb) for a, b in zip(g.X1, f.X1)])
-            dal = max([dal] + [abs(x - y) / abs(y) for g, f in zip(ga, gb)
-                               for x, y in zip(g.alpha, f.alpha)])
-            del ga, gb
-            log(f"  compared unit of {len(u)} system(s): max|dX1| {dx1:.3e} rel|dalpha| {dal:.3e}")
-        return dx1, dal
-
-    def bsr_maxdiff(a, b):
-        """max |A - B| over the union of two block patterns (no dense copy)."""
-        ra = np.repeat(np.arange(a.nb, dtype=np.int64), np.diff(a.row_ptr))
-        rb = np.repeat(np.arange(b.nb, dtype=np.int64), np.diff(b.row_ptr))
-        ka, kb = ra * a.nb + a.col, rb * b.nb + b.col
-        _, ia, ib = np.intersect1d(ka, kb, assume_unique=True, return_indices=True)
-        d = float(np.abs(a.val[ia] - b.val[ib]).max()) if len(ia) else 0.0
-        oa = np.setdiff1d(np.arange(len(ka)), ia, assume_unique=True)
-        ob = np.setdiff1d(np.arange(len(kb)), ib, assume_unique=True)
-        if len(oa):
-            d = max(d, float(np.abs(a.val[oa]).max()))
-        if len(ob):
-            d = max(d, float(np.abs(b.val[ob]).max()))
-        return d
 
     tile_kw = (dict(tune=args.tune, tune_cache=args.tune_cache, graph=bool(args.graph))
                if args.kernel == "tile" else {})
-    # plain FP64 path (every candidate block computed): reference for the gate
-    # and the speed-up, timed the same way as the chosen variant
-    ref_kw = dict(precision="fp64", kernel=args.kernel, **tile_kw)
-    ref_ms = None
-    if not args.no_reference:
-        ref_ms, ref_last, _ = timed(dict(export=False, **ref_kw))
-        ref_useful = sum(x.useful_flops for x in ref_last)
-        r0 = ref_last[0]
-        log(f"plain fp64: {r0.status_name} iters={r0.iters} {r0.branches} alpha={r0.alpha} "
-            f"kept={sum(x.kept_blocks for x in ref_last)} {ref_ms:.1f} ms/solve")
-
+    # plain FP64 path (every candidate block computed): the reference of the
+    # gate and of the speed-up.  Both sides run with profile = 1 (kernel
+    # timing by events), so that they are timed the same way.
+    ref_kw = dict(precision="fp64", kernel=args.kernel, profile=True, **tile_kw)
     chosen = args.precision
     closing = 0 if chosen == "fp64" else 2
+    theta = None
     if args.skip == "mlp":
         from paper_2009_03551_amd import skipnet
-        train_sys = [W.config_system("cube10", L=L, seed=500 + L, eps=sysm.eps, n_dir=len(sysm.H1))
+        train_sys = [W.config_system("cube10", L=L, seed=500 + L, eps=sysm.eps, n_dir=D)
                      for L in (5, 6, 7)]
         t0 = time.perf_counter()
         x, y = skipnet.collect(train_sys)
@@ -484,77 +487,157 @@ def main() -> int:
             f"{losses[0]:.4f} -> {losses[-1]:.4f}, {time.perf_counter() - t0:.1f} s")
     variant = dict(precision=chosen, closing_fp64=closing, kernel=args.kernel, skip=args.skip,
                    fp64_first=args.fp64_first if chosen != "fp64" else 0,
-                   wide=bool(args.wide and chosen != "fp64"))
+                   wide=bool(args.wide and chosen != "fp64"), profile=True, count_useful=True)
     if args.kernel == "tile":
         variant.update(tile_kw)
-    if args.skip == "mlp":
+    if theta is not None:
         variant.update(mlp_weights=theta, mlp_threshold=args.mlp_threshold)
-    ms_per_step, last, per = timed(dict(export=False, profile=True, **variant))
-    r = last[0]
-    useful = sum(x.useful_flops for x in last)
-    executed = sum(x.executed_flops for x in last)
-    value = useful / (ms_per_step * 1e-3) / 1e9
-    # numeric-kernel times per solve, summed over the units (the library
-    # times a context's launches once, on its first system's result)
-    ms_num = sum(sum(x[0].ms_numeric for x in res) / len(res) for res in per)
-    launches = sum(res[-1][0].numeric_launches for res in per)
-    # roofline of the dominant kernel: the numeric kernel kind (FP64, FP32,
-    # BF16 operands, FP32 with FP64 sums) that takes most of the numeric time
-    ms_kind = [sum(sum(x[0].ms_numeric_kind[k] for x in res) / len(res) for res in per)
-               for k in range(4)]
-    dom = max(range(4), key=lambda k: ms_kind[k])
-    dom_launches = sum(res[-1][0].numeric_launches_kind[dom] for res in per)
-    dom_flops = sum(x.useful_flops_kind[dom] for x in last)
-    achieved = dom_flops / (ms_kind[dom] * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[("fp64", "fp32", "bf16", "fp32")[dom]]
-    # attainable peak of the same dtype from the committed GEMM probe (bf16
-    # was not probed)
-    pm = measured_peaks() or {}
-    pk_meas = pm.get({0: "gemm_fp64_tflops", 1: "gemm_fp32_tflops", 3: "gemm_fp32_tflops"}.get(dom, ""))
-    kname = kernel_name(args.kernel, dom, len(sysm.H1), r.tile_shape[dom], sysm.H.b)
-    log(f"{chosen}: {ms_per_step:.1f} ms/solve, numeric {ms_num:.1f} ms in {launches} launches, "
-        f"useful {useful / 1e12:.3f} TF, executed {executed / 1e12:.3f} TF")
-
-    # gate of the chosen variant against the plain FP64 path
-    gate = None
-    if ref_ms is not None:
-        log("gate: chosen variant against the plain FP64 path")
-        dx1, dal = compare(variant, ref_kw)
-        gate = {"max_abs_dX1": dx1, "rel_dalpha": dal, "pass": bool(dx1 < 1e-6 and dal < 1e-6),
-                "against": "plain FP64 GPU path"}
-    # the learned screen against the exact one on the same variant: what it
-    # saves and the error it introduces (measured against the exact-screen run)
-    mlp_vs_bound = None
+    # references solved once per unit, their X1 kept on the host for the gate
+    refs = []
+    if not args.no_reference:
+        refs.append(("plain FP64 GPU path", ref_kw))
     if args.skip == "mlp":
-        bkw = dict(variant, skip="bound")
+        bkw = dict(variant, skip="bound", count_useful=False)
         bkw.pop("mlp_weights")
         bkw.pop("mlp_threshold")
-        b_ms, b_last, _ = timed(dict(export=False, profile=True, **bkw))
-        b_exec = sum(x.executed_flops for x in b_last)
-        log(f"exact screen alone: {b_ms:.1f} ms/solve, executed {b_exec / 1e12:.3f} TF")
-        mdx1, mdal = compare(variant, bkw)
-        mlp_vs_bound = {
-            "s_per_solve_bound": round(b_ms * 1e-3, 4),
-            "speedup_over_bound": round(b_ms / ms_per_step, 3),
-            "executed_tflop_bound": round(b_exec / 1e12, 4),
-            "executed_saved_frac": round(1.0 - executed / b_exec, 4),
-            "max_abs_dX1": mdx1, "rel_dalpha": mdal}
-        log(f"mlp vs bound: {mlp_vs_bound}")
+        refs.append(("exact norm-bound screen, same precision variant", bkw))
+
+    def solve_refs(u):
+        """Each reference on unit u: one timed solve, then its X1 on the host."""
+        out = []
+        for name, kw in refs:
+            sv = T.Solver(u, export=False, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = sv.run(stream=stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            snap = snapshot(sv, D)
+            log(f"  {name}: {res[0].status_name} iters={res[0].iters} {res[0].branches} "
+                f"{wall:.2f} s/solve (device {res[0].seconds:.2f} s); X1 snapshot of "
+                f"{len(snap[0])} entries in {time.perf_counter() - t0:.1f} s")
+            sv.close()
+            out.append((name, res, snap, wall))
+        return out
+
+    gates, ref_s, ref_useful = {}, {}, {}
+    def add_gate(name, g):
+        if name not in gates:
+            gates[name] = dict(g)
+        else:
+            cur = gates[name]
+            cur["max_abs_dX1"] = max(cur["max_abs_dX1"], g["max_abs_dX1"])
+            cur["rel_dalpha"] = max(cur["rel_dalpha"], g["rel_dalpha"])
+            cur["pass"] = cur["pass"] and g["pass"]
+
+    results, per_unit = [], []
+    if not batch:
+        # ---- one system: steps are updates of the solve sequence
+        u = units[0]
+        for name, res, snap, wall in solve_refs(u):
+            ref_s[name] = res[0].seconds
+            refs_done = (name, res, snap)
+            per_unit.append(refs_done)
+        sv = T.Solver(u, export=False, metrics_log=args.metrics_log, **variant)
+        done = []
+        p, r = sv.advance(args.warmup, stream=stream)
+        if r:
+            done.append(r)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p, r = sv.advance(args.steps, stream=stream)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        if r:
+            done.append(r)
+        timed_useful = p["useful_flops"]
+        timed_exec = p["executed_flops"]
+        assert p["updates"] == args.steps
+        # finish the solve in progress (untimed): its iterate is the one gated
+        while p["solve_open"] or not done:
+            p, r = sv.advance(1, stream=stream)
+            if r:
+                done.append(r)
+        results = done[-1]
+        for name, res, snap in per_unit:
+            add_gate(name, gate(sv, snap, results, res, name))
+        sv.close()
+        ms_per_step = elapsed / args.steps * 1e3
+        value = timed_useful / elapsed / 1e9
+        s_solve = sum(x.seconds for x in results[:1])
+        log(f"{chosen}: {args.steps} updates in {elapsed:.3f} s ({ms_per_step:.1f} ms/update), "
+            f"useful {timed_useful / 1e12:.3f} TF -> {value:.1f} GFLOP/s; solve "
+            f"{results[0].iters} updates {results[0].branches} in {s_solve:.2f} s")
+        per = [[results]]
+    else:
+        # ---- batches: steps are solves of every unit, one unit at a time
+        total_s, per = 0.0, []
+        timed_useful = timed_exec = 0.0
+        for u in units:
+            rdone = solve_refs(u)
+            for name, res, snap, wall in rdone:
+                ref_s[name] = ref_s.get(name, 0.0) + res[0].seconds
+            sv = T.Solver(u, export=False, **variant)
+            for _ in range(args.warmup):
+                sv.run(stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = [sv.run(stream=stream) for _ in range(args.steps)]
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            total_s += dt
+            timed_useful += sum(x.useful_flops for x in res[-1])
+            timed_exec += sum(x.executed_flops for x in res[-1])
+            for name, rres, snap, wall in rdone:
+                add_gate(name, gate(sv, snap, res[-1], rres, name))
+            sv.close()
+            log(f"  unit of {len(u)} systems / {sum(x.H.nb for x in u)} atoms: {dt:.2f} s/solve; "
+                f"gate so far {gates}")
+            results += res[-1]
+            per.append(res)
+        elapsed = total_s * args.steps
+        ms_per_step = total_s * 1e3
+        s_solve = total_s
+        value = timed_useful / total_s / 1e9
+        timed_exec = timed_exec
+
+    r = results[0]
+    useful = sum(x.useful_flops for x in results)
+    executed = sum(x.executed_flops for x in results)
+    # roofline of the dominant kernel: the numeric kernel kind (FP64, FP32,
+    # BF16 operands, FP32 with FP64 sums) with the most numeric time, over the
+    # last complete solve of every unit (the library times a context's launches
+    # once, on its first system's result)
+    ms_kind = [sum(res[-1][0].ms_numeric_kind[k] for res in per) for k in range(4)]
+    dom = max(range(4), key=lambda k: ms_kind[k])
+    dom_launches = sum(res[-1][0].numeric_launches_kind[dom] for res in per)
+    dom_flops = sum(x.useful_flops_kind[dom] for res in per for x in res[-1])
+    achieved = dom_flops / (ms_kind[dom] * 1e-3) / 1e12 if ms_kind[dom] > 0 else 0.0
+    peak = PEAK_TFLOPS[("fp64", "fp32", "bf16", "fp32")[dom]]
+    pm = measured_peaks() or {}
+    pk_meas = pm.get({0: "gemm_fp64_tflops", 1: "gemm_fp32_tflops", 3: "gemm_fp32_tflops"}.get(dom, ""))
+    kname = kernel_name(args.kernel, dom, D, r.tile_shape[dom], sysm.H.b)
     traffic = measured_traffic(kname.split("<")[0], args.workload,
                                ("fp64", "fp32", "bf16", "fp32w")[dom])
-    config = {"workload": args.workload, "systems": len(systems), "units": len(units),
+    plain = refs[0][0] if refs and refs[0][0] == "plain FP64 GPU path" else None
+    config = {"workload": args.workload,
+              "step": "one solve of every unit" if batch else "one TC2/TC2-CPSCF update",
+              "systems": len(systems), "units": len(units),
               "atoms": n_atoms, "b": sysm.H.b, "N": sum(sy.H.n for sy in systems),
-              "directions": len(sysm.H1), "eps": sysm.eps, "tol": sysm.tol, "precision": chosen,
-              "closing_fp64": closing, "iters": r.iters, "status": r.status_name,
+              "directions": D, "eps": sysm.eps, "tol": sysm.tol, "precision": chosen,
+              "closing_fp64": closing, "iters": r.iters, "branches": r.branches,
+              "status": r.status_name,
               "kernel": args.kernel, "skip": args.skip, "fp64_first": variant["fp64_first"],
               "wide_accumulate": variant["wide"], "tuned": bool(args.tune),
               "tile_shape": r.tile_shape, "graph_updates": r.graph_updates,
+              "graph_captures": r.graph_captures,
               "screened_blocks": sum(res[-1][0].screened_blocks for res in per),
               "mlp_skipped_blocks": sum(res[-1][0].mlp_skipped_blocks for res in per)}
     if args.units:
         config["unit_indices"] = [int(x) for x in args.units.split(",")]
     if len(systems) > 1:
-        config["iters_range"] = [min(x.iters for x in last), max(x.iters for x in last)]
+        config["iters_range"] = [min(x.iters for x in results), max(x.iters for x in results)]
     out = {
         "metric": "TC2+response s/solve & useful GFLOP/s, chosen vs plain FP64 at max|dX1|<1e-6",
         "value": round(value, 3),
@@ -563,21 +646,23 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3),
-        "s_per_solve": round(ms_per_step * 1e-3, 4),
+        "s_per_solve": round(s_solve, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[chosen],
         "data": "synthetic",
         "config": config,
-        "plain_fp64": None if ref_ms is None else {
-            "s_per_solve": round(ref_ms * 1e-3, 4),
-            "useful_gflops": round(ref_useful / (ref_ms * 1e-3) / 1e9, 3)},
-        "speedup_vs_plain_fp64": None if ref_ms is None else round(ref_ms / ms_per_step, 3),
-        "gate": gate,
-        "mlp_vs_bound": mlp_vs_bound,
+        "plain_fp64": None if plain is None else {
+            "s_per_solve": round(ref_s[plain], 4)},
+        "speedup_vs_plain_fp64": None if plain is None else round(ref_s[plain] / s_solve, 3),
+        "gate": gates.get(plain),
+        "mlp_vs_bound": gates.get("exact norm-bound screen, same precision variant"),
+        "timed_useful_tflop": round(timed_useful / 1e12, 4),
+        "timed_executed_tflop": round(timed_exec / 1e12, 4),
         "useful_tflop_per_solve": round(useful / 1e12, 4),
-        "nominal_tflop_per_solve": round(sum(x.nominal_flops for x in last) / 1e12, 4),
+        "union_tflop_per_solve": round(sum(x.union_flops for x in results) / 1e12, 4),
+        "nominal_tflop_per_solve": round(sum(x.nominal_flops for x in results) / 1e12, 4),
         "executed_tflop_per_solve": round(executed / 1e12, 4),
         "roofline": {"bound": "mfma",
                      "kernel": kname, "achieved": round(achieved, 3),
@@ -588,15 +673,17 @@ def main() -> int:
                      "launches_per_solve": dom_launches,
                      "avg_launch_ms": round(ms_kind[dom] / max(dom_launches, 1), 4),
                      "useful_tflop_per_solve": round(dom_flops / 1e12, 4),
-                     "all_numeric": {"ms_per_solve": round(ms_num, 3), "launches": launches,
-                                     "ms_per_kind": [round(x, 3) for x in ms_kind]}},
+                     "all_numeric_ms_per_kind": [round(x, 3) for x in ms_kind]},
     }
     if not args.no_cpu_baseline:
         if len(systems) == 1 and sysm.H.n <= 20000:
-            log("cpu baseline (oracle) ...")
-            out["cpu_baseline"] = cpu_baseline(sysm, r.iters, useful, args.cpu_sample_iters)
+            log("cpu baseline (dense oracle) ...")
+            out["cpu_baseline"] = cpu_baseline_dense(sysm, r.iters, useful)
+        elif len(systems) == 1:
+            log("cpu baseline (block-list oracle) ...")
+            out["cpu_baseline"] = cpu_baseline_bsr(args.workload, sysm, useful)
         else:
-            log("cpu baseline skipped: the dense oracle does not fit this workload")
+            log("cpu baseline skipped: batch workload")
     print(json.dumps(out), flush=True)
     return 0
 

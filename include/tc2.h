@@ -129,6 +129,26 @@ typedef struct {
                               an update that is being tuned, or the closing
                               FP64 pair (those updates run without a graph);
                               results are identical                            */
+  const char *metrics_log; /* NULL, or a file: after every update one JSON line
+                              per system that took part is appended: solve,
+                              system, update, branch, kernel kind, phase (1 =
+                              closing pair), tr_x0, e0, e1[], alpha[], tr_x1[],
+                              iota = Tr X0 - ||X0||_F^2, dmax (largest change of
+                              the band energies and traces), nnzb (stored
+                              blocks), active (still iterating), status      */
+  int32_t count_useful;    /* 0 or 1: count the useful block products of every
+                              update exactly (an integer pass over the old and
+                              new patterns after each update; see
+                              tc2_result.useful_flops).  0: useful_flops = 0 */
+  float mlp_bound_cap;     /* skip = 2: the network may skip only a candidate whose
+                              exact norm bound is below mlp_bound_cap * eps for
+                              X0 and every X1_d (and, on the DOUBLE branch, never
+                              a stored block whose 2 ||X_IJ|| alone reaches
+                              eps); 0 means 4                                   */
+  double mlp_budget;       /* skip = 2: once, for some problem, the bounds of the
+                              candidates the network skipped in a solve add up
+                              to more than this, the rest of the solve runs with
+                              the exact screen alone (skip = 1); 0: no limit   */
 } tc2_options;
 
 typedef struct {
@@ -142,12 +162,21 @@ typedef struct {
   double e1[3];            /* Tr(X1_d H)                                         */
   double emin, emax;       /* Gershgorin bounds                                  */
   double seconds;          /* device time of the solve                           */
-  double useful_flops;     /* 2 b^3 per block triple landing on a kept block     */
+  double useful_flops;     /* count_useful = 1: 2 b^3 per useful block product:
+                              X0_IK X0_KJ with both blocks nonzero in X0, on an
+                              output (I <= J) that X0 keeps; X0_IK X1_KJ and
+                              X1_IK X0_KJ with both operand blocks nonzero, on an
+                              output that X1_d keeps; summed over the updates */
+  double union_flops;      /* 2 b^3 (1 + 2D) per block triple with a block of
+                              any matrix on both sides, on an output any matrix
+                              keeps (the union pattern): an upper bound of the
+                              useful flops, counted in every run               */
   double executed_flops;   /* MFMA flops issued, padding included                */
   int64_t kept_blocks;     /* stored blocks of the final X pattern (both halves) */
   int64_t screened_blocks; /* output blocks skipped by the exact screen, all
                               updates (batch total, on the first problem)     */
   int64_t mlp_skipped_blocks; /* output blocks skipped by the skip network    */
+  int32_t mlp_updates;     /* updates run with the skip network (skip = 2)      */
   /* phase times in ms, summed over the updates (profile = 1 only) */
   double ms_symbolic, ms_numeric, ms_compact;
   int32_t numeric_launches;
@@ -161,6 +190,7 @@ typedef struct {
   double ms_numeric_kind[4];
   int32_t numeric_launches_kind[4];
   int32_t graph_updates;   /* updates run as a captured graph                   */
+  int32_t graph_captures;  /* update graphs captured (the others were replays)  */
   double nominal_flops;    /* 2 b^3 (1 + 2D) per block triple of the full products
                               on each update's input pattern (sum over rows K of
                               m_K^2): the work of full sparse products, as the
@@ -188,13 +218,78 @@ TC2_API tc2_status tc2_setup(const tc2_problem *problems, int32_t n_problems,
  * before warnings).  May be called again; each call restarts from H. */
 TC2_API tc2_status tc2_run(tc2_ctx *ctx, void *hip_stream, tc2_result *res);
 
+/* Progress of tc2_advance. */
+typedef struct {
+  int32_t updates;         /* updates run by this call                          */
+  int32_t solves_completed;/* solves that finished within this call            */
+  int32_t solve_open;      /* 1: a solve is still in progress after this call   */
+  double useful_flops;     /* count_useful = 1: useful flops of this call's
+                              updates (as tc2_result.useful_flops)              */
+  double executed_flops;   /* MFMA flops issued by this call's updates          */
+} tc2_progress;
+
+/* Run at most max_updates TC2 / TC2-CPSCF updates of the context's solve, on
+ * hip_stream (NULL: the library's stream), and return.  A solve that is not in
+ * progress begins first (Gershgorin bounds and the initial matrices, as
+ * tc2_run).  When a solve finishes within the call (every system stopped and
+ * no stage switch pending), its results are written to res (n_problems
+ * entries, as tc2_run) and, if updates remain, the next solve begins from H.
+ * The updates and results are those of tc2_run: a solve advanced in pieces
+ * gives the same iterates.  tc2_run abandons a solve in progress.
+ * Returns the worst status of the solves finished in this call (TC2_OK if
+ * none finished), or an error; prog is filled in either case.
+ * Errors: TC2_EINVAL (NULL ctx, prog or res; max_updates < 0), and those of
+ * tc2_run. */
+TC2_API tc2_status tc2_advance(tc2_ctx *ctx, void *hip_stream, int32_t max_updates,
+                               tc2_progress *prog, tc2_result *res);
+
+/* ---------------------------------------------------------------------------
+ * Access to the current iterate of a context (after tc2_run, or between two
+ * tc2_advance calls): for checks of sampled rows of systems too large to
+ * export whole, and for comparing two solves of the same problems on the
+ * device.  Matrix index m: 0 = X0, 1 + d = X1_d.
+ * ------------------------------------------------------------------------- */
+
+/* Complete block rows `rows` (n_rows indices into the block rows of problem
+ * `system`, in any order) of X0 and of every X1_d (x1 holds n_dir matrices),
+ * as library-allocated host BSR matrices of the problem's size whose other
+ * rows are empty; columns are the problem's own.  Each output is freed with
+ * tc2_bsr_release.  Errors: TC2_EINVAL (no iterate yet, ranges, NULL),
+ * TC2_ENOMEM, TC2_EDEVICE. */
+TC2_API tc2_status tc2_export_rows(tc2_ctx *ctx, int32_t system, const int32_t *rows,
+                                   int32_t n_rows, tc2_bsr *x0, tc2_bsr *x1);
+
+/* Stored entries (blocks) of the current iterate of all problems of the
+ * context, merged into one block-diagonal matrix in problem order. */
+TC2_API tc2_status tc2_iterate_size(tc2_ctx *ctx, int64_t *nnz);
+
+/* Entries [first, first + count) of that merged pattern, in row-major order:
+ * block row and column (merged indices) and the b x b values of matrix m,
+ * row-major.  Any of rows, cols, vals may be NULL (not written); the caller
+ * owns them (count, count and count*b*b elements).
+ * Errors: TC2_EINVAL (ranges, no iterate), TC2_ENOMEM, TC2_EDEVICE. */
+TC2_API tc2_status tc2_export_entries(tc2_ctx *ctx, int32_t matrix, int64_t first, int64_t count,
+                                      int32_t *rows, int32_t *cols, double *vals);
+
+/* Largest |A - B| over the union of two block patterns: A is given by the
+ * caller as n entries (merged block row and column, strictly increasing in
+ * row-major order, with b x b row-major values), B is matrix m of the current
+ * iterate; a block missing on one side counts as zero.  The caller's values
+ * are uploaded in chunks, so A may be larger than the free device memory
+ * (its rows and columns are uploaded whole).
+ * Errors: TC2_EINVAL (ranges, order, NULL), TC2_ENOMEM, TC2_EDEVICE. */
+TC2_API tc2_status tc2_compare_entries(tc2_ctx *ctx, int32_t matrix, int64_t n, const int32_t *rows,
+                                       const int32_t *cols, const double *vals, double *max_abs);
+
 /* Copy the samples logged by the last tc2_run (log_capacity > 0): features
  * (n x TC2_MLP_IN floats: scaled log10 of the norm bounds of X0 and X1 relative
  * to eps, of the largest single product, of the number of common columns,
  * distance / 10, scaled log10 of the previous block norm or -3, update / 20,
- * branch) and labels (1 = the block was dropped).  Returns the number of
+ * branch), labels (1 = the block was dropped, 0 = kept, -1 = skipped by the
+ * network, outcome unknown) and, if z is not NULL, the logit the in-kernel
+ * network gave the sample (skip = 2; 0 otherwise).  Returns the number of
  * samples copied (at most cap), or a negative tc2_status. */
-TC2_API int64_t tc2_log_copy(tc2_ctx *ctx, float *x, float *y, int64_t cap);
+TC2_API int64_t tc2_log_copy(tc2_ctx *ctx, float *x, float *y, float *z, int64_t cap);
 
 /* Release the context and everything it owns.  NULL-safe. */
 TC2_API void tc2_free(tc2_ctx *ctx);

@@ -112,6 +112,34 @@ def band_energies(X0, X1s, H, H1s):
     return E0, E1, al
 
 
+def block_nonzero(X: np.ndarray, b: int) -> np.ndarray:
+    """(nb x nb) flags: block (I, J) of X has a nonzero element."""
+    nb = X.shape[0] // b
+    return np.any(X.reshape(nb, b, nb, b) != 0.0, axis=(1, 3))
+
+
+def useful_products(prev: Sequence[np.ndarray], new: Sequence[np.ndarray], b: int) -> int:
+    """Useful block products of one update, from the iterate before it (prev =
+    [X0, X1_1, ..]) and after it (new, filtered).  The work of an update of
+    Eq. TC2 / TC2-CPSCF counted on stored blocks only, over the upper
+    triangle of the output (the lower half is its mirror):
+
+    * X0 X0: triples (I, K, J), I <= J, with X0_IK and X0_KJ nonzero and the
+      new X0_IJ nonzero (kept by the filter);
+    * X0 X1_d + X1_d X0: triples with X0_IK and X1_d,KJ nonzero, plus triples
+      with X1_d,IK and X0_KJ nonzero, on outputs where the new X1_d,IJ is
+      nonzero.
+
+    Each product is 2 b^3 flops."""
+    M = [block_nonzero(X, b).astype(np.int64) for X in prev]
+    N = [block_nonzero(X, b) for X in new]
+    up = np.triu(np.ones(N[0].shape, dtype=bool))
+    total = int(((M[0] @ M[0]) * (N[0] & up)).sum())
+    for d in range(1, len(prev)):
+        total += int(((M[0] @ M[d] + M[d] @ M[0]) * (N[d] & up)).sum())
+    return total
+
+
 def stopping_rule(k: int, prev, cur, iotas: Sequence[float], tol: float,
                   stall_guard: bool = True) -> Optional[int]:
     """Stopping decision after update k (k = 1, 2, ...), from the scalars of

@@ -156,11 +156,14 @@ struct TileArgs {
   unsigned long long* screened;  // outputs skipped by the exact screen
   const float* mlp;       // skip network parameters (MLP_NP), skip == 2
   float mlp_z;            // skip when the logit exceeds this (logit of the threshold)
+  float mlp_cap;          // the network may skip only outputs whose bound is < mlp_cap * eps
   unsigned long long* mlp_skipped;
+  double* mlp_bsum;       // per system: sum of the bounds of the outputs the network skipped
   const double* xyz;      // merged atom positions or nullptr
   int iter;               // update index (feature)
   float* log_x;           // logged features (log_cap x MLP_NF)
-  float* log_y;           // logged labels (1 = dropped)
+  float* log_y;           // logged labels (1 = dropped, 0 = kept, -1 = skipped by the network)
+  float* log_z;           // logged logits of the in-kernel network (skip == 2), or nullptr
   unsigned long long* log_count;
   long long log_cap;      // 0: no logging
   int kl_chunk;           // 0: default panel pass length

@@ -6,6 +6,7 @@
 // one merged kernel sequence per update, and applies the stopping rule of
 // Sec. 2.3 (band-energy change below the tolerance) per system.
 #include "tc2_internal.h"
+#include "tc2_context.h"
 #include "tc2_host.h"
 #include "../../include/tc2.h"
 
@@ -20,84 +21,6 @@
 using namespace tc2;
 
 namespace {
-
-// ------------------------------------------------------------------ device buffers
-struct DBuf {
-  void* p = nullptr;
-  size_t cap = 0;
-  ~DBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    cap = 0;
-  }
-  // grow to at least n bytes (contents are not preserved)
-  hipError_t reserve(size_t n) {
-    if (n <= cap && p) return hipSuccess;
-    release();
-    size_t want = std::max<size_t>(n, 256);
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) {
-      p = nullptr;
-      return e;
-    }
-    cap = want;
-    return hipSuccess;
-  }
-  template <typename T> T* as() const { return (T*)p; }
-};
-
-// Page-locked host memory for the small per-update transfers: copies to and
-// from it are plain DMAs, where pageable memory goes through staging copies.
-struct HostPin {
-  void* p = nullptr;
-  size_t cap = 0;
-  ~HostPin() {
-    if (p) (void)hipHostFree(p);
-  }
-  hipError_t reserve(size_t n) {
-    if (n <= cap && p) return hipSuccess;
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-    cap = 0;
-    hipError_t e = hipHostMalloc(&p, n, hipHostMallocDefault);
-    if (e != hipSuccess) {
-      p = nullptr;
-      return e;
-    }
-    cap = n;
-    return hipSuccess;
-  }
-};
-
-struct HostBsr {
-  std::vector<int64_t> row_ptr;
-  std::vector<int32_t> col;
-  std::vector<double> val;
-};
-
-struct SysInfo {
-  int row0 = 0, nb = 0;
-  int64_t n_occ = 0;
-  double eps = 0, tol = 0;
-  int max_iter = 0;
-  std::string replay;
-  int mode = 0;  // 0 iterate, 1 trivial zero (Nocc = 0), 2 trivial identity (Nocc = N)
-};
-
-struct SysState {
-  bool active = false;
-  int k = 0;
-  double prev[1 + 2 * MAXD] = {0};
-  std::vector<double> iota;
-  std::string branches;
-  int closing_left = 0;
-  int closing_first = 1;
-  tc2_status status = TC2_OK;
-  double trip = 0;
-  double trip_kind[4] = {0, 0, 0, 0};  // the same, per kernel kind
-  double nominal = 0;                  // full-product block triples (sum of m_K^2)
-};
 
 // Block triples (I, K, J) of the full product X X on the current pattern, per
 // active system: the sum over rows K of m_K^2, m_K the stored blocks of row K
@@ -116,88 +39,6 @@ __global__ void k_nominal(int nb, const int* rp, const int* sys_of, const int* a
 
 }  // namespace
 
-struct tc2_ctx {
-  int device = 0;
-  hipStream_t own = nullptr;
-  int nsys = 0, D = 0, b = 0, nb = 0, prec = P_FP64, closing = 0, verbose = 0, export_m = 0;
-  int profile = 0;
-  hipEvent_t pev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  double ms_sym = 0, ms_num = 0, ms_cmp = 0;
-  double ms_num_kind[4] = {0, 0, 0, 0};
-  int launches_kind[4] = {0, 0, 0, 0};
-  int last_kind = 0;                // kernel kind of the last update
-  int num_launches = 0;
-  int max_sys_atoms = 0;
-  std::vector<SysInfo> sys;
-  // host copies kept for export
-  std::vector<int> h_sys_of;
-  // device: systems
-  DBuf sys_of, sys_start, sys_end, active, branch, mode, eps, emin, emax, bad;
-  // device: H and H1
-  DBuf h_rp, h_ci, h_v;
-  DBuf h1_rp[MAXD], h1_ci[MAXD], h1_v[MAXD];
-  // initial pattern (union of H and H1 patterns) and its sources
-  int nnz0 = 0;
-  DBuf x0_rp, x0_ci, x0_row, src_h, src_h1[MAXD];
-  // iterate (double buffered)
-  DBuf rp[2], ci[2], xv[2];
-  int nnz[2] = {0, 0};
-  int cur = 0;
-  int cur_prec = P_FP64;
-  // work buffers
-  DBuf cand_cnt, cand_rp, cand_ci, item_cnt, item_rp, item_row, item_c0, partial;
-  DBuf stage, kept_ij, counters, exec_pairs, rowcnt, cursor, tmp_ci, tmp_src, new_src;
-  HostPin pin_graph;              // per-update readback of the graph path
-  HostPin pin_loop;               // active / branch flags in, bad / nominal out
-  DBuf sys_lo, sys_hi, scal, rowlo, rowhi, xfer;
-  long long stage_cap = 0;
-  int kernel = 0;                 // 0 tiled, 1 one wave per block
-  int fp64_first = 0;             // leading FP64 updates of a reduced-precision solve
-  int op_bf16 = 0;                // current stage rounds MFMA operands to bfloat16
-  int wide = 0;                   // FP32 stages: FP64 sums over the column blocks
-  int shape[4] = {0, 0, 0, 0};    // sub-tile shape per kernel kind
-  bool tuned[4] = {false, false, false, false};
-  int tune = 0;                   // 1: measure the shapes once per kind
-  std::string tune_cache;         // file of tuned shapes ("" = none)
-  std::string arch;               // device architecture name (cache key)
-  long long prev_out_bound = -1;  // candidate outputs of the previous update
-  double ms_tune = 0.0;
-  bool kind_used[4] = {false, false, false, false};
-  int skip = 0;                   // 1: exact norm-bound screen, 2: + skip network
-  DBuf bn, screened;              // block norms, skip counters [exact, network]
-  DBuf nominal;                   // per system: sum over rows K of m_K^2, this update
-  unsigned long long screened_total = 0, mlp_total = 0;
-  DBuf mlp;                       // skip network parameters
-  float mlp_z = 0.f;              // logit of the skip threshold
-  DBuf xyz;                       // merged positions (all problems gave them)
-  bool have_xyz = false;
-  long long log_cap = 0, log_n = 0;
-  DBuf log_x, log_y, log_count;
-  int update_index = 0;
-  // test knobs (environment, read at setup): shorter panel passes in the
-  // tiled kernel, and a tiny stage that overflows every update
-  int test_kl_chunk = 0;
-  long long test_stage_cap = 0;
-  std::vector<int> h_active;      // host copy of the active flags
-  // clusters
-  int nc = 0, max_sys_clusters = 0;
-  long long tile_bound = 0;       // most tiles an update can have (P <= Q per system)
-  DBuf clus_atom, clus_sys, atom_clus, csys_start, csys_end;
-  // graph-captured updates (tiled kernel): one executable graph per iterate
-  // buffer, valid while the key (buffers, sizes, kind, shape) is unchanged
-  int graph = 0;                  // option: capture updates in hipGraphs
-  bool graph_ok = true;           // false after a capture the runtime refused
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  hipGraphExec_t gexec_post[2] = {nullptr, nullptr};  // profiling: the part after the products
-  std::vector<unsigned long long> gkey[2];
-  long long kept_prev = 0, kept_prev2 = 0;  // kept upper blocks of the last updates
-  int graph_updates = 0, graph_captures = 0;
-  DBuf panel_cnt, panel_rp, panel_k, panel_e, tile_cnt, tile_rp, tile_pairs, tile_p, tile_q;
-  DBuf tile_bits;                 // cluster bitmaps kept between the two tile passes
-  // results
-  std::vector<HostBsr> out_x0;
-  std::vector<HostBsr> out_x1[MAXD];
-};
 
 namespace {
 
@@ -211,7 +52,6 @@ namespace {
     }                                                                    \
   } while (0)
 
-size_t prec_bytes(int prec) { return prec == P_FP64 ? 8 : 4; }
 
 // padded, column-major device image of a batch of BSR matrices (FP64)
 void pack_blocks(const tc2_bsr& m, int b, std::vector<double>& out) {
@@ -327,6 +167,8 @@ void tc2_free(tc2_ctx* ctx) {
     if (g) (void)hipGraphExecDestroy(g);
   for (hipGraphExec_t& g : ctx->gexec_post)
     if (g) (void)hipGraphExecDestroy(g);
+  if (ctx->run.ev0) (void)hipEventDestroy(ctx->run.ev0);
+  if (ctx->run.ev1) (void)hipEventDestroy(ctx->run.ev1);
   delete ctx;
 }
 
@@ -400,6 +242,8 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   if ((o->skip != 0 || o->log_capacity > 0) && o->numeric_kernel != 0) return TC2_EINVAL;
   if (o->skip == 2) {
     if (!o->mlp_weights || !(o->mlp_threshold > 0.f && o->mlp_threshold < 1.f)) return TC2_EINVAL;
+    if (!(o->mlp_bound_cap >= 0.f) || !(o->mlp_budget >= 0.0) || !std::isfinite(o->mlp_budget))
+      return TC2_EINVAL;
     for (int p = 0; p < MLP_NP; ++p)
       if (!std::isfinite(o->mlp_weights[p])) return TC2_ENAN;
   }
@@ -411,6 +255,7 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   if (o->numeric_kernel < 0 || o->numeric_kernel > 1) return TC2_EINVAL;
   if (o->precision == P_BF16 && o->numeric_kernel != 0) return TC2_EINVAL;
   if (o->fp64_first < 0 || o->fp64_first > TC2_MAX_ITER) return TC2_EINVAL;
+  if (o->count_useful < 0 || o->count_useful > 1) return TC2_EINVAL;
   const int b = probs[0].H.b, D = probs[0].n_dir;
   if (b < 1 || b > BP || D < 0 || D > MAXD) return TC2_EINVAL;
   int64_t nb_tot = 0;
@@ -460,11 +305,18 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   ctx->kernel = o->numeric_kernel;
   ctx->fp64_first = o->fp64_first;
   ctx->skip = o->skip;
+  ctx->skip_now = o->skip;
+  if (o->skip == 2) {
+    ctx->mlp_cap = o->mlp_bound_cap > 0.f ? o->mlp_bound_cap : 4.f;
+    ctx->mlp_budget = o->mlp_budget;
+  }
   ctx->log_cap = o->log_capacity;
   ctx->wide = o->wide_accumulate;
   ctx->tune = o->tune;
   if (o->tune_cache) ctx->tune_cache = o->tune_cache;
   ctx->graph = o->graph;
+  ctx->count_useful = o->count_useful;
+  if (o->metrics_log) ctx->metrics_log = o->metrics_log;
   ctx->arch = arch;
   for (int k = 0; k < 4; ++k) ctx->shape[k] = tile_shape_default(k, D);
   if (ctx->tune) tune_load(ctx);
@@ -643,13 +495,15 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
       ctx->have_xyz = true;
     }
     if (o->skip == 2) {
+      if (ctx->mlp_bsum.reserve((size_t)np * 8) != hipSuccess) return fail(TC2_ENOMEM);
       std::vector<float> th(o->mlp_weights, o->mlp_weights + MLP_NP);
       if ((st = upload(ctx, ctx->mlp, th)) != TC2_OK) return fail(st);
       ctx->mlp_z = std::log(o->mlp_threshold / (1.f - o->mlp_threshold));
     }
     if (ctx->log_cap > 0) {
       if (ctx->log_x.reserve((size_t)ctx->log_cap * MLP_NF * 4) ||
-          ctx->log_y.reserve((size_t)ctx->log_cap * 4) || ctx->log_count.reserve(8))
+          ctx->log_y.reserve((size_t)ctx->log_cap * 4) ||
+          ctx->log_z.reserve((size_t)ctx->log_cap * 4) || ctx->log_count.reserve(8))
         return fail(TC2_ENOMEM);
     }
   }
@@ -876,7 +730,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     ctx->ms_sym += ms;
   }
   HIPCHK(ctx->exec_pairs.reserve(8));
-  const bool screen = tiled && (ctx->skip != 0 || ctx->log_cap > 0);
+  const bool screen = tiled && (ctx->skip_now != 0 || ctx->log_cap > 0);
   if (screen) {
     HIPCHK(ctx->bn.reserve((size_t)std::max(ctx->nnz[c], 1) * (1 + D) * 4));
     HIPCHK(ctx->screened.reserve(16));
@@ -925,17 +779,20 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     ta.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
     ta.bf16 = (ctx->op_bf16 && ctx->cur_prec == P_FP32) ? 1 : 0;
     ta.wide = wide_now;
-    ta.skip = ctx->skip;
+    ta.skip = ctx->skip_now;
     ta.bn = screen ? ctx->bn.as<float>() : nullptr;
     ta.screened = screen ? ctx->screened.as<unsigned long long>() : nullptr;
     ta.mlp_skipped = screen ? ctx->screened.as<unsigned long long>() + 1 : nullptr;
-    ta.mlp = ctx->skip == 2 ? ctx->mlp.as<float>() : nullptr;
+    ta.mlp = ctx->skip_now == 2 ? ctx->mlp.as<float>() : nullptr;
     ta.mlp_z = ctx->mlp_z;
+    ta.mlp_cap = ctx->mlp_cap;
+    ta.mlp_bsum = ctx->skip_now == 2 ? ctx->mlp_bsum.as<double>() : nullptr;
     ta.xyz = ctx->have_xyz ? ctx->xyz.as<double>() : nullptr;
     ta.iter = ctx->update_index;
     ta.log_cap = ctx->log_cap;
     ta.log_x = ctx->log_cap > 0 ? ctx->log_x.as<float>() : nullptr;
     ta.log_y = ctx->log_cap > 0 ? ctx->log_y.as<float>() : nullptr;
+    ta.log_z = ctx->log_cap > 0 ? ctx->log_z.as<float>() : nullptr;
     ta.log_count = ctx->log_cap > 0 ? ctx->log_count.as<unsigned long long>() : nullptr;
     ta.kl_chunk = ctx->test_kl_chunk;
     return ta;
@@ -1091,6 +948,21 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     ctx->screened_total += sc[0];
     ctx->mlp_total += sc[1];
   }
+  if (tiled && ctx->skip_now == 2) {
+    // the network's budget: once the bounds of the outputs it skipped add up
+    // to more than mlp_budget for some system, the rest of the solve runs
+    // with the exact screen alone
+    ctx->mlp_updates++;
+    if (ctx->mlp_budget > 0.0) {
+      std::vector<double> bs(ctx->nsys);
+      HIPCHK(hipMemcpyAsync(bs.data(), ctx->mlp_bsum.p, (size_t)ctx->nsys * 8, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (double v : bs)
+        if (v > ctx->mlp_budget) ctx->skip_now = 1;
+      if (ctx->skip_now == 1 && ctx->verbose)
+        fprintf(stderr, "tc2: skip network budget spent after %d updates\n", ctx->mlp_updates);
+    }
+  }
   if (ctx->verbose) {
     float ms = 0.f;
     if (ctx->profile) (void)hipEventElapsedTime(&ms, ctx->pev[2], ctx->pev[3]);
@@ -1191,7 +1063,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   const int shape = ctx->shape[kind];
   const int mult = tile_subs(shape);
   const size_t tile = (size_t)(1 + D) * BS * prec_bytes(ctx->cur_prec);
-  const bool screen = ctx->skip != 0;
+  const bool screen = ctx->skip_now != 0;
   bool any_stopped = false;
   for (int s = 0; s < ctx->nsys; ++s) any_stopped |= !ctx->h_active[s];
   ctx->kind_used[kind] = true;
@@ -1207,6 +1079,13 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     double g = ctx->kept_prev2 > 0 ? (double)ctx->kept_prev / (double)ctx->kept_prev2 : 2.0;
     g = std::min(2.0, std::max(1.0, g));
     est = (long long)(ctx->kept_prev * g * 1.1) + 1024;
+  }
+  // geometric buckets (steps of 2^(1/4)): the capacity is part of the graph
+  // key, so updates whose estimates share a bucket replay the same graph
+  {
+    double v = 1024.0;
+    while (v < (double)est) v *= 1.189207115002721;
+    est = (long long)v;
   }
   if (ctx->test_stage_cap > 0) est = ctx->test_stage_cap;
   est = std::min<long long>(est, INT32_MAX / 2);
@@ -1349,7 +1228,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       ta.bf16 = kind == K_BF16 ? 1 : 0;
       ta.wide = kind == K_WIDE ? 1 : 0;
       ta.shape = shape;
-      ta.skip = ctx->skip;
+      ta.skip = ctx->skip_now;
       ta.bn = screen ? ctx->bn.as<float>() : nullptr;
       ta.screened = screen ? ctx->screened.as<unsigned long long>() : nullptr;
       ta.mlp_skipped = screen ? ctx->screened.as<unsigned long long>() + 1 : nullptr;
@@ -1549,12 +1428,25 @@ tc2_status export_results(tc2_ctx* ctx, hipStream_t st) {
   return TC2_OK;
 }
 
-tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
-  if (!ctx || !res) return TC2_EINVAL;
-  HIPCHK(hipSetDevice(ctx->device));
-  hipStream_t st = stream ? (hipStream_t)stream : ctx->own;
+// Whether the solve in progress has finished: no system is active and no
+// stage switch is pending (the next stage would reactivate systems).
+bool solve_finished(const tc2_ctx* ctx) {
+  const RunState& R = ctx->run;
+  for (int s = 0; s < ctx->nsys; ++s)
+    if (R.ss[s].active) return false;
+  if (R.phase == 0 && ctx->op_bf16) return false;
+  if (R.phase == 0 && R.reduced && ctx->closing == 2) return false;
+  return true;
+}
+
+// Start of a solve: counters reset, Gershgorin bounds, the initial matrices
+// and their scalars (every system restarts from H).
+tc2_status begin_solve(tc2_ctx* ctx, hipStream_t st) {
+  RunState& R = ctx->run;
   const int nsys = ctx->nsys, D = ctx->D, b = ctx->b, nb = ctx->nb;
-  std::vector<SysState> ss(nsys);
+  R.open = false;
+  R.st = st;
+  R.ss.assign(nsys, SysState());
   ctx->ms_sym = ctx->ms_num = ctx->ms_cmp = 0.0;
   for (int k = 0; k < 4; ++k) {
     ctx->ms_num_kind[k] = 0.0;
@@ -1564,41 +1456,52 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
   ctx->prev_out_bound = -1;
   ctx->kept_prev = ctx->kept_prev2 = 0;
   ctx->graph_updates = 0;
+  ctx->graph_captures = 0;
   for (bool& u : ctx->kind_used) u = false;
   ctx->screened_total = 0;
   ctx->mlp_total = 0;
   ctx->log_n = 0;
   if (ctx->log_cap > 0) launch_fill_int(st, ctx->log_count.as<int>(), 0, 2);
   ctx->num_launches = 0;
-  hipEvent_t ev0, ev1;
-  HIPCHK(hipEventCreate(&ev0));
-  HIPCHK(hipEventCreate(&ev1));
-  HIPCHK(hipEventRecord(ev0, st));
+  ctx->skip_now = ctx->skip;
+  ctx->mlp_updates = 0;
+  if (ctx->skip == 2) launch_fill_int(st, ctx->mlp_bsum.as<int>(), 0, 2LL * nsys);
+  if (ctx->count_useful) {
+    HIPCHK(ctx->useful_acc.reserve((size_t)nsys * 4 * 8));
+    launch_fill_int(st, ctx->useful_acc.as<int>(), 0, 8LL * nsys);
+  }
+  if (!R.ev0) HIPCHK(hipEventCreate(&R.ev0));
+  if (!R.ev1) HIPCHK(hipEventCreate(&R.ev1));
+  HIPCHK(hipEventRecord(R.ev0, st));
 
   // ---- Gershgorin bounds and the initial matrices
-  std::vector<double> emin(nsys), emax(nsys);
+  R.emin.assign(nsys, 0.0);
+  R.emax.assign(nsys, 0.0);
   launch_gershgorin(st, nb, b, ctx->h_rp.as<int>(), ctx->h_ci.as<int>(), ctx->h_v.as<double>(),
                     ctx->rowlo.as<double>(), ctx->rowhi.as<double>());
   launch_sys_minmax(st, nsys, ctx->sys_start.as<int>(), ctx->sys_end.as<int>(), b, ctx->rowlo.as<double>(),
                     ctx->rowhi.as<double>(), ctx->emin.as<double>(), ctx->emax.as<double>());
-  HIPCHK(hipMemcpyAsync(emin.data(), ctx->emin.p, nsys * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(emax.data(), ctx->emax.p, nsys * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(R.emin.data(), ctx->emin.p, nsys * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(R.emax.data(), ctx->emax.p, nsys * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  std::vector<int> mode(nsys), active(nsys, 0), branch(nsys, 0), bad(nsys, 0);
-  std::vector<unsigned long long> nominal(nsys, 0);
-  const size_t pin_nominal = ((size_t)nsys * 12 + 7) / 8 * 8;  // after three int arrays
-  HIPCHK(ctx->pin_loop.reserve(pin_nominal + (size_t)nsys * 8));
+  R.mode.assign(nsys, 0);
+  R.active.assign(nsys, 0);
+  R.branch.assign(nsys, 0);
+  R.bad.assign(nsys, 0);
+  R.nominal.assign(nsys, 0);
+  R.pin_nominal = ((size_t)nsys * 12 + 7) / 8 * 8;  // after three int arrays
+  HIPCHK(ctx->pin_loop.reserve(R.pin_nominal + (size_t)nsys * 8));
   for (int s = 0; s < nsys; ++s) {
-    mode[s] = ctx->sys[s].mode;
-    ss[s].status = TC2_OK;
-    if (mode[s] == 0 && !(emax[s] > emin[s])) {
-      ss[s].status = TC2_EDEGENERATE;
-      mode[s] = 1;  // placeholder result; status reports the error
+    R.mode[s] = ctx->sys[s].mode;
+    R.ss[s].status = TC2_OK;
+    if (R.mode[s] == 0 && !(R.emax[s] > R.emin[s])) {
+      R.ss[s].status = TC2_EDEGENERATE;
+      R.mode[s] = 1;  // placeholder result; status reports the error
     }
-    if (mode[s] == 0) ss[s].active = true;
+    if (R.mode[s] == 0) R.ss[s].active = true;
   }
-  HIPCHK(hipMemcpyAsync(ctx->mode.p, mode.data(), nsys * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(ctx->bad.p, bad.data(), nsys * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->mode.p, R.mode.data(), nsys * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->bad.p, R.bad.data(), nsys * 4, hipMemcpyHostToDevice, st));
   // reduced precision keeps FP32 values; BF16 rounds the MFMA operands only.
   // fp64_first leading updates run in FP64 before the switch.
   const int start_prec = (ctx->prec == P_FP64 || ctx->fp64_first > 0) ? P_FP64 : P_FP32;
@@ -1623,174 +1526,258 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
                 ctx->src_h.as<int>(), src1, ctx->h_v.as<double>(), h1v, ctx->sys_of.as<int>(),
                 ctx->emin.as<double>(), ctx->emax.as<double>(), ctx->mode.as<int>(), ctx->xv[0].p);
   }
-  std::vector<double> scal;
-  tc2_status st0 = measure(ctx, st, scal);
+  ctx->have_iterate = true;
+  tc2_status st0 = measure(ctx, st, R.scal);
   if (st0 != TC2_OK) return st0;
   for (int s = 0; s < nsys; ++s) {
-    energies(&scal[(size_t)s * NQ], D, ss[s].prev);
-    branch[s] = scal[(size_t)s * NQ + Q_TR0] >= (double)ctx->sys[s].n_occ ? 1 : 0;
+    energies(&R.scal[(size_t)s * NQ], D, R.ss[s].prev);
+    R.branch[s] = R.scal[(size_t)s * NQ + Q_TR0] >= (double)ctx->sys[s].n_occ ? 1 : 0;
   }
-
-  // ---- iterate.  phase 0: working precision; phase 1: closing FP64 pair
-  unsigned long long exec_pairs = 0;
+  if (ctx->count_useful) {
+    st0 = mask_iterate(ctx, st);
+    if (st0 != TC2_OK) return st0;
+  }
   // stages of a reduced-precision solve: [FP64 x fp64_first] -> [BF16] -> FP32
   // -> closing FP64 pair; each reduced stage runs to its own stopping test.
-  const bool reduced = ctx->prec != P_FP64;
+  R.reduced = ctx->prec != P_FP64;
   ctx->op_bf16 = ctx->prec == P_BF16 ? 1 : 0;
-  int phase = 0, updates = 0;
-  bool later_stage = false;
+  R.phase = 0;
+  R.updates = 0;
+  R.later_stage = false;
+  R.exec_pairs = 0;
+  R.open = true;
+  ctx->solve_index++;
+  return TC2_OK;
+}
+
+// One JSON line per system that took part in the update just run: the
+// scalars of the new iterate, the stopping quantities and the stored blocks.
+void log_update(tc2_ctx* ctx, const std::vector<int>& was_active, const std::vector<double>& dmax,
+                const std::vector<int>& cnt) {
+  FILE* f = fopen(ctx->metrics_log.c_str(), "a");
+  if (!f) return;
+  static const char* kinds[4] = {"fp64", "fp32", "bf16", "fp32w"};
+  const RunState& R = ctx->run;
+  for (int s = 0; s < ctx->nsys; ++s) {
+    if (!was_active[s]) continue;
+    const SysState& S = R.ss[s];
+    const double* q = &R.scal[(size_t)s * NQ];
+    fprintf(f, "{\"solve\": %d, \"system\": %d, \"update\": %d, \"branch\": \"%c\", "
+               "\"kind\": \"%s\", \"phase\": %d, \"tr_x0\": %.17g, \"e0\": %.17g, \"iota\": %.17g, "
+               "\"dmax\": %.17g, \"nnzb\": %d",
+            ctx->solve_index, s, S.k, S.branches.back(), kinds[ctx->last_kind], R.phase, q[Q_TR0],
+            q[Q_E0], q[Q_TR0] - q[Q_FRO0], dmax[s], cnt[s + 1] - cnt[s]);
+    const char* names[3] = {"tr_x1", "e1", "alpha"};
+    const int base[3] = {Q_TR1, Q_E1, Q_AL};
+    for (int k = 0; k < 3; ++k) {
+      fprintf(f, ", \"%s\": [", names[k]);
+      for (int d = 0; d < ctx->D; ++d) fprintf(f, "%s%.17g", d ? ", " : "", q[base[k] + d]);
+      fprintf(f, "]");
+    }
+    fprintf(f, ", \"active\": %s, \"status\": %d}\n", S.active ? "true" : "false", (int)S.status);
+  }
+  fclose(f);
+}
+
+// One update of every active system, preceded by the stage switch that is
+// due (BF16 -> FP32, reduced stage -> closing FP64 pair).  *done is set, and
+// no update runs, when the solve has finished.
+tc2_status advance_one(tc2_ctx* ctx, bool* done) {
+  RunState& R = ctx->run;
+  hipStream_t st = R.st;
+  const int nsys = ctx->nsys, D = ctx->D;
+  std::vector<SysState>& ss = R.ss;
+  *done = false;
   for (;;) {
     bool any = false;
     for (int s = 0; s < nsys; ++s) {
-      active[s] = ss[s].active ? 1 : 0;
+      R.active[s] = ss[s].active ? 1 : 0;
       any |= ss[s].active;
       if (ss[s].active) {
         const std::string& rep = ctx->sys[s].replay;
-        if (phase == 0 && !rep.empty()) branch[s] = rep[ss[s].k] == 'S' ? 1 : 0;
-        ss[s].branches.push_back(branch[s] ? 'S' : 'D');
+        if (R.phase == 0 && !rep.empty()) R.branch[s] = rep[ss[s].k] == 'S' ? 1 : 0;
+        ss[s].branches.push_back(R.branch[s] ? 'S' : 'D');
       }
     }
-    if (!any) {
-      if (phase == 0 && ctx->op_bf16) {
-        // BF16 stage done: continue with FP32 operands from where it stopped
-        ctx->op_bf16 = 0;
-        later_stage = true;
-        for (int s = 0; s < nsys; ++s)
-          if (mode[s] == 0 && ss[s].status >= 0 && ctx->sys[s].replay.empty()) {
-            ss[s].active = true;
-            ss[s].iota.clear();
-          }
-        continue;
-      }
-      if (phase == 0 && reduced && ctx->closing == 2) {
-        // closing pair in FP64: trace rule, then the opposite branch
-        tc2_status cs = convert_iterate(ctx, st, P_FP64);
-        if (cs != TC2_OK) return cs;
-        phase = 1;
-        for (int s = 0; s < nsys; ++s)
-          if (mode[s] == 0 && ss[s].status >= 0) {
-            ss[s].active = true;
-            ss[s].closing_left = 2;
-            ss[s].closing_first = branch[s];
-          }
-        continue;
-      }
-      break;
-    }
-    // flags in and status out through page-locked memory (the previous
-    // update's stream synchronisation guarantees its copies have completed):
-    // [active | branch | bad] ints, then nominal counts
-    char* pin = (char*)ctx->pin_loop.p;
-    memcpy(pin, active.data(), nsys * 4);
-    memcpy(pin + (size_t)nsys * 4, branch.data(), nsys * 4);
-    HIPCHK(hipMemcpyAsync(ctx->active.p, pin, nsys * 4, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ctx->branch.p, pin + (size_t)nsys * 4, nsys * 4, hipMemcpyHostToDevice, st));
-    ctx->h_active = active;
-    ctx->update_index = updates;
-    tc2_status r = TC2_OK;
-    {
-      const int kind_now = ctx->cur_prec == P_FP64 ? K_FP64
-                           : (ctx->op_bf16 ? K_BF16 : (ctx->wide ? K_WIDE : K_FP32));
-      // the closing pair runs as direct launches: two updates gain nothing
-      // from a captured graph, and sizing their FP64 buffers exactly (not by
-      // the graph's bounds) lets them fit in the buffers the reduced stage
-      // already holds
-      const bool use_graph = ctx->graph && ctx->graph_ok && ctx->kernel == 0 &&
-                             ctx->log_cap == 0 && ctx->skip != 2 && phase == 0 &&
-                             (!ctx->tune || ctx->tuned[kind_now]);
-      int g = 1;
-      if (use_graph) {
-        g = step_graph(ctx, st, scal, exec_pairs);
-        if (g == 1) ctx->graph_ok = false;  // the runtime refused the capture
-      }
-      r = g == 1 ? step(ctx, st, scal, exec_pairs) : (tc2_status)g;
-    }
-    if (r != TC2_OK) return r;
-    ++updates;
-    if (reduced && phase == 0 && ctx->cur_prec == P_FP64 && updates >= ctx->fp64_first) {
-      r = convert_iterate(ctx, st, P_FP32);
-      if (r != TC2_OK) return r;
-    }
-    HIPCHK(hipMemcpyAsync(pin + (size_t)nsys * 8, ctx->bad.p, nsys * 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(pin + pin_nominal, ctx->nominal.p, nsys * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    memcpy(bad.data(), pin + (size_t)nsys * 8, nsys * 4);
-    memcpy(nominal.data(), pin + pin_nominal, nsys * 8);
-    for (int s = 0; s < nsys; ++s) {
-      if (!ss[s].active) continue;
-      SysState& S = ss[s];
-      const SysInfo& si = ctx->sys[s];
-      const double* q = &scal[(size_t)s * NQ];
-      S.k++;
-      S.trip += q[Q_TRIP];
-      S.trip_kind[ctx->last_kind] += q[Q_TRIP];
-      S.nominal += (double)nominal[s];
-      double cur[1 + 2 * MAXD];
-      energies(q, D, cur);
-      const double iota = q[Q_TR0] - q[Q_FRO0];
-      S.iota.push_back(iota);
-      double dmax = 0.0;
-      for (int k = 0; k < 1 + 2 * D; ++k) dmax = std::max(dmax, std::fabs(cur[k] - S.prev[k]));
-      std::copy(cur, cur + 1 + 2 * D, S.prev);
-      if (ctx->verbose)
-        fprintf(stderr, "tc2 sys %d it %d %c tr-nocc %.3e iota %.3e E0 %.12f dmax %.3e\n", s, S.k,
-                S.branches.back(), q[Q_TR0] - (double)si.n_occ, iota, cur[0], dmax);
-      if (bad[s]) {
-        S.status = TC2_ENAN;
-        S.active = false;
-        continue;
-      }
-      if (phase == 1) {
-        // closing pair: the second step takes the branch opposite to the first
-        if (--S.closing_left == 0) S.active = false;
-        else branch[s] = S.closing_first ? 0 : 1;
-        continue;
-      }
-      const double tol = ctx->cur_prec == P_FP64 ? si.tol
-                                                 : std::max(si.tol, ctx->op_bf16 ? 1e-3 : 1e-6);
-      bool stop = false;
-      if (!si.replay.empty()) {
-        if (S.k == (int)si.replay.size()) {
-          stop = true;
-          S.status = TC2_OK;
+    if (any) break;
+    if (R.phase == 0 && ctx->op_bf16) {
+      // BF16 stage done: continue with FP32 operands from where it stopped
+      ctx->op_bf16 = 0;
+      R.later_stage = true;
+      for (int s = 0; s < nsys; ++s)
+        if (R.mode[s] == 0 && ss[s].status >= 0 && ctx->sys[s].replay.empty()) {
+          ss[s].active = true;
+          ss[s].iota.clear();
         }
-      } else if (S.k >= 2 && dmax < tol) {
-        stop = true;
-        S.status = TC2_OK;
-      } else if (ctx->op_bf16 && S.k >= 3 && std::fabs(iota) < 1e-2 * (double)si.n_occ) {
-        // bfloat16 stage: hand over to FP32 while the spectrum of X0 is still
-        // well inside (0, 1), before bfloat16 rounding can push it out
-        stop = true;
-        S.status = TC2_OK;
-      } else if (S.iota.size() >= 3 && (std::fabs(iota) < 1.0 || later_stage) &&
-                 std::fabs(iota) >= std::fabs(S.iota[S.iota.size() - 3])) {
-        // precision floor; in a stage that starts from a reduced-precision
-        // iterate, also a growing |iota| (eigenvalues pushed out of [0, 1])
-        stop = true;
-        S.status = TC2_FLOOR_REACHED;
-      } else if (S.k >= si.max_iter) {
-        stop = true;
-        S.status = TC2_NOT_CONVERGED;
-      }
-      if (stop) S.active = false;
-      branch[s] = q[Q_TR0] >= (double)si.n_occ ? 1 : 0;
+      continue;
     }
+    if (R.phase == 0 && R.reduced && ctx->closing == 2) {
+      // closing pair in FP64: trace rule, then the opposite branch
+      tc2_status cs = convert_iterate(ctx, st, P_FP64);
+      if (cs != TC2_OK) return cs;
+      if (ctx->count_useful && (cs = mask_iterate(ctx, st)) != TC2_OK) return cs;
+      R.phase = 1;
+      for (int s = 0; s < nsys; ++s)
+        if (R.mode[s] == 0 && ss[s].status >= 0) {
+          ss[s].active = true;
+          ss[s].closing_left = 2;
+          ss[s].closing_first = R.branch[s];
+        }
+      continue;
+    }
+    *done = true;
+    return TC2_OK;
   }
-  HIPCHK(hipEventRecord(ev1, st));
+  // flags in and status out through page-locked memory (the previous
+  // update's stream synchronisation guarantees its copies have completed):
+  // [active | branch | bad] ints, then nominal counts
+  char* pin = (char*)ctx->pin_loop.p;
+  memcpy(pin, R.active.data(), nsys * 4);
+  memcpy(pin + (size_t)nsys * 4, R.branch.data(), nsys * 4);
+  HIPCHK(hipMemcpyAsync(ctx->active.p, pin, nsys * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->branch.p, pin + (size_t)nsys * 4, nsys * 4, hipMemcpyHostToDevice, st));
+  ctx->h_active = R.active;
+  ctx->update_index = R.updates;
+  tc2_status r = TC2_OK;
+  {
+    const int kind_now = ctx->cur_prec == P_FP64 ? K_FP64
+                         : (ctx->op_bf16 ? K_BF16 : (ctx->wide ? K_WIDE : K_FP32));
+    // the closing pair runs as direct launches: two updates gain nothing
+    // from a captured graph, and sizing their FP64 buffers exactly (not by
+    // the graph's bounds) lets them fit in the buffers the reduced stage
+    // already holds
+    const bool use_graph = ctx->graph && ctx->graph_ok && ctx->kernel == 0 &&
+                           ctx->log_cap == 0 && ctx->skip_now != 2 && R.phase == 0 &&
+                           (!ctx->tune || ctx->tuned[kind_now]);
+    int g = 1;
+    if (use_graph) {
+      g = step_graph(ctx, st, R.scal, R.exec_pairs);
+      if (g == 1) ctx->graph_ok = false;  // the runtime refused the capture
+    }
+    r = g == 1 ? step(ctx, st, R.scal, R.exec_pairs) : (tc2_status)g;
+  }
+  if (r != TC2_OK) return r;
+  ++R.updates;
+  // exact useful count of this update, while the old iterate is still held
+  if (ctx->count_useful && (r = count_update(ctx, st)) != TC2_OK) return r;
+  if (R.reduced && R.phase == 0 && ctx->cur_prec == P_FP64 && R.updates >= ctx->fp64_first) {
+    r = convert_iterate(ctx, st, P_FP32);
+    if (r != TC2_OK) return r;
+    if (ctx->count_useful && (r = mask_iterate(ctx, st)) != TC2_OK) return r;
+  }
+  HIPCHK(hipMemcpyAsync(pin + (size_t)nsys * 8, ctx->bad.p, nsys * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(pin + R.pin_nominal, ctx->nominal.p, nsys * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  memcpy(R.bad.data(), pin + (size_t)nsys * 8, nsys * 4);
+  memcpy(R.nominal.data(), pin + R.pin_nominal, nsys * 8);
+  std::vector<int> was_active(R.active);
+  std::vector<double> dmaxs(nsys, 0.0);
+  for (int s = 0; s < nsys; ++s) {
+    if (!ss[s].active) continue;
+    SysState& S = ss[s];
+    const SysInfo& si = ctx->sys[s];
+    const double* q = &R.scal[(size_t)s * NQ];
+    S.k++;
+    S.trip += q[Q_TRIP];
+    S.nominal += (double)R.nominal[s];
+    double cur[1 + 2 * MAXD];
+    energies(q, D, cur);
+    const double iota = q[Q_TR0] - q[Q_FRO0];
+    S.iota.push_back(iota);
+    double dmax = 0.0;
+    for (int k = 0; k < 1 + 2 * D; ++k) dmax = std::max(dmax, std::fabs(cur[k] - S.prev[k]));
+    dmaxs[s] = dmax;
+    std::copy(cur, cur + 1 + 2 * D, S.prev);
+    if (ctx->verbose)
+      fprintf(stderr, "tc2 sys %d it %d %c tr-nocc %.3e iota %.3e E0 %.12f dmax %.3e\n", s, S.k,
+              S.branches.back(), q[Q_TR0] - (double)si.n_occ, iota, cur[0], dmax);
+    if (R.bad[s]) {
+      S.status = TC2_ENAN;
+      S.active = false;
+      continue;
+    }
+    if (R.phase == 1) {
+      // closing pair: the second step takes the branch opposite to the first
+      if (--S.closing_left == 0) S.active = false;
+      else R.branch[s] = S.closing_first ? 0 : 1;
+      continue;
+    }
+    const double tol = ctx->cur_prec == P_FP64 ? si.tol
+                                               : std::max(si.tol, ctx->op_bf16 ? 1e-3 : 1e-6);
+    bool stop = false;
+    if (!si.replay.empty()) {
+      if (S.k == (int)si.replay.size()) {
+        stop = true;
+        S.status = TC2_OK;
+      }
+    } else if (S.k >= 2 && dmax < tol) {
+      stop = true;
+      S.status = TC2_OK;
+    } else if (ctx->op_bf16 && S.k >= 3 && std::fabs(iota) < 1e-2 * (double)si.n_occ) {
+      // bfloat16 stage: hand over to FP32 while the spectrum of X0 is still
+      // well inside (0, 1), before bfloat16 rounding can push it out
+      stop = true;
+      S.status = TC2_OK;
+    } else if (S.iota.size() >= 3 && (std::fabs(iota) < 1.0 || R.later_stage) &&
+               std::fabs(iota) >= std::fabs(S.iota[S.iota.size() - 3])) {
+      // precision floor; in a stage that starts from a reduced-precision
+      // iterate, also a growing |iota| (eigenvalues pushed out of [0, 1])
+      stop = true;
+      S.status = TC2_FLOOR_REACHED;
+    } else if (S.k >= si.max_iter) {
+      stop = true;
+      S.status = TC2_NOT_CONVERGED;
+    }
+    if (stop) S.active = false;
+    R.branch[s] = q[Q_TR0] >= (double)si.n_occ ? 1 : 0;
+  }
+  if (!ctx->metrics_log.empty()) {
+    // stored blocks per system, from the new row pointer at the system
+    // boundaries: cnt[s + 1] - cnt[s]
+    std::vector<int> rp(ctx->nb + 1), cnt(nsys + 1, 0);
+    HIPCHK(hipMemcpyAsync(rp.data(), ctx->rp[ctx->cur].p, (size_t)(ctx->nb + 1) * 4,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int s = 0; s < nsys; ++s)
+      cnt[s + 1] = cnt[s] + (rp[ctx->sys[s].row0 + ctx->sys[s].nb] - rp[ctx->sys[s].row0]);
+    log_update(ctx, was_active, dmaxs, cnt);
+  }
+  return TC2_OK;
+}
+
+// Useful block products counted so far in this solve, per system and kernel
+// kind (count_useful), read from the device.
+tc2_status read_useful(tc2_ctx* ctx, hipStream_t st, std::vector<unsigned long long>& acc) {
+  acc.assign((size_t)ctx->nsys * 4, 0ull);
+  if (!ctx->count_useful) return TC2_OK;
+  HIPCHK(hipMemcpyAsync(acc.data(), ctx->useful_acc.p, acc.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return TC2_OK;
+}
+
+// End of a solve: timing, final scalars from the stored iterate, the export
+// and the per-system results.
+tc2_status finish_solve(tc2_ctx* ctx, tc2_result* res) {
+  RunState& R = ctx->run;
+  hipStream_t st = R.st;
+  const int nsys = ctx->nsys, D = ctx->D, b = ctx->b, nb = ctx->nb;
+  R.open = false;
+  HIPCHK(hipEventRecord(R.ev1, st));
   if (ctx->log_cap > 0) {
     unsigned long long n = 0;
     HIPCHK(hipMemcpyAsync(&n, ctx->log_count.p, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     ctx->log_n = std::min<long long>((long long)n, ctx->log_cap);
   }
-  HIPCHK(hipEventSynchronize(ev1));
+  HIPCHK(hipEventSynchronize(R.ev1));
   float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
+  HIPCHK(hipEventElapsedTime(&ms, R.ev0, R.ev1));
+  std::vector<unsigned long long> acc;
+  if (tc2_status s0 = read_useful(ctx, st, acc); s0 != TC2_OK) return s0;
 
   // final scalars straight from the stored iterate
-  st0 = measure(ctx, st, scal);
+  std::vector<double> scal;
+  tc2_status st0 = measure(ctx, st, scal);
   if (st0 != TC2_OK) return st0;
   if (ctx->export_m) {
     st0 = export_results(ctx, st);
@@ -1804,52 +1791,138 @@ tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
   const double b3 = 2.0 * b * b * b;
   const double kst = (double)((b + 3) / 4) * 4;
   for (int s = 0; s < nsys; ++s) {
-    tc2_result& R = res[s];
-    memset(&R, 0, sizeof(R));
+    tc2_result& Rs = res[s];
+    const SysState& S = R.ss[s];
+    memset(&Rs, 0, sizeof(Rs));
     const double* q = &scal[(size_t)s * NQ];
-    R.status = ss[s].status;
-    R.iters = ss[s].k;
-    R.tr_x0 = q[Q_TR0];
-    R.idem_err = q[Q_TR0] - q[Q_FRO0];
-    R.e0 = q[Q_E0];
+    Rs.status = S.status;
+    Rs.iters = S.k;
+    Rs.tr_x0 = q[Q_TR0];
+    Rs.idem_err = q[Q_TR0] - q[Q_FRO0];
+    Rs.e0 = q[Q_E0];
     for (int d = 0; d < D; ++d) {
-      R.trace_x1h1[d] = q[Q_AL + d];
-      R.tr_x1[d] = q[Q_TR1 + d];
-      R.e1[d] = q[Q_E1 + d];
+      Rs.trace_x1h1[d] = q[Q_AL + d];
+      Rs.tr_x1[d] = q[Q_TR1 + d];
+      Rs.e1[d] = q[Q_E1 + d];
     }
-    R.emin = emin[s];
-    R.emax = emax[s];
-    R.seconds = ms * 1e-3;
-    R.useful_flops = ss[s].trip * b3 * (1 + 2 * D);
-    R.nominal_flops = ss[s].nominal * b3 * (1 + 2 * D);
-    R.executed_flops = (s == 0) ? (double)exec_pairs * (1 + 2 * D) * 2.0 * BP * BP * kst : 0.0;
-    strncpy(R.branches, ss[s].branches.c_str(), TC2_MAX_ITER + 3);
-    R.ms_symbolic = ctx->ms_sym;
-    R.ms_numeric = ctx->ms_num;
+    Rs.emin = R.emin[s];
+    Rs.emax = R.emax[s];
+    Rs.seconds = ms * 1e-3;
+    Rs.union_flops = S.trip * b3 * (1 + 2 * D);
+    Rs.nominal_flops = S.nominal * b3 * (1 + 2 * D);
+    Rs.executed_flops = (s == 0) ? (double)R.exec_pairs * (1 + 2 * D) * 2.0 * BP * BP * kst : 0.0;
+    strncpy(Rs.branches, S.branches.c_str(), TC2_MAX_ITER + 3);
+    Rs.ms_symbolic = ctx->ms_sym;
+    Rs.ms_numeric = ctx->ms_num;
     for (int k = 0; k < 4; ++k) {
-      R.useful_flops_kind[k] = ss[s].trip_kind[k] * b3 * (1 + 2 * D);
-      R.ms_numeric_kind[k] = ctx->ms_num_kind[k];
-      R.numeric_launches_kind[k] = ctx->launches_kind[k];
+      Rs.useful_flops_kind[k] = (double)acc[(size_t)s * 4 + k] * b3;
+      Rs.useful_flops += Rs.useful_flops_kind[k];
+      Rs.ms_numeric_kind[k] = ctx->ms_num_kind[k];
+      Rs.numeric_launches_kind[k] = ctx->launches_kind[k];
     }
-    R.graph_updates = ctx->graph_updates;
-    R.ms_compact = ctx->ms_cmp;
-    R.numeric_launches = ctx->num_launches;
-    for (int k = 0; k < 4; ++k) R.tile_shape[k] = ctx->kind_used[k] ? ctx->shape[k] : -1;
-    R.ms_tune = ctx->ms_tune;
-    R.screened_blocks = (s == 0) ? (int64_t)ctx->screened_total : 0;
-    R.mlp_skipped_blocks = (s == 0) ? (int64_t)ctx->mlp_total : 0;
-    R.kept_blocks = final_rp[ctx->sys[s].row0 + ctx->sys[s].nb] - final_rp[ctx->sys[s].row0];
+    Rs.graph_updates = ctx->graph_updates;
+    Rs.graph_captures = ctx->graph_captures;
+    Rs.ms_compact = ctx->ms_cmp;
+    Rs.numeric_launches = ctx->num_launches;
+    for (int k = 0; k < 4; ++k) Rs.tile_shape[k] = ctx->kind_used[k] ? ctx->shape[k] : -1;
+    Rs.ms_tune = ctx->ms_tune;
+    Rs.screened_blocks = (s == 0) ? (int64_t)ctx->screened_total : 0;
+    Rs.mlp_skipped_blocks = (s == 0) ? (int64_t)ctx->mlp_total : 0;
+    Rs.mlp_updates = ctx->mlp_updates;
+    Rs.kept_blocks = final_rp[ctx->sys[s].row0 + ctx->sys[s].nb] - final_rp[ctx->sys[s].row0];
     if (ctx->export_m) {
       HostBsr& x0 = ctx->out_x0[s];
-      R.X0 = tc2_bsr{ctx->sys[s].nb, b, x0.row_ptr.data(), x0.col.data(), x0.val.data()};
+      Rs.X0 = tc2_bsr{ctx->sys[s].nb, b, x0.row_ptr.data(), x0.col.data(), x0.val.data()};
       for (int d = 0; d < D; ++d) {
         HostBsr& x1 = ctx->out_x1[d][s];
-        R.X1[d] = tc2_bsr{ctx->sys[s].nb, b, x1.row_ptr.data(), x1.col.data(), x1.val.data()};
+        Rs.X1[d] = tc2_bsr{ctx->sys[s].nb, b, x1.row_ptr.data(), x1.col.data(), x1.val.data()};
       }
     }
-    if (R.status < 0 && (worst >= 0 || R.status < worst)) worst = R.status;
-    else if (worst >= 0 && R.status > worst) worst = R.status;
+    if (Rs.status < 0 && (worst >= 0 || Rs.status < worst)) worst = Rs.status;
+    else if (worst >= 0 && Rs.status > worst) worst = Rs.status;
   }
+  return worst;
+}
+
+tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
+  if (!ctx || !res) return TC2_EINVAL;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = stream ? (hipStream_t)stream : ctx->own;
+  tc2_status r = begin_solve(ctx, st);
+  if (r != TC2_OK) return r;
+  for (;;) {
+    bool done = false;
+    if ((r = advance_one(ctx, &done)) != TC2_OK) {
+      ctx->run.open = false;
+      return r;
+    }
+    if (done) break;
+  }
+  return finish_solve(ctx, res);
+}
+
+tc2_status advance_impl(tc2_ctx* ctx, void* stream, int32_t max_updates, tc2_progress* prog,
+                        tc2_result* res) {
+  if (!ctx || !prog || !res || max_updates < 0) return TC2_EINVAL;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = stream ? (hipStream_t)stream : ctx->own;
+  memset(prog, 0, sizeof(*prog));
+  RunState& R = ctx->run;
+  tc2_status worst = TC2_OK;
+  const double b3 = 2.0 * ctx->b * ctx->b * ctx->b;
+  const double kst = (double)((ctx->b + 3) / 4) * 4;
+  auto useful_total = [&](double* out) -> tc2_status {
+    std::vector<unsigned long long> acc;
+    if (tc2_status s0 = read_useful(ctx, st, acc); s0 != TC2_OK) return s0;
+    double t = 0.0;
+    for (unsigned long long v : acc) t += (double)v;
+    *out = t * b3;
+    return TC2_OK;
+  };
+  double u0 = 0.0;
+  unsigned long long p0 = 0;
+  if (R.open) {
+    R.st = st;
+    if (tc2_status s0 = useful_total(&u0); s0 != TC2_OK) return s0;
+    p0 = R.exec_pairs;
+  }
+  auto bank = [&]() -> tc2_status {  // add the open solve's work since u0/p0 to prog
+    double u = 0.0;
+    if (tc2_status s0 = useful_total(&u); s0 != TC2_OK) return s0;
+    prog->useful_flops += u - u0;
+    prog->executed_flops += (double)(R.exec_pairs - p0) * (1 + 2 * ctx->D) * 2.0 * BP * BP * kst;
+    return TC2_OK;
+  };
+  tc2_status r;
+  while (prog->updates < max_updates) {
+    if (!R.open) {
+      if ((r = begin_solve(ctx, st)) != TC2_OK) return r;
+      u0 = 0.0;
+      p0 = 0;
+    }
+    bool done = false;
+    if ((r = advance_one(ctx, &done)) != TC2_OK) {
+      R.open = false;
+      return r;
+    }
+    if (done) {
+      if ((r = bank()) != TC2_OK) return r;
+      worst = finish_solve(ctx, res);
+      if (worst < 0) return worst;
+      prog->solves_completed++;
+      continue;
+    }
+    prog->updates++;
+  }
+  if (R.open && solve_finished(ctx)) {
+    if ((r = bank()) != TC2_OK) return r;
+    worst = finish_solve(ctx, res);
+    if (worst < 0) return worst;
+    prog->solves_completed++;
+  } else if (R.open) {
+    if ((r = bank()) != TC2_OK) return r;
+  }
+  prog->solve_open = R.open ? 1 : 0;
   return worst;
 }
 
@@ -1865,14 +1938,26 @@ extern "C" tc2_status tc2_run(tc2_ctx* ctx, void* hip_stream, tc2_result* res) {
   }
 }
 
-extern "C" int64_t tc2_log_copy(tc2_ctx* ctx, float* x, float* y, int64_t cap) {
+extern "C" tc2_status tc2_advance(tc2_ctx* ctx, void* hip_stream, int32_t max_updates,
+                                  tc2_progress* prog, tc2_result* res) {
+  try {
+    return advance_impl(ctx, hip_stream, max_updates, prog, res);
+  } catch (const std::bad_alloc&) {
+    return TC2_ENOMEM;
+  } catch (...) {
+    return TC2_EDEVICE;
+  }
+}
+
+extern "C" int64_t tc2_log_copy(tc2_ctx* ctx, float* x, float* y, float* z, int64_t cap) {
   if (!ctx || cap < 0 || (cap > 0 && (!x || !y))) return TC2_EINVAL;
   if (ctx->log_cap <= 0) return 0;
   if (hipSetDevice(ctx->device) != hipSuccess) return TC2_EDEVICE;
   const long long n = std::min<long long>(ctx->log_n, cap);
   if (n == 0) return 0;
   if (hipMemcpy(x, ctx->log_x.p, (size_t)n * MLP_NF * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(y, ctx->log_y.p, (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      hipMemcpy(y, ctx->log_y.p, (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      (z && hipMemcpy(z, ctx->log_z.p, (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess))
     return TC2_EDEVICE;
   return n;
 }

@@ -454,6 +454,7 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
       }
     }
     int nlog = 0;
+    unsigned netskip_mask = 0u;  // outputs skipped by the network (bit o)
     bool logit_o[NO];
     float feat[MLP_NF];
 #pragma unroll
@@ -502,24 +503,42 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
                          : -3.f;
       feat[6] = 0.05f * (float)a.iter;
       feat[7] = square ? 1.f : 0.f;
+      bool net_skip = false;
+      float z = 0.f;
       if (a.skip == 2) {
-        const float z = mlp_logit_wave(th, feat, lane);
-        if (z > a.mlp_z) {
-          owned[o] = false;
-          if (lane == 0) atomicAdd(a.mlp_skipped, 1ull);
-          continue;
+        z = mlp_logit_wave(th, feat, lane);
+        // the network may skip only an output whose exact bound is below
+        // mlp_cap * eps for every matrix, and never, on the DOUBLE branch, a
+        // stored block whose 2 ||X_IJ|| alone reaches eps
+        bool allowed = true;
+        double bmx = 0.0;
+#pragma unroll
+        for (int m = 0; m <= D; ++m) {
+          allowed = allowed && bnd[m] < (double)a.mlp_cap * eps;
+          if (!square && eIJ >= 0) allowed = allowed && 2.0 * (double)a.bn[(size_t)eIJ * (1 + D) + m] < eps;
+          bmx = fmax(bmx, bnd[m]);
+        }
+        net_skip = allowed && z > a.mlp_z;
+        if (net_skip && lane == 0) {
+          atomicAdd(a.mlp_skipped, 1ull);
+          atomicAdd(&a.mlp_bsum[sys], bmx);
         }
       }
       if (a.log_cap > 0) {
         logit_o[o] = true;
-        // features to a slot claimed below; lane o keeps them until then
-        if (lane < MLP_NF) {
-          float v = 0.f;
+        // features (and the logit) to a slot claimed below; the wave keeps them
+        // in its private scratch until then
+        if (lane <= MLP_NF) {
+          float v = z;
 #pragma unroll
           for (int i = 0; i < MLP_NF; ++i) v = (lane == i) ? feat[i] : v;
-          ns[wave * NO * MLP_NF + o * MLP_NF + lane] = v;  // wave-private scratch
+          ns[wave * NO * (MLP_NF + 1) + o * (MLP_NF + 1) + lane] = v;
         }
         ++nlog;
+      }
+      if (net_skip) {
+        owned[o] = false;
+        netskip_mask |= 1u << o;
       }
     }
     if (a.log_cap > 0 && nlog > 0) {
@@ -532,7 +551,11 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
         if (!logit_o[o]) continue;
         const long long slot = (long long)base_slot + rank++;
         if (slot < a.log_cap) {
-          if (lane < MLP_NF) a.log_x[slot * MLP_NF + lane] = ns[wave * NO * MLP_NF + o * MLP_NF + lane];
+          const float* v = ns + wave * NO * (MLP_NF + 1) + o * (MLP_NF + 1);
+          if (lane < MLP_NF) a.log_x[slot * MLP_NF + lane] = v[lane];
+          if (lane == 0 && a.log_z) a.log_z[slot] = v[MLP_NF];
+          // the outcome of an output the network skipped is not known
+          if (lane == 0 && ((netskip_mask >> o) & 1u)) a.log_y[slot] = -1.f;
           if (lane == o) my_slot = (int)slot;
         }
       }

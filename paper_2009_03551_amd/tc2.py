@@ -45,7 +45,8 @@ class tc2_options(C.Structure):
                 ("fp64_first", C.c_int32), ("mlp_weights", C.POINTER(C.c_float)),
                 ("mlp_threshold", C.c_float), ("log_capacity", C.c_int64),
                 ("wide_accumulate", C.c_int32), ("tune", C.c_int32), ("tune_cache", C.c_char_p),
-                ("graph", C.c_int32)]
+                ("graph", C.c_int32), ("metrics_log", C.c_char_p), ("count_useful", C.c_int32),
+                ("mlp_bound_cap", C.c_float), ("mlp_budget", C.c_double)]
 
 
 class tc2_result(C.Structure):
@@ -53,14 +54,15 @@ class tc2_result(C.Structure):
                 ("tr_x0", C.c_double), ("idem_err", C.c_double), ("tr_x1", C.c_double * 3),
                 ("e0", C.c_double), ("e1", C.c_double * 3), ("emin", C.c_double),
                 ("emax", C.c_double), ("seconds", C.c_double), ("useful_flops", C.c_double),
+                ("union_flops", C.c_double),
                 ("executed_flops", C.c_double), ("kept_blocks", C.c_int64),
                 ("screened_blocks", C.c_int64), ("mlp_skipped_blocks", C.c_int64),
-                ("ms_symbolic", C.c_double), ("ms_numeric", C.c_double),
+                ("mlp_updates", C.c_int32), ("ms_symbolic", C.c_double), ("ms_numeric", C.c_double),
                 ("ms_compact", C.c_double), ("numeric_launches", C.c_int32),
                 ("tile_shape", C.c_int32 * 4), ("ms_tune", C.c_double),
                 ("useful_flops_kind", C.c_double * 4), ("ms_numeric_kind", C.c_double * 4),
                 ("numeric_launches_kind", C.c_int32 * 4), ("graph_updates", C.c_int32),
-                ("nominal_flops", C.c_double),
+                ("graph_captures", C.c_int32), ("nominal_flops", C.c_double),
                 ("branches", C.c_char * (TC2_MAX_ITER + 4)),
                 ("X0", tc2_bsr), ("X1", tc2_bsr * 3)]
 
@@ -99,12 +101,19 @@ def lib() -> C.CDLL:
     return _lib
 
 
-EXPORTED = ("tc2_setup", "tc2_run", "tc2_free", "tc2_strerror", "tc2_version",
+EXPORTED = ("tc2_setup", "tc2_run", "tc2_advance", "tc2_free", "tc2_strerror", "tc2_version",
+            "tc2_export_rows", "tc2_iterate_size", "tc2_export_entries", "tc2_compare_entries",
             "tc2_mlp_forward", "tc2_mlp_grad", "tc2_mlp_train", "tc2_log_copy",
             "tc2_dense_response", "tc2_lowdin", "tc2_congruence", "tc2_bsr_release",
             "tc2_lowdin_response", "tc2_congruence_response")
 
 MLP_IN, MLP_PARAMS = 8, 4801
+
+
+class tc2_progress(C.Structure):
+    _fields_ = [("updates", C.c_int32), ("solves_completed", C.c_int32),
+                ("solve_open", C.c_int32), ("useful_flops", C.c_double),
+                ("executed_flops", C.c_double)]
 
 
 class tc2_mlp_train_opts(C.Structure):
@@ -205,6 +214,9 @@ class Result:
     X0: Optional[BSR] = None
     X1: List[BSR] = field(default_factory=list)
     nominal_flops: float = 0.0
+    union_flops: float = 0.0
+    graph_captures: int = 0
+    mlp_updates: int = 0
 
     @property
     def status_name(self) -> str:
@@ -239,7 +251,9 @@ class Solver:
                  profile: bool = False, kernel: str = "tile", use_xyz: bool = True,
                  fp64_first: int = 0, skip: str = "none", mlp_weights=None,
                  mlp_threshold: float = 0.99, log_capacity: int = 0, wide: bool = False,
-                 tune: bool = False, tune_cache: Optional[str] = None, graph: bool = False):
+                 tune: bool = False, tune_cache: Optional[str] = None, graph: bool = False,
+                 count_useful: bool = False, metrics_log: Optional[str] = None,
+                 mlp_bound_cap: float = 0.0, mlp_budget: float = 0.0):
         if isinstance(systems, System):
             systems = [systems]
         self.systems = list(systems)
@@ -277,19 +291,16 @@ class Solver:
                            1 if export else 0, 1 if verbose else 0, 1 if profile else 0,
                            KERNEL[kernel], int(fp64_first), wptr, float(mlp_threshold),
                            int(log_capacity), 1 if wide else 0, 1 if tune else 0,
-                           tune_cache.encode() if tune_cache else None, 1 if graph else 0)
+                           tune_cache.encode() if tune_cache else None, 1 if graph else 0,
+                           metrics_log.encode() if metrics_log else None,
+                           1 if count_useful else 0, float(mlp_bound_cap), float(mlp_budget))
         self.log_capacity = int(log_capacity)
         self._ctx = C.c_void_p()
         st = lib().tc2_setup(probs, n, C.byref(opts), C.byref(self._ctx))
         if st != 0:
             raise TC2Error(st, "tc2_setup")
 
-    def run(self, stream: Optional[int] = None, check: bool = True) -> List[Result]:
-        n = len(self.systems)
-        res = (tc2_result * n)()
-        st = lib().tc2_run(self._ctx, C.c_void_p(stream) if stream else None, res)
-        if check and st < 0:
-            raise TC2Error(st, "tc2_run")
+    def _results(self, res) -> List[Result]:
         out = []
         D = self.n_dir
         for r in res:
@@ -303,20 +314,126 @@ class Solver:
                               r.numeric_launches, list(r.tile_shape), r.ms_tune,
                               list(r.useful_flops_kind), list(r.ms_numeric_kind),
                               list(r.numeric_launches_kind), r.graph_updates, x0, x1,
-                              r.nominal_flops))
+                              r.nominal_flops, r.union_flops, r.graph_captures,
+                              r.mlp_updates))
         return out
 
-    def log(self):
-        """(features n x 8, labels n) logged by the last run (1 = dropped)."""
+    def run(self, stream: Optional[int] = None, check: bool = True) -> List[Result]:
+        n = len(self.systems)
+        res = (tc2_result * n)()
+        st = lib().tc2_run(self._ctx, C.c_void_p(stream) if stream else None, res)
+        if check and st < 0:
+            raise TC2Error(st, "tc2_run")
+        return self._results(res)
+
+    def advance(self, max_updates: int, stream: Optional[int] = None):
+        """Run at most ``max_updates`` updates (tc2_advance).  Returns
+        (progress dict, results of the last solve finished in this call or
+        None)."""
+        n = len(self.systems)
+        res = (tc2_result * n)()
+        prog = tc2_progress()
+        L = lib()
+        L.tc2_advance.restype = C.c_int
+        L.tc2_advance.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(tc2_progress),
+                                  C.POINTER(tc2_result)]
+        st = L.tc2_advance(self._ctx, C.c_void_p(stream) if stream else None, int(max_updates),
+                           C.byref(prog), res)
+        if st < 0:
+            raise TC2Error(st, "tc2_advance")
+        p = dict(updates=prog.updates, solves_completed=prog.solves_completed,
+                 solve_open=bool(prog.solve_open), useful_flops=prog.useful_flops,
+                 executed_flops=prog.executed_flops)
+        return p, (self._results(res) if prog.solves_completed else None)
+
+    def export_rows(self, system: int, rows: Sequence[int]):
+        """Complete block rows of the current X0 and X1_d of one problem
+        (tc2_export_rows): (X0, [X1_d]) as BSR with only those rows filled."""
+        rr = np.ascontiguousarray(rows, dtype=np.int32)
+        x0 = tc2_bsr()
+        x1 = (tc2_bsr * 3)()
+        L = lib()
+        L.tc2_export_rows.restype = C.c_int
+        L.tc2_export_rows.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                      C.POINTER(tc2_bsr), C.POINTER(tc2_bsr)]
+        st = L.tc2_export_rows(self._ctx, int(system), rr.ctypes.data_as(C.POINTER(C.c_int32)),
+                               len(rr), C.byref(x0), x1)
+        if st != 0:
+            raise TC2Error(st, "tc2_export_rows")
+        try:
+            return _py_bsr(x0), [_py_bsr(x1[d]) for d in range(self.n_dir)]
+        finally:
+            _release(x0)
+            for d in range(self.n_dir):
+                _release(x1[d])
+
+    def iterate_size(self) -> int:
+        n = C.c_int64()
+        L = lib()
+        L.tc2_iterate_size.restype = C.c_int
+        L.tc2_iterate_size.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        st = L.tc2_iterate_size(self._ctx, C.byref(n))
+        if st != 0:
+            raise TC2Error(st, "tc2_iterate_size")
+        return int(n.value)
+
+    def export_entries(self, matrix: int, first: int, count: int, values: bool = True):
+        """(rows, cols, vals) of entries [first, first + count) of the merged
+        current iterate, matrix 0 = X0, 1 + d = X1_d (tc2_export_entries)."""
+        b = self.systems[0].H.b
+        rows = np.empty(max(count, 1), dtype=np.int32)
+        cols = np.empty(max(count, 1), dtype=np.int32)
+        vals = np.empty((max(count, 1), b, b), dtype=np.float64) if values else None
+        L = lib()
+        L.tc2_export_entries.restype = C.c_int
+        L.tc2_export_entries.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64,
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_double)]
+        st = L.tc2_export_entries(self._ctx, int(matrix), int(first), int(count),
+                                  rows.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  cols.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  vals.ctypes.data_as(C.POINTER(C.c_double)) if values else None)
+        if st != 0:
+            raise TC2Error(st, "tc2_export_entries")
+        return rows[:count], cols[:count], (vals[:count] if values else None)
+
+    def compare_entries(self, matrix: int, rows, cols, vals) -> float:
+        """max |A - B| over the union of the patterns of the caller's entries A
+        and matrix ``matrix`` of the current iterate B (tc2_compare_entries)."""
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        cols = np.ascontiguousarray(cols, dtype=np.int32)
+        vals = np.ascontiguousarray(vals, dtype=np.float64)
+        out = C.c_double()
+        L = lib()
+        L.tc2_compare_entries.restype = C.c_int
+        L.tc2_compare_entries.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]
+        st = L.tc2_compare_entries(self._ctx, int(matrix), len(rows),
+                                   rows.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   cols.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   vals.ctypes.data_as(C.POINTER(C.c_double)), C.byref(out))
+        if st != 0:
+            raise TC2Error(st, "tc2_compare_entries")
+        return float(out.value)
+
+    def log(self, logits: bool = False):
+        """(features n x 8, labels n) logged by the last run (1 = dropped,
+        0 = kept, -1 = skipped by the network); with ``logits``, also the
+        logits of the in-kernel network."""
         cap = self.log_capacity
         x = np.empty((max(cap, 1), MLP_IN), dtype=np.float32)
         y = np.empty(max(cap, 1), dtype=np.float32)
+        z = np.empty(max(cap, 1), dtype=np.float32)
         L = lib()
         L.tc2_log_copy.restype = C.c_int64
-        L.tc2_log_copy.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int64]
-        n = L.tc2_log_copy(self._ctx, _fptr(x), _fptr(y), cap)
+        L.tc2_log_copy.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                   C.POINTER(C.c_float), C.c_int64]
+        n = L.tc2_log_copy(self._ctx, _fptr(x), _fptr(y), _fptr(z), cap)
         if n < 0:
             raise TC2Error(int(n), "tc2_log_copy")
+        if logits:
+            return x[:n].copy(), y[:n].copy(), z[:n].copy()
         return x[:n].copy(), y[:n].copy()
 
     def close(self):

@@ -1,6 +1,8 @@
 """Write the oracle's results for the full-size workloads used by the GPU
-parity tests (scalars and a seeded sample of blocks).  Calls only oracle/ and
-the seeded input generator; run it on the CPU:
+parity tests: the scalars of every update (Tr X0, E0, E1_d, alpha_d, iota),
+a seeded sample of blocks, and complete block rows of the final X0 and X1_d
+(a corner, an edge and the centre atom of the cube) in <name>_rows.npz.
+Calls only oracle/ and the seeded input generator; run it on the CPU:
 
     python tests/golden/make_golden.py cube10      # about 15 min on 8 cores
 """
@@ -31,6 +33,16 @@ def sample_pairs(nb, X0, b, rng, n_near=24, n_far=8):
     return pairs
 
 
+def full_rows(name, nb):
+    """Atoms whose complete block rows are stored: a corner, an edge atom and
+    the centre of the cube (or the two ends and the middle of a chain)."""
+    L = round(nb ** (1.0 / 3.0))
+    if L ** 3 == nb:
+        h = L // 2
+        return [0, h * L, h * L * L + h * L + h]          # (0,0,0), (0,h,0), (h,h,h)
+    return [0, nb // 2, nb - 1]
+
+
 def main(name):
     s = W.config_system(name)
     t0 = time.time()
@@ -45,11 +57,24 @@ def main(name):
                emin=r.emin, emax=r.emax, tr_x0=float(np.trace(r.X0)),
                e0=r.history[-1]["E0"], e1=r.history[-1]["E1"],
                idem=r.history[-1]["iota"], oracle_seconds=dt,
+               history=r.history,
                blocks=[dict(I=i, J=j, X0=blk(r.X0, i, j), X1=[blk(x, i, j) for x in r.X1])
                        for i, j in pairs])
     path = os.path.join(HERE, f"{name}_oracle.json")
     with open(path, "w") as f:
         json.dump(out, f)
+    # complete rows: every block (I, J) nonzero in X0 or some X1_d
+    rows = full_rows(name, nb)
+    mats = [r.X0] + list(r.X1)
+    arrays = {}
+    for I in rows:
+        strip = np.stack([m[I * b:(I + 1) * b, :].reshape(b, nb, b).transpose(1, 0, 2) for m in mats],
+                         axis=1)                                  # (nb, 1 + D, b, b)
+        cols = np.nonzero(np.any(strip != 0.0, axis=(1, 2, 3)))[0]
+        arrays[f"cols_{I}"] = cols.astype(np.int32)
+        arrays[f"vals_{I}"] = strip[cols]
+    arrays["rows"] = np.array(rows, dtype=np.int32)
+    np.savez_compressed(os.path.join(HERE, f"{name}_rows.npz"), **arrays)
     print(f"wrote {path}: {r.iters} updates {r.branches} alpha={r.alpha} in {dt:.0f} s")
 
 

@@ -392,3 +392,54 @@ def test_solve_stops_where_the_rule_first_fires():
     # on this run a guard comparing with k-1 would stop one update earlier
     k1 = next(k for k in range(3, len(io) + 1) if io[k - 1] < 1.0 and io[k - 1] >= io[k - 2])
     assert k1 == 22
+
+
+# ---------------------------------------------------------------- useful block products of an update
+def _brute_useful(prev, new, b):
+    """The same count by a triple loop over block indices (the definition
+    written out element by element)."""
+    nb = prev[0].shape[0] // b
+    nz = lambda X, i, j: np.any(X[i * b:(i + 1) * b, j * b:(j + 1) * b] != 0.0)
+    total = 0
+    for I in range(nb):
+        for J in range(I, nb):
+            for K in range(nb):
+                if nz(new[0], I, J) and nz(prev[0], I, K) and nz(prev[0], K, J):
+                    total += 1
+                for d in range(1, len(prev)):
+                    if nz(new[d], I, J):
+                        total += int(nz(prev[0], I, K) and nz(prev[d], K, J))
+                        total += int(nz(prev[d], I, K) and nz(prev[0], K, J))
+    return total
+
+
+def test_useful_products_by_hand():
+    # 3 blocks of size 1; X0 tridiagonal, X1 diagonal; after the update every
+    # X0 block is kept, X1 keeps only (0, 0) and (0, 1)
+    X0 = np.array([[1.0, 0.5, 0.0], [0.5, 1.0, 0.5], [0.0, 0.5, 1.0]])
+    X1 = np.diag([0.2, 0.0, 0.3])
+    N0 = np.ones((3, 3))
+    N1 = np.zeros((3, 3))
+    N1[0, 0] = N1[0, 1] = N1[1, 0] = 1.0
+    # X0 X0 on upper outputs: (0,0): K=0,1 -> 2; (0,1): K=0,1 -> 2; (0,2): K=1 -> 1;
+    # (1,1): 3; (1,2): 2; (2,2): 2  => 12
+    # X0 X1 + X1 X0 at (0,0): X0_00 X1_00 + X1_00 X0_00 = 2; at (0,1): X0_0K X1_K1 (X1_11 = 0) -> 0,
+    # X1_0K X0_K1: K = 0 -> 1  => 3
+    assert O.useful_products([X0, X1], [N0, N1], 1) == 15
+    assert _brute_useful([X0, X1], [N0, N1], 1) == 15
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_useful_products_equals_the_triple_loop(seed):
+    rng = np.random.default_rng(seed)
+    nb, b, D = 7, 2, 2
+
+    def sym_blocks(p):
+        m = np.triu(rng.random((nb, nb)) < p)
+        m = m | m.T | np.eye(nb, dtype=bool)
+        X = rng.standard_normal((nb * b, nb * b)) * np.kron(m, np.ones((b, b)))
+        return X + X.T
+    prev = [sym_blocks(0.4) for _ in range(1 + D)]
+    new = [sym_blocks(0.6) for _ in range(1 + D)]
+    prev[1][:b, :] = 0.0                        # an empty block row of X1_1
+    assert O.useful_products(prev, new, b) == _brute_useful(prev, new, b)
