@@ -351,15 +351,37 @@ def snapshot(solver, D: int, chunk: int = 1 << 20):
     return rows, cols, vals
 
 
-def gate(solver, snap, res, ref_res, name: str) -> dict:
+def gate(solver, snap, res, ref_res, name: str, eps: float) -> dict:
     """max |dX1| over the union of the patterns (on the device) and relative
-    |d alpha| of the chosen variant's last solve against a reference."""
+    |d alpha| of the chosen variant's last solve against a reference.  The
+    difference is also split into blocks both runs keep and blocks only one
+    run keeps (a block whose norm lies near the drop threshold, kept by one
+    run and dropped by the other)."""
     rows, cols, vals = snap
-    dx1 = max([solver.compare_entries(1 + d, rows, cols, v) for d, v in enumerate(vals)] + [0.0])
+    dx1, det = 0.0, None
+    for d, v in enumerate(vals):
+        x, dd = solver.compare_entries(1 + d, rows, cols, v, detail=True)
+        dx1 = max(dx1, x)
+        if det is None:
+            det = dd
+        else:
+            for k in ("max_both", "max_given_only", "max_iterate_only", "max_norm_one_side"):
+                det[k] = max(det[k], dd[k])
+            det["n_given_only"] += dd["n_given_only"]
+            det["n_iterate_only"] += dd["n_iterate_only"]
     dal = max([abs(x - y) / abs(y) for g, f in zip(res, ref_res) for x, y in zip(g.alpha, f.alpha)]
               + [0.0])
-    return {"max_abs_dX1": dx1, "rel_dalpha": dal, "pass": bool(dx1 < 1e-6 and dal < 1e-6),
-            "against": name}
+    out = {"max_abs_dX1": dx1, "rel_dalpha": dal, "pass": bool(dx1 < 1e-6 and dal < 1e-6),
+           "against": name}
+    if det:
+        out["split"] = {"max_abs_dX1_blocks_both_keep": det["max_both"],
+                        "blocks_kept_by_reference_only": det["n_given_only"],
+                        "blocks_kept_by_chosen_only": det["n_iterate_only"],
+                        "max_abs_in_one_side_blocks": max(det["max_given_only"],
+                                                          det["max_iterate_only"]),
+                        "max_norm_of_one_side_block_over_eps": det["max_norm_one_side"] / eps
+                        if eps > 0 else None}
+    return out
 
 
 def main() -> int:
@@ -527,6 +549,8 @@ def main() -> int:
             gates[name] = dict(g)
         else:
             cur = gates[name]
+            if g["max_abs_dX1"] > cur["max_abs_dX1"]:
+                cur["split"] = g.get("split")
             cur["max_abs_dX1"] = max(cur["max_abs_dX1"], g["max_abs_dX1"])
             cur["rel_dalpha"] = max(cur["rel_dalpha"], g["rel_dalpha"])
             cur["pass"] = cur["pass"] and g["pass"]
@@ -561,7 +585,7 @@ def main() -> int:
                 done.append(r)
         results = done[-1]
         for name, res, snap in per_unit:
-            add_gate(name, gate(sv, snap, results, res, name))
+            add_gate(name, gate(sv, snap, results, res, name, sysm.eps))
         sv.close()
         ms_per_step = elapsed / args.steps * 1e3
         value = timed_useful / elapsed / 1e9
@@ -590,7 +614,7 @@ def main() -> int:
             timed_useful += sum(x.useful_flops for x in res[-1])
             timed_exec += sum(x.executed_flops for x in res[-1])
             for name, rres, snap, wall in rdone:
-                add_gate(name, gate(sv, snap, res[-1], rres, name))
+                add_gate(name, gate(sv, snap, res[-1], rres, name, sysm.eps))
             sv.close()
             log(f"  unit of {len(u)} systems / {sum(x.H.nb for x in u)} atoms: {dt:.2f} s/solve; "
                 f"gate so far {gates}")

@@ -276,10 +276,17 @@ TC2_API tc2_status tc2_export_entries(tc2_ctx *ctx, int32_t matrix, int64_t firs
  * row-major order, with b x b row-major values), B is matrix m of the current
  * iterate; a block missing on one side counts as zero.  The caller's values
  * are uploaded in chunks, so A may be larger than the free device memory
- * (its rows and columns are uploaded whole).
+ * (its rows and columns are uploaded whole).  detail (NULL, or 6 doubles)
+ * receives: the largest difference over blocks both sides hold; the largest
+ * |A| over nonzero blocks only A holds; the largest |B| over nonzero blocks
+ * only B holds; the counts of those two kinds of blocks; and the largest
+ * Frobenius norm of a block held by one side only.  Under a drop threshold,
+ * blocks held by one side only are those whose norm lies near the threshold
+ * and that one side kept and the other dropped.
  * Errors: TC2_EINVAL (ranges, order, NULL), TC2_ENOMEM, TC2_EDEVICE. */
 TC2_API tc2_status tc2_compare_entries(tc2_ctx *ctx, int32_t matrix, int64_t n, const int32_t *rows,
-                                       const int32_t *cols, const double *vals, double *max_abs);
+                                       const int32_t *cols, const double *vals, double *max_abs,
+                                       double *detail);
 
 /* Copy the samples logged by the last tc2_run (log_capacity > 0): features
  * (n x TC2_MLP_IN floats: scaled log10 of the norm bounds of X0 and X1 relative

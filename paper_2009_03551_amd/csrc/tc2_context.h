@@ -9,6 +9,7 @@
 #include "../../include/tc2.h"
 
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace tc2 {
@@ -38,6 +39,40 @@ struct DBuf {
     }
     cap = want;
     return hipSuccess;
+  }
+  // grow to at least n bytes, by at least a quarter of the current capacity
+  // (contents are not preserved): a buffer that grows over many updates is
+  // reallocated a few times instead of at every update
+  hipError_t reserve_grow(size_t n) {
+    if (n <= cap && p) return hipSuccess;
+    const size_t g = cap + cap / 4;
+    return reserve(n > g ? n : g);
+  }
+  // grow to at least n bytes keeping the first `keep` bytes: a new buffer,
+  // a device copy on stream st, then the old buffer is freed (after the copy)
+  hipError_t grow_keep(size_t n, size_t keep, hipStream_t st) {
+    if (n <= cap && p) return hipSuccess;
+    const size_t g = cap + cap / 4;
+    const size_t want = n > g ? n : g;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, want);
+    if (e != hipSuccess) return e;
+    if (p && keep) {
+      e = hipMemcpyAsync(q, p, keep < cap ? keep : cap, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        (void)hipFree(q);
+        return e;
+      }
+    }
+    release();
+    p = q;
+    cap = want;
+    return hipSuccess;
+  }
+  void swap(DBuf& o) {
+    std::swap(p, o.p);
+    std::swap(cap, o.cap);
   }
   template <typename T> T* as() const { return (T*)p; }
 };
@@ -138,7 +173,10 @@ struct tc2_ctx {
   // initial pattern (union of H and H1 patterns) and its sources
   int nnz0 = 0;
   tc2::DBuf x0_rp, x0_ci, x0_row, src_h, src_h1[tc2::MAXD];
-  // iterate (double buffered)
+  // iterate: the pattern (rp, ci) is double buffered; the values are held in
+  // one buffer, xv[cur] (an update writes the new values over the old ones
+  // once its products have read them; the other slot is empty except during
+  // a precision switch)
   tc2::DBuf rp[2], ci[2], xv[2];
   int nnz[2] = {0, 0};
   int cur = 0;
@@ -181,9 +219,9 @@ struct tc2_ctx {
   long long log_cap = 0, log_n = 0;
   tc2::DBuf log_x, log_y, log_z, log_count;
   int update_index = 0;
-  // exact useful-flop count (count_useful): per-entry masks of the nonzero
-  // matrices of each iterate buffer, and per system x kernel kind the block
-  // triples of each product kind (X0 X0 and the response terms) on kept outputs
+  // per-entry masks of the nonzero matrices of each pattern buffer (see
+  // mask_iterate), and the exact useful-flop count (count_useful): per system
+  // x kernel kind, the useful block products on kept outputs
   int count_useful = 0;
   std::string metrics_log;        // JSONL file of per-update scalars ("" = none)
   int solve_index = 0;            // solves begun by this context
@@ -193,6 +231,7 @@ struct tc2_ctx {
   // tiled kernel, and a tiny stage that overflows every update
   int test_kl_chunk = 0;
   long long test_stage_cap = 0;
+  int test_no_zero_skip = 0;      // issue every product (masks not passed to the kernel)
   std::vector<int> h_active;      // host copy of the active flags
   // clusters
   int nc = 0, max_sys_clusters = 0;
@@ -224,7 +263,13 @@ inline size_t prec_bytes(int prec) { return prec == P_FP64 ? 8 : 4; }
 // iterate, then the block triples of the update on kept outputs into
 // ctx->useful_acc under the kernel kind of the update.
 tc2_status count_update(tc2_ctx* ctx, hipStream_t st);
-// Masks of the nonzero matrices of every entry of the current iterate.
+// Masks of the nonzero matrices of every entry of the current iterate (bit m
+// of mask[e] set when block m of entry e has a nonzero element).  The numeric
+// kernel issues no product with a zero operand block; the useful count uses
+// the masks of the old and the new iterate.
 tc2_status mask_iterate(tc2_ctx* ctx, hipStream_t st);
+// The same for nnz entries of xv (at most *nnz_dev when given), as stream work.
+void launch_block_masks(hipStream_t st, int prec, long long nnz, int D, const void* xv,
+                        unsigned char* mask, const int* nnz_dev);
 
 }  // namespace tc2

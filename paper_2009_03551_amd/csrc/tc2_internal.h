@@ -153,6 +153,8 @@ struct TileArgs {
   const int* n_tiles_dev; // nullptr, or the tile count on the device
   int skip;               // 0 none, 1 exact norm-bound screen, 2 bound + network
   const float* bn;        // block norms (nnz x (1+D)) when skip != 0 or logging
+  const unsigned char* xmask;  // per entry: bit m set when block m is nonzero (products of a
+                               // zero block are not issued); nullptr: every product issued
   unsigned long long* screened;  // outputs skipped by the exact screen
   const float* mlp;       // skip network parameters (MLP_NP), skip == 2
   float mlp_z;            // skip when the logit exceeds this (logit of the threshold)
@@ -194,7 +196,7 @@ struct TileArgs {
   int* overflow;
   int* bad;
   double* partial;        // n_tiles x NQ
-  unsigned long long* exec_pairs;
+  unsigned long long* exec_pairs;  // block products issued
 };
 
 // Rows of systems that stopped iterating: their upper blocks go to the stage
@@ -264,9 +266,11 @@ void launch_block_norms(hipStream_t st, int prec, long long nnz, int D, const vo
 void launch_compact_count(hipStream_t st, const CompactArgs& a, int n_kept);
 void launch_compact_scatter(hipStream_t st, const CompactArgs& a, int n_kept);
 void launch_row_sort(hipStream_t st, const CompactArgs& a);
-// nnz_dev (optional): the new entry count on the device, at most nnz
+// nnz_dev (optional): the new entry count on the device, at most nnz;
+// skip_flag (optional): nothing is written when *skip_flag is nonzero
 void launch_gather(hipStream_t st, int prec, int nnz, int D, const int* new_src,
-                   const void* stage, void* xv, const int* nnz_dev = nullptr);
+                   const void* stage, void* xv, const int* nnz_dev = nullptr,
+                   const int* skip_flag = nullptr);
 void launch_reduce(hipStream_t st, int nsys, const int* sys_item_lo, const int* sys_item_hi,
                    const double* partial, double* scal);
 void launch_sys_items(hipStream_t st, int nsys, int mult, const int* sys_start, const int* sys_end,

@@ -297,7 +297,7 @@ __global__ __launch_bounds__(256) void k_numeric(NumArgs a) {
         }
       }
     }
-    issued += npairs;
+    issued += (unsigned long long)npairs * (1 + 2 * D);  // block products
     const int pIJ = bsearch_eq(rowI, mI, J);
     epilogue<T, D>(E, acc, I, J, pIJ >= 0 ? r0 + pIJ : -1, square, eps, npairs, s, q);
   }
@@ -449,7 +449,10 @@ __global__ __launch_bounds__(256) void k_row_sort(CompactArgs a) {
 // C_IJ^T column-major, i.e. the stage as it is.
 template <typename T>
 __global__ void k_gather(long long n, int D, const int* new_src, const T* stage, T* xv,
-                         const int* nnz_dev) {
+                         const int* nnz_dev, const int* skip_flag) {
+  // an update whose stage overflowed is run again: its values must not be
+  // written over the iterate that the repeated products read
+  if (skip_flag && *skip_flag) return;
   // four consecutive elements per thread: one column segment (c, r..r+3) of a
   // column-major tile, a 4-vector store; the source is the same segment of
   // the stage (mirrored entry) or four rows of one column (transpose)
@@ -659,15 +662,15 @@ void launch_row_sort(hipStream_t st, const CompactArgs& a) {
 }
 
 void launch_gather(hipStream_t st, int prec, int nnz, int D, const int* new_src,
-                   const void* stage, void* xv, const int* nnz_dev) {
+                   const void* stage, void* xv, const int* nnz_dev, const int* skip_flag) {
   long long n = (long long)nnz * (1 + D) * BS;
   if (n == 0) return;
   if (prec == P_FP64)
     hipLaunchKernelGGL(k_gather<double>, dim3(sblk(n / 4, 256)), dim3(256), 0, st, n, D, new_src,
-                       (const double*)stage, (double*)xv, nnz_dev);
+                       (const double*)stage, (double*)xv, nnz_dev, skip_flag);
   else
     hipLaunchKernelGGL(k_gather<float>, dim3(sblk(n / 4, 256)), dim3(256), 0, st, n, D, new_src,
-                       (const float*)stage, (float*)xv, nnz_dev);
+                       (const float*)stage, (float*)xv, nnz_dev, skip_flag);
 }
 
 void launch_reduce(hipStream_t st, int nsys, const int* lo, const int* hi,

@@ -37,8 +37,9 @@ namespace {
 // nonzero element.  One wave per entry.
 template <typename T>
 __global__ void k_block_masks(long long nnz, int D, const T* __restrict__ xv,
-                              unsigned char* __restrict__ mask) {
+                              unsigned char* __restrict__ mask, const int* nnz_dev) {
   const int lane = threadIdx.x & 63;
+  if (nnz_dev) nnz = min(nnz, (long long)*nnz_dev);
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
   for (long long e = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < nnz; e += nwaves) {
     unsigned bits = 0u;
@@ -144,49 +145,92 @@ __global__ void k_gather_entries(long long n, int D, int m, int b, const long lo
 // per given entry.  The maximum of non-negative doubles is taken on their bit
 // patterns, which order the same way, so the result does not depend on the
 // order of the waves.
+// stats: [0] max over entries both sides hold, [1] max over entries only
+// the caller gave, [2] max over entries only the iterate holds (bit patterns
+// of non-negative doubles), [3] entries only the caller gave, [4] entries only
+// the iterate holds, [5] max Frobenius norm of a block held by one side only
 template <typename T>
 __global__ void k_compare_given(long long n, int D, int m, int b, const int* __restrict__ rows,
                                 const int* __restrict__ cols, const double* __restrict__ vals,
                                 const int* __restrict__ rp, const int* __restrict__ ci,
                                 const T* __restrict__ xv, unsigned char* found,
-                                unsigned long long* maxbits) {
+                                unsigned long long* stats) {
   const int lane = threadIdx.x & 63;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-  double mx = 0.0;
+  double mx_both = 0.0, mx_only = 0.0, nrm_only = 0.0;
+  unsigned long long n_only = 0;
   for (long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n; i += nwaves) {
     const int I = rows[i], J = cols[i];
     const int r0 = rp[I];
     const int q = bsearch_eq(ci + r0, rp[I + 1] - r0, J);
     const long long e = q >= 0 ? (long long)r0 + q : -1;
     if (e >= 0 && lane == 0) found[e] = 1;
+    double mx = 0.0, ss = 0.0;
     for (int rc = lane; rc < b * b; rc += 64) {
       const int r = rc / b, c = rc - r * b;
       const double x = e >= 0 ? (double)xv[((size_t)e * (1 + D) + m) * BS + c * BP + r] : 0.0;
-      mx = fmax(mx, fabs(vals[(size_t)i * b * b + rc] - x));
+      const double v = vals[(size_t)i * b * b + rc];
+      mx = fmax(mx, fabs(v - x));
+      ss += v * v;
+    }
+    if (e >= 0) {
+      mx_both = fmax(mx_both, mx);
+    } else {
+      ss = wave_sum(ss);
+      if (ss > 0.0) {
+        mx_only = fmax(mx_only, mx);
+        nrm_only = fmax(nrm_only, sqrt(ss));
+        n_only += 1;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mx_both = fmax(mx_both, __shfl_xor(mx_both, o, 64));
+    mx_only = fmax(mx_only, __shfl_xor(mx_only, o, 64));
+  }
+  if (lane == 0) {
+    if (mx_both > 0.0) atomicMax(&stats[0], (unsigned long long)__double_as_longlong(mx_both));
+    if (mx_only > 0.0) atomicMax(&stats[1], (unsigned long long)__double_as_longlong(mx_only));
+    if (nrm_only > 0.0) atomicMax(&stats[5], (unsigned long long)__double_as_longlong(nrm_only));
+    if (n_only) atomicAdd(&stats[3], n_only);
+  }
+}
+
+// Entries of the iterate that the caller did not give: their largest
+// |stored|, count (nonzero blocks only) and largest Frobenius norm.
+template <typename T>
+__global__ void k_compare_missing(long long nnz, int D, int m, const T* __restrict__ xv,
+                                  const unsigned char* __restrict__ found,
+                                  unsigned long long* stats) {
+  const int lane = threadIdx.x & 63;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+  double mx = 0.0, nrm = 0.0;
+  unsigned long long cnt = 0;
+  for (long long e = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < nnz; e += nwaves) {
+    if (found[e]) continue;
+    const T* x = xv + ((size_t)e * (1 + D) + m) * BS;
+    double bm = 0.0, ss = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double v = (double)x[lane + 64 * j];
+      bm = fmax(bm, fabs(v));
+      ss += v * v;
+    }
+    ss = wave_sum(ss);
+    if (ss > 0.0) {
+      mx = fmax(mx, bm);
+      nrm = fmax(nrm, sqrt(ss));
+      cnt += 1;
     }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-  if (lane == 0 && mx > 0.0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(mx));
-}
-
-// Entries of the iterate that the caller did not give: their largest |stored|.
-template <typename T>
-__global__ void k_compare_missing(long long nnz, int D, int m, const T* __restrict__ xv,
-                                  const unsigned char* __restrict__ found,
-                                  unsigned long long* maxbits) {
-  const int lane = threadIdx.x & 63;
-  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-  double mx = 0.0;
-  for (long long e = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < nnz; e += nwaves) {
-    if (found[e]) continue;
-    const T* x = xv + ((size_t)e * (1 + D) + m) * BS;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) mx = fmax(mx, fabs((double)x[lane + 64 * j]));
+  if (lane == 0) {
+    if (mx > 0.0) atomicMax(&stats[2], (unsigned long long)__double_as_longlong(mx));
+    if (nrm > 0.0) atomicMax(&stats[5], (unsigned long long)__double_as_longlong(nrm));
+    if (cnt) atomicAdd(&stats[4], cnt);
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-  if (lane == 0 && mx > 0.0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(mx));
 }
 
 // A device buffer of one call, freed on return.
@@ -204,25 +248,31 @@ struct Tmp {
 // ====================================================================== counting
 namespace tc2 {
 
+void launch_block_masks(hipStream_t st, int prec, long long nnz, int D, const void* xv,
+                        unsigned char* mask, const int* nnz_dev) {
+  if (nnz == 0) return;
+  const unsigned g = grid_waves(nnz, 4);
+  if (prec == P_FP64)
+    hipLaunchKernelGGL(k_block_masks<double>, dim3(g), dim3(256), 0, st, nnz, D,
+                       (const double*)xv, mask, nnz_dev);
+  else
+    hipLaunchKernelGGL(k_block_masks<float>, dim3(g), dim3(256), 0, st, nnz, D,
+                       (const float*)xv, mask, nnz_dev);
+}
+
 tc2_status mask_iterate(tc2_ctx* ctx, hipStream_t st) {
   const int c = ctx->cur;
   const long long nnz = ctx->nnz[c];
   HIPCHK(ctx->mask[c].reserve((size_t)std::max(nnz, 1LL)));
-  if (nnz == 0) return TC2_OK;
-  const unsigned g = grid_waves(nnz, 4);
-  if (ctx->cur_prec == P_FP64)
-    hipLaunchKernelGGL(k_block_masks<double>, dim3(g), dim3(256), 0, st, nnz, ctx->D,
-                       ctx->xv[c].as<double>(), ctx->mask[c].as<unsigned char>());
-  else
-    hipLaunchKernelGGL(k_block_masks<float>, dim3(g), dim3(256), 0, st, nnz, ctx->D,
-                       ctx->xv[c].as<float>(), ctx->mask[c].as<unsigned char>());
+  launch_block_masks(st, ctx->cur_prec, nnz, ctx->D, ctx->xv[c].p, ctx->mask[c].as<unsigned char>(),
+                     nullptr);
   HIPCHK(hipGetLastError());
   return TC2_OK;
 }
 
+// The masks of the new iterate were computed by the update itself.
 tc2_status count_update(tc2_ctx* ctx, hipStream_t st) {
   const int n = ctx->cur, o = n ^ 1;
-  if (tc2_status r = mask_iterate(ctx, st); r != TC2_OK) return r;
   UsefulArgs a{};
   a.nb = ctx->nb;
   a.D = ctx->D;
@@ -367,7 +417,8 @@ tc2_status export_entries_impl(tc2_ctx* ctx, int32_t matrix, int64_t first, int6
 }
 
 tc2_status compare_entries_impl(tc2_ctx* ctx, int32_t matrix, int64_t n, const int32_t* rows,
-                                const int32_t* cols, const double* vals, double* max_abs) {
+                                const int32_t* cols, const double* vals, double* max_abs,
+                                double* detail) {
   if (!ctx || !ctx->have_iterate || !max_abs || matrix < 0 || matrix > ctx->D || n < 0 ||
       (n > 0 && (!rows || !cols || !vals)))
     return TC2_EINVAL;
@@ -386,9 +437,9 @@ tc2_status compare_entries_impl(tc2_ctx* ctx, int32_t matrix, int64_t n, const i
   HIPCHK(drows.alloc((size_t)std::max<int64_t>(n, 1) * 4));
   HIPCHK(dcols.alloc((size_t)std::max<int64_t>(n, 1) * 4));
   HIPCHK(dfound.alloc((size_t)std::max(nnz, 1LL)));
-  HIPCHK(dmax.alloc(8));
+  HIPCHK(dmax.alloc(6 * 8));
   HIPCHK(hipMemsetAsync(dfound.p, 0, (size_t)std::max(nnz, 1LL), st));
-  HIPCHK(hipMemsetAsync(dmax.p, 0, 8, st));
+  HIPCHK(hipMemsetAsync(dmax.p, 0, 6 * 8, st));
   if (n) {
     HIPCHK(hipMemcpyAsync(drows.p, rows, (size_t)n * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(dcols.p, cols, (size_t)n * 4, hipMemcpyHostToDevice, st));
@@ -425,12 +476,17 @@ tc2_status compare_entries_impl(tc2_ctx* ctx, int32_t matrix, int64_t n, const i
                          dmax.as<unsigned long long>());
     HIPCHK(hipGetLastError());
   }
-  unsigned long long bits = 0;
-  HIPCHK(hipMemcpyAsync(&bits, dmax.p, 8, hipMemcpyDeviceToHost, st));
+  unsigned long long bits[6] = {0, 0, 0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(bits, dmax.p, 6 * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  double v;
-  memcpy(&v, &bits, 8);
-  *max_abs = v;
+  double v[6];
+  for (int k = 0; k < 6; ++k) {
+    if (k == 3 || k == 4) v[k] = (double)bits[k];
+    else memcpy(&v[k], &bits[k], 8);
+  }
+  *max_abs = std::max(v[0], std::max(v[1], v[2]));
+  if (detail)
+    for (int k = 0; k < 6; ++k) detail[k] = v[k];
   return TC2_OK;
 }
 
@@ -467,9 +523,10 @@ TC2_API tc2_status tc2_export_entries(tc2_ctx* ctx, int32_t matrix, int64_t firs
 }
 
 TC2_API tc2_status tc2_compare_entries(tc2_ctx* ctx, int32_t matrix, int64_t n, const int32_t* rows,
-                                       const int32_t* cols, const double* vals, double* max_abs) {
+                                       const int32_t* cols, const double* vals, double* max_abs,
+                                       double* detail) {
   try {
-    return compare_entries_impl(ctx, matrix, n, rows, cols, vals, max_abs);
+    return compare_entries_impl(ctx, matrix, n, rows, cols, vals, max_abs, detail);
   } catch (const std::bad_alloc&) {
     return TC2_ENOMEM;
   } catch (...) {

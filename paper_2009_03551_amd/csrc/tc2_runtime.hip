@@ -322,6 +322,7 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   if (ctx->tune) tune_load(ctx);
   if (const char* v = getenv("TC2_TEST_KL_CHUNK")) ctx->test_kl_chunk = std::max(0, atoi(v));
   if (const char* v = getenv("TC2_TEST_STAGE_CAP")) ctx->test_stage_cap = std::max(0LL, atoll(v));
+  if (const char* v = getenv("TC2_TEST_NO_ZERO_SKIP")) ctx->test_no_zero_skip = atoi(v) != 0;
   tc2_status st = TC2_OK;
   auto fail = [&](tc2_status s) {
     tc2_free(ctx);
@@ -535,6 +536,10 @@ tc2_status convert_iterate(tc2_ctx* ctx, hipStream_t st, int to_prec) {
   int c = ctx->cur;
   long long n = (long long)ctx->nnz[c] * (1 + ctx->D) * BS;
   DBuf& dst = ctx->xv[c ^ 1];
+  // the stage is sized in the old precision and reserved again by the next
+  // update: release it first, so that both copies of the values fit
+  HIPCHK(hipStreamSynchronize(st));
+  ctx->stage.release();
   HIPCHK(dst.reserve((size_t)n * prec_bytes(to_prec)));
   launch_convert(st, ctx->cur_prec, to_prec, n, ctx->xv[c].p, dst.p);
   // move the pattern along
@@ -545,7 +550,10 @@ tc2_status convert_iterate(tc2_ctx* ctx, hipStream_t st, int to_prec) {
   ctx->nnz[c ^ 1] = ctx->nnz[c];
   ctx->cur = c ^ 1;
   ctx->cur_prec = to_prec;
-  return TC2_OK;
+  // the values in the old precision are no longer needed
+  HIPCHK(hipStreamSynchronize(st));
+  ctx->xv[c].release();
+  return mask_iterate(ctx, st);
 }
 
 // Scalars of the current iterate into host memory (nsys x NQ).
@@ -780,6 +788,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     ta.bf16 = (ctx->op_bf16 && ctx->cur_prec == P_FP32) ? 1 : 0;
     ta.wide = wide_now;
     ta.skip = ctx->skip_now;
+    ta.xmask = ctx->test_no_zero_skip ? nullptr : ctx->mask[c].as<unsigned char>();
     ta.bn = screen ? ctx->bn.as<float>() : nullptr;
     ta.screened = screen ? ctx->screened.as<unsigned long long>() : nullptr;
     ta.mlp_skipped = screen ? ctx->screened.as<unsigned long long>() + 1 : nullptr;
@@ -998,16 +1007,21 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   HIPCHK(ctx->tmp_src.reserve((size_t)std::max(nnz_new, 1) * 4));
   HIPCHK(ctx->new_src.reserve((size_t)std::max(nnz_new, 1) * 4));
   HIPCHK(ctx->ci[n].reserve((size_t)std::max(nnz_new, 1) * 4));
-  HIPCHK(ctx->xv[n].reserve((size_t)std::max(nnz_new, 1) * tile));
+  // the products and the copy-through have read the old values (the stream
+  // was synchronised above): the new values go into the same buffer
+  ctx->xv[n].release();
+  HIPCHK(ctx->xv[c].reserve_grow((size_t)std::max(nnz_new, 1) * tile));
   ca.tmp_ci = ctx->tmp_ci.as<int>();
   ca.tmp_src = ctx->tmp_src.as<int>();
   ca.new_ci = ctx->ci[n].as<int>();
   ca.new_src = ctx->new_src.as<int>();
   launch_compact_scatter(st, ca, n_kept);
   launch_row_sort(st, ca);
-  launch_gather(st, ctx->cur_prec, nnz_new, D, ctx->new_src.as<int>(), ctx->stage.p, ctx->xv[n].p);
+  launch_gather(st, ctx->cur_prec, nnz_new, D, ctx->new_src.as<int>(), ctx->stage.p, ctx->xv[c].p);
+  ctx->xv[c].swap(ctx->xv[n]);
   ctx->nnz[n] = nnz_new;
   ctx->cur = n;
+  if (tc2_status r = mask_iterate(ctx, st); r != TC2_OK) return r;
   if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[1], st));
 
   // ---- per-system scalars of the new iterate
@@ -1047,7 +1061,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     if (e_ == hipErrorOutOfMemory) {                                     \
       (void)hipGetLastError();                                           \
       for (DBuf* b_ : {&ctx->stage, &ctx->kept_ij, &ctx->tmp_ci, &ctx->tmp_src, \
-                       &ctx->new_src, &ctx->ci[n], &ctx->xv[n]})           \
+                       &ctx->new_src, &ctx->ci[n]})                        \
         b_->release();                                                   \
       return 1;                                                          \
     }                                                                    \
@@ -1069,7 +1083,6 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   ctx->kind_used[kind] = true;
   ctx->last_kind = kind;
   const long long nnz_c = ctx->nnz[c];
-  const long long cap_c = std::max<long long>((long long)(ctx->xv[c].cap / tile), 1);
 
   // kept-block estimate: the last count grown by the last growth factor
   long long est;
@@ -1111,10 +1124,6 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     GRESERVE(ctx->partial.reserve((size_t)std::max(ctx->tile_bound * 4, (long long)nb) * NQ * 8));
     GRESERVE(ctx->sys_lo.reserve((size_t)ctx->nsys * 4));
     GRESERVE(ctx->sys_hi.reserve((size_t)ctx->nsys * 4));
-    if (screen) {
-      GRESERVE(ctx->bn.reserve((size_t)cap_c * (1 + D) * 4));
-      GRESERVE(ctx->screened.reserve(16));
-    }
     GRESERVE(ctx->stage.reserve((size_t)cap * tile));
     GRESERVE(ctx->kept_ij.reserve((size_t)cap * 8));
     GRESERVE(ctx->rowcnt.reserve((size_t)nb * 4));
@@ -1125,7 +1134,18 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     GRESERVE(ctx->tmp_src.reserve(cap2 * 4));
     GRESERVE(ctx->new_src.reserve(cap2 * 4));
     GRESERVE(ctx->ci[n].reserve(cap2 * 4));
-    GRESERVE(ctx->xv[n].reserve(cap2 * tile));
+    GRESERVE(ctx->mask[n].reserve(cap2));
+    // one value buffer holds the current values and receives the new ones:
+    // it grows, keeping the current values, to the larger of the two
+    ctx->xv[n].release();
+    GRESERVE(ctx->xv[c].grow_keep(std::max<size_t>(cap2, (size_t)nnz_c) * tile, (size_t)nnz_c * tile, st));
+    // entries the value buffer can hold: a bound of the current entries for
+    // the kernels that read their count from the device
+    const long long cap_c = std::max<long long>((long long)(ctx->xv[c].cap / tile), 1);
+    if (screen) {
+      GRESERVE(ctx->bn.reserve((size_t)cap_c * (1 + D) * 4));
+      GRESERVE(ctx->screened.reserve(16));
+    }
     GRESERVE(ctx->scal.reserve((size_t)ctx->nsys * NQ * 8));
     GRESERVE(ctx->pin_graph.reserve(64 + (size_t)ctx->nsys * NQ * 8));
     int* cnt = ctx->counters.as<int>();  // [1] stage count [2] overflow [4] work counter
@@ -1136,7 +1156,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
         (unsigned long long)any_stopped, (unsigned long long)cap, (unsigned long long)cap_c,
         (unsigned long long)ctx->profile, (unsigned long long)(uintptr_t)st,
         (uintptr_t)ctx->xv[c].p, (uintptr_t)ctx->rp[c].p, (uintptr_t)ctx->ci[c].p,
-        (uintptr_t)ctx->xv[n].p, (uintptr_t)ctx->rp[n].p, (uintptr_t)ctx->ci[n].p,
+        (uintptr_t)ctx->rp[n].p, (uintptr_t)ctx->ci[n].p,
         (uintptr_t)ctx->panel_k.p, (uintptr_t)ctx->panel_e.p, (uintptr_t)ctx->tile_p.p,
         (uintptr_t)ctx->tile_q.p, (uintptr_t)ctx->partial.p, (uintptr_t)ctx->bn.p,
         (uintptr_t)ctx->stage.p, (uintptr_t)ctx->kept_ij.p, (uintptr_t)ctx->tmp_ci.p,
@@ -1145,7 +1165,8 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
         (uintptr_t)ctx->rowcnt.p, (uintptr_t)ctx->cursor.p, (uintptr_t)ctx->sys_lo.p,
         (uintptr_t)ctx->sys_hi.p, (uintptr_t)ctx->panel_cnt.p, (uintptr_t)ctx->panel_rp.p,
         (uintptr_t)ctx->tile_cnt.p, (uintptr_t)ctx->tile_rp.p, (uintptr_t)ctx->tile_pairs.p,
-        (uintptr_t)ctx->tile_bits.p, (uintptr_t)ctx->nominal.p};
+        (uintptr_t)ctx->tile_bits.p, (uintptr_t)ctx->nominal.p, (uintptr_t)ctx->mask[c].p,
+        (uintptr_t)ctx->mask[n].p};
     // the three parts of the update, as stream work (captured or not)
     auto rec_pre = [&]() {
       (void)count_nominal(ctx, st, ctx->rp[c].as<int>());
@@ -1229,6 +1250,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       ta.wide = kind == K_WIDE ? 1 : 0;
       ta.shape = shape;
       ta.skip = ctx->skip_now;
+      ta.xmask = ctx->test_no_zero_skip ? nullptr : ctx->mask[c].as<unsigned char>();
       ta.bn = screen ? ctx->bn.as<float>() : nullptr;
       ta.screened = screen ? ctx->screened.as<unsigned long long>() : nullptr;
       ta.mlp_skipped = screen ? ctx->screened.as<unsigned long long>() + 1 : nullptr;
@@ -1274,8 +1296,12 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       launch_scan(st, nb, ctx->rowcnt.as<int>(), ctx->rp[n].as<int>(), cnt);
       launch_compact_scatter(st, cm, cap);
       launch_row_sort(st, cm);
+      // the gather writes over the current values: skipped when the stage
+      // overflowed (the update is then run again from those values)
       launch_gather(st, ctx->cur_prec, (int)cap2, D, ctx->new_src.as<int>(), ctx->stage.p,
-                    ctx->xv[n].p, ctx->rp[n].as<int>() + nb);
+                    ctx->xv[c].p, ctx->rp[n].as<int>() + nb, cnt + 2);
+      launch_block_masks(st, ctx->cur_prec, (long long)cap2, D, ctx->xv[c].p,
+                         ctx->mask[n].as<unsigned char>(), ctx->rp[n].as<int>() + nb);
       launch_reduce(st, ctx->nsys, ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>(),
                     ctx->partial.as<double>(), ctx->scal.as<double>());
     };
@@ -1377,6 +1403,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   ctx->kept_prev2 = ctx->kept_prev;
   ctx->kept_prev = hcnt[1];
   ctx->stage_cap = std::max<long long>(ctx->stage_cap, (long long)hcnt[1] * 5 / 4 + 1024);
+  ctx->xv[c].swap(ctx->xv[n]);
   ctx->nnz[n] = nnz_new;
   ctx->cur = n;
   ctx->graph_updates++;
@@ -1510,6 +1537,9 @@ tc2_status begin_solve(tc2_ctx* ctx, hipStream_t st) {
   ctx->nnz[0] = ctx->nnz0;
   ctx->stage_cap = 0;
   const size_t tile = (size_t)(1 + D) * BS * prec_bytes(start_prec);
+  // the value buffer of the last solve (in either slot) is kept for this one
+  if (ctx->xv[1].cap > ctx->xv[0].cap) ctx->xv[0].swap(ctx->xv[1]);
+  ctx->xv[1].release();
   HIPCHK(ctx->rp[0].reserve((size_t)(nb + 1) * 4));
   HIPCHK(ctx->ci[0].reserve((size_t)std::max(ctx->nnz0, 1) * 4));
   HIPCHK(ctx->xv[0].reserve((size_t)std::max(ctx->nnz0, 1) * tile));
@@ -1533,10 +1563,8 @@ tc2_status begin_solve(tc2_ctx* ctx, hipStream_t st) {
     energies(&R.scal[(size_t)s * NQ], D, R.ss[s].prev);
     R.branch[s] = R.scal[(size_t)s * NQ + Q_TR0] >= (double)ctx->sys[s].n_occ ? 1 : 0;
   }
-  if (ctx->count_useful) {
-    st0 = mask_iterate(ctx, st);
-    if (st0 != TC2_OK) return st0;
-  }
+  st0 = mask_iterate(ctx, st);
+  if (st0 != TC2_OK) return st0;
   // stages of a reduced-precision solve: [FP64 x fp64_first] -> [BF16] -> FP32
   // -> closing FP64 pair; each reduced stage runs to its own stopping test.
   R.reduced = ctx->prec != P_FP64;
@@ -1615,7 +1643,6 @@ tc2_status advance_one(tc2_ctx* ctx, bool* done) {
       // closing pair in FP64: trace rule, then the opposite branch
       tc2_status cs = convert_iterate(ctx, st, P_FP64);
       if (cs != TC2_OK) return cs;
-      if (ctx->count_useful && (cs = mask_iterate(ctx, st)) != TC2_OK) return cs;
       R.phase = 1;
       for (int s = 0; s < nsys; ++s)
         if (R.mode[s] == 0 && ss[s].status >= 0) {
@@ -1663,7 +1690,6 @@ tc2_status advance_one(tc2_ctx* ctx, bool* done) {
   if (R.reduced && R.phase == 0 && ctx->cur_prec == P_FP64 && R.updates >= ctx->fp64_first) {
     r = convert_iterate(ctx, st, P_FP32);
     if (r != TC2_OK) return r;
-    if (ctx->count_useful && (r = mask_iterate(ctx, st)) != TC2_OK) return r;
   }
   HIPCHK(hipMemcpyAsync(pin + (size_t)nsys * 8, ctx->bad.p, nsys * 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(pin + R.pin_nominal, ctx->nominal.p, nsys * 8, hipMemcpyDeviceToHost, st));
@@ -1810,7 +1836,7 @@ tc2_status finish_solve(tc2_ctx* ctx, tc2_result* res) {
     Rs.seconds = ms * 1e-3;
     Rs.union_flops = S.trip * b3 * (1 + 2 * D);
     Rs.nominal_flops = S.nominal * b3 * (1 + 2 * D);
-    Rs.executed_flops = (s == 0) ? (double)R.exec_pairs * (1 + 2 * D) * 2.0 * BP * BP * kst : 0.0;
+    Rs.executed_flops = (s == 0) ? (double)R.exec_pairs * 2.0 * BP * BP * kst : 0.0;
     strncpy(Rs.branches, S.branches.c_str(), TC2_MAX_ITER + 3);
     Rs.ms_symbolic = ctx->ms_sym;
     Rs.ms_numeric = ctx->ms_num;
@@ -1890,7 +1916,7 @@ tc2_status advance_impl(tc2_ctx* ctx, void* stream, int32_t max_updates, tc2_pro
     double u = 0.0;
     if (tc2_status s0 = useful_total(&u); s0 != TC2_OK) return s0;
     prog->useful_flops += u - u0;
-    prog->executed_flops += (double)(R.exec_pairs - p0) * (1 + 2 * ctx->D) * 2.0 * BP * BP * kst;
+    prog->executed_flops += (double)(R.exec_pairs - p0) * 2.0 * BP * BP * kst;
     return TC2_OK;
   };
   tc2_status r;

@@ -308,6 +308,11 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
     }
     return e;
   };
+  // Masks of the nonzero matrices of the entries eg (lane-distributed as the
+  // entries); all bits set when no masks are given
+  auto load_masks = [&](int eg) {
+    return eg < 0 ? 0 : (a.xmask ? (int)a.xmask[eg] : 0xff);
+  };
   // Copy the blocks of a column group (entries eg, as load_entries) into
   // buffer bb.  A block that meets no present partner of a computed output in
   // its column is not copied (marked absent): no product needs it.
@@ -581,23 +586,42 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
   __syncthreads();
 
   // Products of one column block K (buffer bb, slot gi) for the present
-  // outputs pm (K-steps of 4 up to the block size).
-  auto column = [&](unsigned pm, int bb, int gi) {
+  // outputs pm (K-steps of 4 up to the block size).  mk holds, lane gi*NE + x,
+  // the mask of the nonzero matrices of block x of the column: a product with
+  // a zero operand block is not issued (it would add exact zeros).
+  unsigned long long nprod = 0;  // block products issued by this wave
+  auto column = [&](unsigned pm, int bb, int gi, int mk) {
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
       if (!((pm >> o) & 1u)) continue;
+      const unsigned ma = (unsigned)__builtin_amdgcn_readlane(mk, gi * NE + so[o]);
+      const unsigned mb = (unsigned)__builtin_amdgcn_readlane(mk, gi * NE + SP + to[o]);
+      // enabled products: bit 0 X0 X0; bit 1 + d X0 X1_d; bit 1 + MAXD + d X1_d X0
+      unsigned en = ma & mb & 1u;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        en |= ((ma & (mb >> (1 + d))) & 1u) << (1 + d);
+        en |= (((ma >> (1 + d)) & mb) & 1u) << (1 + MAXD + d);
+      }
+      en = __builtin_amdgcn_readfirstlane(en);
+      if (!en) continue;
+      nprod += __popc(en);
       const T* xa = &buf[bb][gi][so[o]][0];
       const T* xb = &buf[bb][gi][SP + to[o]][0];
       if constexpr (BF) {
         // bfloat16 operands: one 16x16x16 MFMA per block product
         const s4 a0 = bf16_frag((const float*)xa, lane), b0 = bf16_frag((const float*)xb, lane);
-        mfma_bf16(acc[o][0], a0, b0);
+        if (en & 1u) mfma_bf16(acc[o][0], a0, b0);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          const s4 a1 = bf16_frag((const float*)xa + (1 + d) * BS, lane);
-          const s4 b1 = bf16_frag((const float*)xb + (1 + d) * BS, lane);
-          mfma_bf16(acc[o][1 + d], a0, b1);
-          mfma_bf16(acc[o][1 + d], a1, b0);
+          if ((en >> (1 + d)) & 1u) {
+            const s4 b1 = bf16_frag((const float*)xb + (1 + d) * BS, lane);
+            mfma_bf16(acc[o][1 + d], a0, b1);
+          }
+          if ((en >> (1 + MAXD + d)) & 1u) {
+            const s4 a1 = bf16_frag((const float*)xa + (1 + d) * BS, lane);
+            mfma_bf16(acc[o][1 + d], a1, b0);
+          }
         }
       } else {
         // W: this column's FP32 products go to temporaries, then to the FP64 sums
@@ -613,19 +637,24 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
         for (int kk = 0; kk < 4; ++kk) {
           if (!FK && kk >= a.ksteps) break;
           const T a0 = xa[lane + kk * 64], b0 = xb[lane + kk * 64];
-          mfma(dst[0], a0, b0);
+          if (en & 1u) mfma(dst[0], a0, b0);
 #pragma unroll
           for (int d = 0; d < D; ++d) {
-            const T a1 = xa[(1 + d) * BS + lane + kk * 64], b1 = xb[(1 + d) * BS + lane + kk * 64];
-            mfma(dst[1 + d], a0, b1);
-            mfma(dst[1 + d], a1, b0);
+            if ((en >> (1 + d)) & 1u) mfma(dst[1 + d], a0, xb[(1 + d) * BS + lane + kk * 64]);
+            if ((en >> (1 + MAXD + d)) & 1u) mfma(dst[1 + d], xa[(1 + d) * BS + lane + kk * 64], b0);
           }
         }
         if constexpr (W) {
+          if (en & 1u) {
 #pragma unroll
-          for (int m = 0; m <= D; ++m)
+            for (int r = 0; r < 4; ++r) wacc[o][0].v[r] += (double)tmp[0].v[r];
+          }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) wacc[o][m].v[r] += (double)tmp[m].v[r];
+          for (int d = 0; d < D; ++d)
+            if ((en >> (1 + d)) & ((1u << MAXD) | 1u)) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) wacc[o][1 + d].v[r] += (double)tmp[1 + d].v[r];
+            }
         }
       }
     }
@@ -637,9 +666,11 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
     const int nm = build_kl(base, end, true);
     // ---- pipelined products over the common columns
     const int ngroups = (nm + KG - 1) / KG;
-    int e_next = 0;
+    int e_next = 0, m_cur = 0, m_next = 0;
     if (ngroups > 0) {
-      issue(load_entries(0, nm), 0);
+      const int e0 = load_entries(0, nm);
+      issue(e0, 0);
+      m_cur = load_masks(e0);
       e_next = load_entries(1, nm);
     }
     for (int g = 0; g < ngroups; ++g) {
@@ -648,6 +679,7 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
       __syncthreads();
       if (g + 1 < ngroups) {
         issue(e_next, bb ^ 1);
+        m_next = load_masks(e_next);
         e_next = load_entries(g + 2, nm);
       }
       if (any_owned) {
@@ -664,9 +696,10 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
           pm = __builtin_amdgcn_readfirstlane(pm & own_mask);
 #pragma unroll
           for (int o = 0; o < NO; ++o) np[o] += (int)((pm >> o) & 1u);
-          column(pm, bb, gi);
+          column(pm, bb, gi, m_cur);
         }
       }
+      m_cur = m_next;
     }
     __syncthreads();
   }
@@ -678,7 +711,6 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
   double q[NQ];
 #pragma unroll
   for (int k = 0; k < NQ; ++k) q[k] = 0.0;
-  unsigned long long issued = 0;
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
     const int eIJ = __builtin_amdgcn_readlane(my_e, o);
@@ -686,7 +718,6 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
     if (!owned[o]) continue;
     bool kept = false;
     if (np[o] > 0) {
-      issued += np[o];
       if constexpr (W)
         kept = epilogue<T, D, AccW>(E, wacc[o], Io[o], Jo[o], eIJ, square, eps, np[o], sys, q);
       else
@@ -697,7 +728,7 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < NQ; ++k) spart[wave][k] = q[k];
-    if (issued) atomicAdd(a.exec_pairs, issued);
+    if (nprod) atomicAdd(a.exec_pairs, nprod);
   }
   __syncthreads();
   if (t < NQ) {

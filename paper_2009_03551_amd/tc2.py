@@ -397,25 +397,32 @@ class Solver:
             raise TC2Error(st, "tc2_export_entries")
         return rows[:count], cols[:count], (vals[:count] if values else None)
 
-    def compare_entries(self, matrix: int, rows, cols, vals) -> float:
+    def compare_entries(self, matrix: int, rows, cols, vals, detail: bool = False):
         """max |A - B| over the union of the patterns of the caller's entries A
-        and matrix ``matrix`` of the current iterate B (tc2_compare_entries)."""
+        and matrix ``matrix`` of the current iterate B (tc2_compare_entries);
+        with ``detail``, also a dict separating blocks both hold from blocks
+        one side holds."""
         rows = np.ascontiguousarray(rows, dtype=np.int32)
         cols = np.ascontiguousarray(cols, dtype=np.int32)
         vals = np.ascontiguousarray(vals, dtype=np.float64)
         out = C.c_double()
+        det = (C.c_double * 6)()
         L = lib()
         L.tc2_compare_entries.restype = C.c_int
         L.tc2_compare_entries.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_int32),
                                           C.POINTER(C.c_int32), C.POINTER(C.c_double),
-                                          C.POINTER(C.c_double)]
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]
         st = L.tc2_compare_entries(self._ctx, int(matrix), len(rows),
                                    rows.ctypes.data_as(C.POINTER(C.c_int32)),
                                    cols.ctypes.data_as(C.POINTER(C.c_int32)),
-                                   vals.ctypes.data_as(C.POINTER(C.c_double)), C.byref(out))
+                                   vals.ctypes.data_as(C.POINTER(C.c_double)), C.byref(out), det)
         if st != 0:
             raise TC2Error(st, "tc2_compare_entries")
-        return float(out.value)
+        if not detail:
+            return float(out.value)
+        return float(out.value), dict(max_both=det[0], max_given_only=det[1],
+                                      max_iterate_only=det[2], n_given_only=int(det[3]),
+                                      n_iterate_only=int(det[4]), max_norm_one_side=det[5])
 
     def log(self, logits: bool = False):
         """(features n x 8, labels n) logged by the last run (1 = dropped,

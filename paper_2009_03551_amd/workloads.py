@@ -22,6 +22,8 @@ Random numbers come from ``numpy.random.default_rng(seed)`` (PCG64).
 """
 from __future__ import annotations
 
+import json
+import os
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -206,23 +208,22 @@ def make_displacement(system: System, atom: int, amp_s: float = 0.05, amp_h: flo
     return only(_assemble(nb, b, pairs, h_off, h_diag)), only(_assemble(nb, b, pairs, s_off, s_diag))
 
 
-# Named workloads.  Readings of what the paper leaves open (lattice spacing,
-# occupation for b = 13, tolerances) are fixed here and listed in the design
-# notes.
-CONFIGS = {
-    # 64-atom chain, b = 8, N = 512, one direction
-    "chain64": dict(kind="chain", n=64, spacing=1.0, b=8, occ=4, cutoff=4.0,
-                    n_dir=1, eps=1e-7, tol=1e-9, seed=1),
-    # 10^3 cube, b = 13, N = 13000, one direction
-    "cube10": dict(kind="cube", L=10, spacing=2.5, b=13, occ=4, cutoff=3.0,
-                   n_dir=1, eps=1e-6, tol=1e-9, seed=2),
-    # 20^3 cube, N = 104000, three directions
-    "cube20": dict(kind="cube", L=20, spacing=2.5, b=13, occ=4, cutoff=3.0,
-                   n_dir=3, eps=1e-6, tol=1e-9, seed=3),
-    # 30^3 cube, N = 351000, three directions
-    "cube30": dict(kind="cube", L=30, spacing=2.5, b=13, occ=4, cutoff=3.0,
-                   n_dir=3, eps=1e-5, tol=1e-9, seed=5),
-}
+# Named workloads: one JSON file each under configs/, holding the recipe
+# parameters and the readings of what the paper leaves open for that workload
+# (lattice spacing, occupation for b = 13, tolerances, batch geometry).
+_CONFIG_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
+
+
+def _load_configs() -> dict:
+    out = {}
+    for f in sorted(os.listdir(_CONFIG_DIR)):
+        if f.endswith(".json"):
+            with open(os.path.join(_CONFIG_DIR, f)) as fh:
+                out[f[:-5]] = json.load(fh)
+    return out
+
+
+CONFIGS = _load_configs()
 
 
 def config_system(name: str, **override) -> System:
@@ -231,8 +232,10 @@ def config_system(name: str, **override) -> System:
     c.update(override)
     if c["kind"] == "chain":
         xyz = chain_positions(c["n"], c["spacing"])
-    else:
+    elif c["kind"] == "cube":
         xyz = cubic_positions(c["L"], c["spacing"], c.get("n_first"))
+    else:
+        raise ValueError(f"{name} is a batch: use batch_systems()")
     return make_system(xyz, c["b"], c["occ"], c["cutoff"], c["seed"],
                        n_dir=c["n_dir"], eps=c["eps"], tol=c["tol"],
                        name=name)
@@ -256,13 +259,26 @@ def pack_units(systems: Sequence[System], max_atoms: int) -> List[List[System]]:
     return units
 
 
-def batch_systems(n_sys: int = 32, lo: int = 200, hi: int = 4000, seed: int = 4,
-                  b: int = 13, n_dir: int = 3, eps: float = 1e-6,
-                  tol: float = 1e-9, spacing: float = 2.5,
+def batch_systems(n_sys: Optional[int] = None, lo: Optional[int] = None,
+                  hi: Optional[int] = None, seed: Optional[int] = None,
+                  b: Optional[int] = None, n_dir: Optional[int] = None,
+                  eps: Optional[float] = None, tol: Optional[float] = None,
+                  spacing: Optional[float] = None,
                   sizes: Optional[Sequence[int]] = None) -> List[System]:
-    """Independent systems of uneven size: n_k atoms drawn uniformly in
-    [lo, hi]; system k is the first n_k sites (row-major) of the smallest
-    cube holding them, with its own seed 1000*seed + k."""
+    """Independent systems of uneven size (defaults: configs/batch32.json):
+    n_k atoms drawn uniformly in [lo, hi]; system k is the first n_k sites
+    (row-major) of the smallest cube holding them, with its own seed
+    1000*seed + k."""
+    c = CONFIGS["batch32"]
+    n_sys = c["n_sys"] if n_sys is None else n_sys
+    lo = c["lo"] if lo is None else lo
+    hi = c["hi"] if hi is None else hi
+    seed = c["size_seed"] if seed is None else seed
+    b = c["b"] if b is None else b
+    n_dir = c["n_dir"] if n_dir is None else n_dir
+    eps = c["eps"] if eps is None else eps
+    tol = c["tol"] if tol is None else tol
+    spacing = c["spacing"] if spacing is None else spacing
     if sizes is None:
         sizes = np.random.default_rng(seed).integers(lo, hi + 1, n_sys)
     out = []
@@ -272,6 +288,6 @@ def batch_systems(n_sys: int = 32, lo: int = 200, hi: int = 4000, seed: int = 4,
         while L ** 3 < n:
             L += 1
         xyz = cubic_positions(L, spacing, n_first=n)
-        out.append(make_system(xyz, b, 4, 3.0, 1000 * seed + k, n_dir=n_dir,
+        out.append(make_system(xyz, b, c["occ"], c["cutoff"], 1000 * seed + k, n_dir=n_dir,
                                eps=eps, tol=tol, name=f"batch{k}"))
     return out

@@ -92,6 +92,86 @@ def test_cube10_fp32_wide_meets_gate():
     assert dx1 < 1e-6 and dal < 1e-6
 
 
+def golden_rows(name):
+    z = np.load(os.path.join(HERE, "golden", f"{name}_rows.npz"))
+    return {int(I): (z[f"cols_{I}"], z[f"vals_{I}"]) for I in z["rows"]}
+
+
+def rows_maxdiff(sv, rows):
+    """Largest difference between the solver's current rows and the stored
+    complete rows of the oracle (blocks missing on one side count as zero),
+    and whether the block patterns agree."""
+    x0, x1 = sv.export_rows(0, list(rows))
+    worst, same = 0.0, True
+    for I, (cols, vals) in rows.items():
+        a0, a1 = int(x0.row_ptr[I]), int(x0.row_ptr[I + 1])
+        gcols = x0.col[a0:a1]
+        same = same and np.array_equal(gcols, cols)
+        for m, X in enumerate([x0] + x1):
+            g = dict(zip(gcols.tolist(), X.val[a0:a1]))
+            o = dict(zip(cols.tolist(), vals[:, m]))
+            for J in set(g) | set(o):
+                d = np.abs(g.get(J, 0.0) - o.get(J, 0.0)).max()
+                worst = max(worst, float(d))
+    return worst, same
+
+
+def test_cube10_plain_fp64_history_and_rows(tmp_path):
+    # every update's scalars (Tr X0, E0, Tr(X1 H), alpha, iota) against the
+    # oracle's history, and complete block rows (corner, edge, centre) of the
+    # final X0 and X1
+    g0 = golden("cube10")
+    rows = golden_rows("cube10")
+    s = W.config_system("cube10")
+    path = str(tmp_path / "m.jsonl")
+    sv = T.Solver(s, precision="fp64", graph=True, export=False, metrics_log=path)
+    try:
+        r = sv.run()[0]
+        worst, same = rows_maxdiff(sv, rows)
+    finally:
+        sv.close()
+    lines = [json.loads(x) for x in open(path)]
+    assert r.branches == g0["branches"] and len(lines) == len(g0["history"])
+    for x, h in zip(lines, g0["history"]):
+        assert x["branch"] == h["branch"]
+        assert x["tr_x0"] == pytest.approx(h["tr"], rel=1e-12)
+        assert x["e0"] == pytest.approx(h["E0"], rel=1e-11)
+        assert x["e1"][0] == pytest.approx(h["E1"][0], rel=1e-8, abs=1e-9)
+        assert x["alpha"][0] == pytest.approx(h["alpha"][0], rel=1e-11)
+        assert x["iota"] == pytest.approx(h["iota"], rel=1e-9, abs=1e-9)
+    print(f"  plain FP64: {len(lines)} updates match; complete rows {sorted(rows)}: "
+          f"max diff {worst:.2e}, patterns equal {same}", flush=True)
+    assert same and worst < 1e-9
+
+
+def test_cube10_benchmarked_variant_against_the_oracle(tmp_path):
+    # the variant the benchmark times (FP32 products with FP64 sums, four
+    # leading FP64 updates with their scalars equal to the oracle's, exact
+    # screen, update graphs, closing FP64 pair), on the stored complete rows
+    # and alpha, at the gate
+    g0 = golden("cube10")
+    rows = golden_rows("cube10")
+    s = W.config_system("cube10")
+    path = str(tmp_path / "m.jsonl")
+    sv = T.Solver(s, precision="fp32", wide=True, fp64_first=4, closing_fp64=2, skip="bound",
+                  graph=True, export=False, metrics_log=path)
+    try:
+        r = sv.run()[0]
+        worst, same = rows_maxdiff(sv, rows)
+    finally:
+        sv.close()
+    lines = [json.loads(x) for x in open(path)]
+    for x, h in zip(lines[:4], g0["history"][:4]):
+        assert x["kind"] == "fp64" and x["branch"] == h["branch"]
+        assert x["e0"] == pytest.approx(h["E0"], rel=1e-11)
+        assert x["alpha"][0] == pytest.approx(h["alpha"][0], rel=1e-11)
+    dal = abs(r.alpha[0] - g0["alpha"][0]) / abs(g0["alpha"][0])
+    print(f"  benchmarked variant: {r.branches} ({r.graph_updates} graph updates); complete rows: "
+          f"max|dX| {worst:.2e}, patterns equal {same}; rel|dalpha| {dal:.2e}", flush=True)
+    assert r.graph_updates > 0
+    assert worst < 1e-6 and dal < 1e-6
+
+
 def test_cube20_invariants_three_directions():
     s = W.config_system("cube20")
     r = T.solve(s, export=False, skip="bound")[0]

@@ -96,3 +96,15 @@ def test_graph_edge_cases(case):
         systems, kw = [a, W.config_system("chain64", n=17), W.config_system("chain64", n=30)], {}
     ref, got = both(systems, **kw)
     assert any(g.graph_updates > 0 for g in got) or all(r.iters == 0 for r in ref)
+
+
+def test_graph_is_replayed_once_the_pattern_settles():
+    # the capacity in the graph key is rounded up to geometric buckets, so the
+    # updates after the pattern stops growing replay a captured graph
+    s = W.config_system("cube10", L=6, n_dir=1)
+    g = T.solve(s, precision="fp32", wide=True, fp64_first=4, closing_fp64=2, skip="bound",
+                graph=True)[0]
+    print(f"  {g.iters} updates, {g.graph_updates} as graphs, {g.graph_captures} captures",
+          flush=True)
+    assert g.graph_updates >= g.iters - 2            # the closing pair runs without graphs
+    assert 0 < g.graph_captures < g.graph_updates

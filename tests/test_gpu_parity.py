@@ -236,7 +236,7 @@ def test_nominal_flops_count_full_product_triples(kernel):
     # products on each update's input pattern, i.e. the sum over rows K of
     # m_K^2 for the union block pattern of X0 and X1 (an integer count, exact)
     s = W.config_system("cube10", L=4)
-    g = T.solve(s, kernel=kernel)[0]
+    g = T.solve(s, kernel=kernel, count_useful=True)[0]
     b, D = s.H.b, len(s.H1)
     H = O.bsr_to_dense(s.H.nb, b, s.H.row_ptr, s.H.col, s.H.val)
     H1 = [O.bsr_to_dense(m.nb, b, m.row_ptr, m.col, m.val) for m in s.H1]
@@ -256,4 +256,25 @@ def test_nominal_flops_count_full_product_triples(kernel):
     want = total * 2.0 * b ** 3 * (1 + 2 * D)
     print(f"  nominal {g.nominal_flops:.6e} oracle {want:.6e} useful {g.useful_flops:.6e}", flush=True)
     assert g.nominal_flops == want
-    assert g.nominal_flops > g.useful_flops
+    assert g.nominal_flops > g.union_flops >= g.useful_flops > 0
+
+
+@pytest.mark.parametrize("variant", [dict(precision="fp64"), dict(precision="fp64", kernel="block"),
+                                     dict(precision="fp32", wide=True, fp64_first=2, closing_fp64=2,
+                                          skip="bound", graph=True),
+                                     dict(precision="bf16", closing_fp64=2)])
+def test_zero_block_products_are_not_issued(knob, variant):
+    # products with a block that is zero for its matrix (the union pattern
+    # stores such blocks) add exact zeros: leaving them out changes no bit of
+    # the result, and issues fewer products
+    s = W.config_system("cube10", L=4, n_dir=3, eps=1e-5)
+    a = T.solve(s, **variant)[0]
+    knob("TC2_TEST_NO_ZERO_SKIP", 1)
+    b = T.solve(s, **variant)[0]
+    print(f"  executed {a.executed_flops / 1e9:.2f} GF with the masks, {b.executed_flops / 1e9:.2f} "
+          f"without", flush=True)
+    assert a.branches == b.branches and a.alpha == b.alpha
+    for x, y in zip([a.X0] + a.X1, [b.X0] + b.X1):
+        assert np.array_equal(x.col, y.col) and np.array_equal(x.val, y.val)
+    if variant.get("kernel") != "block":
+        assert a.executed_flops < b.executed_flops
