@@ -341,6 +341,22 @@ TC2_API tc2_status tc2_mlp_forward(const float *theta, const float *x, int64_t n
 TC2_API tc2_status tc2_mlp_grad(const float *theta, const float *x, const float *y,
                                 int64_t n, int32_t device, float *grad, double *loss);
 
+/* tc2_mlp_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same gradient and mean loss, with every pointer a DEVICE pointer owned
+ * by the caller (theta: TC2_MLP_PARAMS floats, x: n x TC2_MLP_IN, y: n,
+ * grad: TC2_MLP_PARAMS floats, loss: one double), on the current device and
+ * hip_stream (NULL: the null stream).  Asynchronous: grad and loss hold the
+ * result once the stream reaches this work.  The per-block partial sums live
+ * in a fixed library array on each device (about 4.9 MB, held until the
+ * process ends), so 1 <= n <= TC2_MLP_NOALLOC_MAX_N; calls that overlap on one
+ * device share that array and race.  Inputs are not checked for NaN (they are
+ * not on the host); a non-finite input gives non-finite outputs.
+ * Errors: TC2_EINVAL (NULL pointer, n out of range), TC2_EDEVICE. */
+#define TC2_MLP_NOALLOC_MAX_N 65536
+TC2_API tc2_status tc2_mlp_grad_noalloc(const float *theta, const float *x, const float *y,
+                                        int64_t n, void *hip_stream, float *grad, double *loss);
+
 /* Train with Adam on the device; theta holds the initial parameters on entry
  * (drawn by the caller) and the trained ones on return.  loss_per_epoch, if
  * not NULL, receives `epochs` mean losses. */

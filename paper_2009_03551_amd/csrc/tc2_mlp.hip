@@ -10,6 +10,7 @@
 #include "../../include/tc2.h"
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 namespace tc2 {
@@ -157,6 +158,16 @@ __global__ void k_adam(float* th, float* m, float* v, const float* g, float lr, 
   th[p] -= lr * mh / (sqrtf(vh) + eps);
 }
 
+// Scratch of tc2_mlp_grad_noalloc: the per-block gradient partials (float,
+// TC2_MLP_NOALLOC_MAX_N / 256 blocks of MLP_NP) followed by the per-block loss
+// partials (double).  Every device the library runs on holds its own copy
+// until the process ends.
+constexpr int NA_BLOCKS = TC2_MLP_NOALLOC_MAX_N / 256;
+constexpr size_t NA_GPART = (size_t)NA_BLOCKS * MLP_NP * sizeof(float);
+constexpr size_t NA_LPART_OFF = (NA_GPART + 255) / 256 * 256;
+constexpr size_t NA_BYTES = NA_LPART_OFF + (size_t)NA_BLOCKS * sizeof(double);
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
 }  // namespace tc2
 
 using namespace tc2;
@@ -204,9 +215,49 @@ tc2_status grad_dev(hipStream_t st, const float* th, const float* x, const float
   return TC2_OK;
 }
 
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (the array's host-side name is not a device address).
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex na_lock;
+void* na_ptr[NA_MAX_DEVICES] = {};
+
+tc2_status scratch_of(int device, void** out) {
+  if (device < 0 || device >= NA_MAX_DEVICES) return TC2_EDEVICE;
+  std::lock_guard<std::mutex> g(na_lock);
+  if (!na_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TC2_EDEVICE;
+    na_ptr[device] = p;
+  }
+  *out = na_ptr[device];
+  return TC2_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+tc2_status tc2_mlp_grad_noalloc(const float* theta, const float* x, const float* y, int64_t n,
+                                void* hip_stream, float* grad, double* loss) {
+  if (!theta || !x || !y || !grad || !loss || n <= 0) return TC2_EINVAL;
+  if (n > TC2_MLP_NOALLOC_MAX_N) return TC2_EINVAL;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return TC2_EDEVICE;
+  void* base = nullptr;
+  if (tc2_status s = scratch_of(device, &base); s != TC2_OK) return s;
+  float* gpart = (float*)base;
+  double* lpart = (double*)((unsigned char*)base + NA_LPART_OFF);
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int nblk = (int)((n + 255) / 256);
+  // every partial the sum reads is written by the gradient kernel first: no
+  // clearing is needed
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(256), 0, st, theta, x, y, (long long)n,
+                     1.0 / (double)n, gpart, lpart);
+  hipLaunchKernelGGL(k_mlp_sum, dim3((MLP_NP + 255) / 256), dim3(256), 0, st, gpart, lpart, nblk,
+                     grad, loss);
+  MLPCHK(hipGetLastError());
+  return TC2_OK;
+}
 
 tc2_status tc2_mlp_forward(const float* theta, const float* x, int64_t n, int32_t device,
                            float* logits) {

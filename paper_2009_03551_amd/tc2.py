@@ -105,7 +105,7 @@ EXPORTED = ("tc2_setup", "tc2_run", "tc2_advance", "tc2_free", "tc2_strerror", "
             "tc2_export_rows", "tc2_iterate_size", "tc2_export_entries", "tc2_compare_entries",
             "tc2_mlp_forward", "tc2_mlp_grad", "tc2_mlp_train", "tc2_log_copy",
             "tc2_dense_response", "tc2_lowdin", "tc2_congruence", "tc2_bsr_release",
-            "tc2_lowdin_response", "tc2_congruence_response")
+            "tc2_lowdin_response", "tc2_congruence_response", "tc2_mlp_grad_noalloc")
 
 MLP_IN, MLP_PARAMS = 8, 4801
 
@@ -157,6 +157,25 @@ def mlp_grad(theta, X, y, device: int = 0):
     if st != 0:
         raise TC2Error(st, "tc2_mlp_grad")
     return g, loss.value
+
+
+MLP_NOALLOC_MAX_N = 65536
+
+
+def mlp_grad_noalloc(theta_ptr: int, x_ptr: int, y_ptr: int, n: int, grad_ptr: int,
+                     loss_ptr: int, stream: Optional[int] = None) -> None:
+    """tc2_mlp_grad_noalloc on device pointers (ints, e.g. tensor data_ptr()):
+    gradient and mean loss written to grad_ptr / loss_ptr asynchronously on
+    ``stream``; nothing is allocated."""
+    L = lib()
+    L.tc2_mlp_grad_noalloc.restype = C.c_int
+    L.tc2_mlp_grad_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                       C.c_void_p, C.c_void_p]
+    st = L.tc2_mlp_grad_noalloc(C.c_void_p(theta_ptr), C.c_void_p(x_ptr), C.c_void_p(y_ptr),
+                                C.c_int64(n), C.c_void_p(stream) if stream else None,
+                                C.c_void_p(grad_ptr), C.c_void_p(loss_ptr))
+    if st != 0:
+        raise TC2Error(st, "tc2_mlp_grad_noalloc")
 
 
 def mlp_train(X, y, theta0, epochs: int = 10, batch: int = 4096, lr: float = 1e-3,
