@@ -15,14 +15,32 @@
 namespace tc2 {
 
 // ------------------------------------------------------------------ device buffers
+// Buffers of at least VM_MIN bytes live in a reserved virtual range with
+// physical chunks mapped as they grow, taken from and given back to a pool
+// per device (tc2_memory.hip); smaller ones are plain allocations.
+struct DBuf;
+constexpr size_t VM_MIN = (size_t)64 << 20;
+hipError_t vm_grow(DBuf& b, size_t n);     // map up to >= n bytes, contents kept
+void vm_release(DBuf& b);                  // chunks back to the pool, range freed
+hipError_t dev_malloc(void** p, size_t n); // hipMalloc, retried after pool_trim
+void pool_trim();                          // pooled chunks of the device to the driver
+
 struct DBuf {
   void* p = nullptr;
   size_t cap = 0;
+  bool vm = false;                         // p is a virtual range (see above)
+  size_t va = 0;                           // its reserved bytes
+  int dev = 0;
+  std::vector<hipMemGenericAllocationHandle_t> chunks;
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
   ~DBuf() { release(); }
   void release() {
+    if (vm) {
+      vm_release(*this);
+      return;
+    }
     if (p) (void)hipFree(p);
     p = nullptr;
     cap = 0;
@@ -30,9 +48,15 @@ struct DBuf {
   // grow to at least n bytes (contents are not preserved)
   hipError_t reserve(size_t n) {
     if (n <= cap && p) return hipSuccess;
+    if (vm || n >= VM_MIN) {
+      if (!vm) release();
+      const hipError_t e = vm_grow(*this, n);
+      if (e != hipErrorNotSupported) return e;
+      (void)hipGetLastError();
+    }
     release();
     size_t want = n < 256 ? 256 : n;
-    hipError_t e = hipMalloc(&p, want);
+    hipError_t e = dev_malloc(&p, want);
     if (e != hipSuccess) {
       p = nullptr;
       return e;
@@ -40,22 +64,42 @@ struct DBuf {
     cap = want;
     return hipSuccess;
   }
-  // grow to at least n bytes, by at least a quarter of the current capacity
-  // (contents are not preserved): a buffer that grows over many updates is
-  // reallocated a few times instead of at every update
+  // grow to at least n bytes; a plain allocation grows by at least a quarter
+  // of its capacity, so that a buffer that grows over many updates is
+  // reallocated a few times instead of at every update (contents are not
+  // preserved)
   hipError_t reserve_grow(size_t n) {
     if (n <= cap && p) return hipSuccess;
+    if (vm || n >= VM_MIN) return reserve(n);
     const size_t g = cap + cap / 4;
     return reserve(n > g ? n : g);
   }
-  // grow to at least n bytes keeping the first `keep` bytes: a new buffer,
-  // a device copy on stream st, then the old buffer is freed (after the copy)
+  // grow to at least n bytes keeping the first `keep` bytes (a virtual range
+  // keeps them by mapping more chunks; a plain allocation is copied on
+  // stream st into its replacement, then freed)
   hipError_t grow_keep(size_t n, size_t keep, hipStream_t st) {
     if (n <= cap && p) return hipSuccess;
+    if (vm) return vm_grow(*this, n);
+    if (n >= VM_MIN) {
+      DBuf t;
+      hipError_t e = vm_grow(t, n);
+      if (e == hipSuccess) {
+        if (p && keep) {
+          e = hipMemcpyAsync(t.p, p, keep < cap ? keep : cap, hipMemcpyDeviceToDevice, st);
+          if (e == hipSuccess) e = hipStreamSynchronize(st);
+          if (e != hipSuccess) return e;
+        }
+        release();
+        swap(t);
+        return hipSuccess;
+      }
+      if (e != hipErrorNotSupported) return e;
+      (void)hipGetLastError();
+    }
     const size_t g = cap + cap / 4;
     const size_t want = n > g ? n : g;
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, want);
+    hipError_t e = dev_malloc(&q, want);
     if (e != hipSuccess) return e;
     if (p && keep) {
       e = hipMemcpyAsync(q, p, keep < cap ? keep : cap, hipMemcpyDeviceToDevice, st);
@@ -73,6 +117,10 @@ struct DBuf {
   void swap(DBuf& o) {
     std::swap(p, o.p);
     std::swap(cap, o.cap);
+    std::swap(vm, o.vm);
+    std::swap(va, o.va);
+    std::swap(dev, o.dev);
+    chunks.swap(o.chunks);
   }
   template <typename T> T* as() const { return (T*)p; }
 };

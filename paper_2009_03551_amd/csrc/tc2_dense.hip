@@ -15,6 +15,7 @@
 //   traces over the stored blocks of H and H1_d (k_trace_bsr; partial sums per
 //   workgroup added on the host in a fixed order)
 #include "tc2_host.h"
+#include "tc2_internal.h"
 #include "../../include/tc2.h"
 
 #include <hip/hip_runtime.h>
@@ -103,7 +104,7 @@ struct Dev {  // device allocation released with its owner
   ~Dev() {
     if (p) (void)hipFree(p);
   }
-  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 8); }
+  hipError_t alloc(size_t bytes) { return tc2::dev_malloc(&p, bytes ? bytes : 8); }
   double* d() const { return (double*)p; }
   int* i() const { return (int*)p; }
 };

@@ -236,6 +236,10 @@ struct CompactArgs {
                           // clamped to the host count, the stage capacity)
 };
 
+// hipMalloc that, when the device is out of memory, first returns the chunks
+// the solver keeps pooled for reuse to the driver and tries again
+hipError_t dev_malloc(void** p, size_t n);
+
 // kernels (launch wrappers), all asynchronous on `st`
 void launch_gershgorin(hipStream_t st, int nb, int b, const int* rp, const int* ci,
                        const double* hv, double* rowlo, double* rowhi);

@@ -257,7 +257,7 @@ struct Buf {  // device allocation released with its owner
   hipError_t alloc(size_t bytes) {
     if (p) (void)hipFree(p);
     p = nullptr;
-    return hipMalloc(&p, bytes ? bytes : 8);
+    return tc2::dev_malloc(&p, bytes ? bytes : 8);
   }
   int* i() const { return (int*)p; }
   double* d() const { return (double*)p; }

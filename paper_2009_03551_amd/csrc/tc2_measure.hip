@@ -239,7 +239,7 @@ struct Tmp {
   ~Tmp() {
     if (p) (void)hipFree(p);
   }
-  hipError_t alloc(size_t n) { return hipMalloc(&p, n < 256 ? 256 : n); }
+  hipError_t alloc(size_t n) { return tc2::dev_malloc(&p, n < 256 ? 256 : n); }
   template <typename T> T* as() const { return (T*)p; }
 };
 

@@ -11,6 +11,7 @@
 #include "../../include/tc2.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -136,6 +137,9 @@ tc2_status select_gfx950(int device, std::string* arch) {
 
 }  // namespace tc2
 
+// contexts alive per device (see tc2_free)
+static std::atomic<int> live_contexts[64];
+
 // ====================================================================== ABI
 extern "C" {
 
@@ -160,6 +164,7 @@ const char* tc2_strerror(tc2_status s) {
 void tc2_free(tc2_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
+  const int dev = ctx->device;
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
   for (hipEvent_t& e : ctx->pev)
     if (e) (void)hipEventDestroy(e);
@@ -170,6 +175,9 @@ void tc2_free(tc2_ctx* ctx) {
   if (ctx->run.ev0) (void)hipEventDestroy(ctx->run.ev0);
   if (ctx->run.ev1) (void)hipEventDestroy(ctx->run.ev1);
   delete ctx;
+  // the last context of a device gives the pooled chunks back, so that the
+  // process's other allocations find the memory
+  if (--live_contexts[dev] == 0) pool_trim();
 }
 
 // ---- tuned sub-tile shapes.  The cache file holds one JSON object per line,
@@ -287,11 +295,13 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   if (nb_tot > (1 << 26) || max_atoms > MAX_SYS_BITS) return TC2_EOVERFLOW;
 
   std::string arch;
+  if (o->device < 0 || o->device >= 64) return TC2_EDEVICE;
   if (tc2_status st = select_gfx950(o->device, &arch); st != TC2_OK) return st;
 
   ctx = new (std::nothrow) tc2_ctx();
   if (!ctx) return TC2_ENOMEM;
   ctx->device = o->device;
+  ++live_contexts[ctx->device];  // tc2_free (also on a failed setup) counts it down
   ctx->nsys = np;
   ctx->D = D;
   ctx->b = b;

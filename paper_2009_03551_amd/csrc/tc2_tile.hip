@@ -633,16 +633,19 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
             for (int r = 0; r < 4; ++r) tmp[m].v[r] = 0.f;
         }
         Acc<T>* dst = W ? tmp : &acc[W ? 0 : o][0];
+        // each enabled product runs its K-steps as one straight block
+        auto product = [&](Acc<T>& c, const T* pa, const T* pb) {
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          if (!FK && kk >= a.ksteps) break;
-          const T a0 = xa[lane + kk * 64], b0 = xb[lane + kk * 64];
-          if (en & 1u) mfma(dst[0], a0, b0);
-#pragma unroll
-          for (int d = 0; d < D; ++d) {
-            if ((en >> (1 + d)) & 1u) mfma(dst[1 + d], a0, xb[(1 + d) * BS + lane + kk * 64]);
-            if ((en >> (1 + MAXD + d)) & 1u) mfma(dst[1 + d], xa[(1 + d) * BS + lane + kk * 64], b0);
+          for (int kk = 0; kk < 4; ++kk) {
+            if (!FK && kk >= a.ksteps) break;
+            mfma(c, pa[lane + kk * 64], pb[lane + kk * 64]);
           }
+        };
+        if (en & 1u) product(dst[0], xa, xb);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          if ((en >> (1 + d)) & 1u) product(dst[1 + d], xa, xb + (1 + d) * BS);
+          if ((en >> (1 + MAXD + d)) & 1u) product(dst[1 + d], xa + (1 + d) * BS, xb);
         }
         if constexpr (W) {
           if (en & 1u) {
