@@ -403,6 +403,12 @@ def main() -> int:
                     help="mlp: train the skip network first on logged solves of smaller "
                          "cubes (seeds 500+L, same drop threshold), then skip with it")
     ap.add_argument("--mlp-threshold", type=float, default=0.995)
+    ap.add_argument("--mlp-cap", type=float, default=0.0,
+                    help="the network skips only candidates whose exact bound is below "
+                         "cap * eps (0: the library default, 4)")
+    ap.add_argument("--mlp-budget", type=float, default=0.0,
+                    help="summed bounds of the network's skips per solve, after which the "
+                         "solve continues with the exact screen alone (0: no limit)")
     ap.add_argument("--fp64-first", type=int, default=4)
     ap.add_argument("--wide", type=int, default=1, choices=[0, 1],
                     help="FP32 stages: FP64 sums of the per-block FP32 products")
@@ -516,15 +522,16 @@ def main() -> int:
     if args.kernel == "tile":
         variant.update(tile_kw)
     if theta is not None:
-        variant.update(mlp_weights=theta, mlp_threshold=args.mlp_threshold)
+        variant.update(mlp_weights=theta, mlp_threshold=args.mlp_threshold,
+                       mlp_bound_cap=args.mlp_cap, mlp_budget=args.mlp_budget)
     # references solved once per unit, their X1 kept on the host for the gate
     refs = []
     if not args.no_reference:
         refs.append(("plain FP64 GPU path", ref_kw))
     if args.skip == "mlp":
         bkw = dict(variant, skip="bound", count_useful=False)
-        bkw.pop("mlp_weights")
-        bkw.pop("mlp_threshold")
+        for k in ("mlp_weights", "mlp_threshold", "mlp_bound_cap", "mlp_budget"):
+            bkw.pop(k)
         refs.append(("exact norm-bound screen, same precision variant", bkw))
 
     def solve_refs(u):
@@ -661,6 +668,10 @@ def main() -> int:
               "graph_captures": r.graph_captures,
               "screened_blocks": sum(res[-1][0].screened_blocks for res in per),
               "mlp_skipped_blocks": sum(res[-1][0].mlp_skipped_blocks for res in per)}
+    if args.skip == "mlp":
+        config.update(mlp_threshold=args.mlp_threshold, mlp_cap=args.mlp_cap or 4.0,
+                      mlp_budget=args.mlp_budget or None,
+                      mlp_updates=sum(res[-1][0].mlp_updates for res in per))
     if args.units:
         config["unit_indices"] = [int(x) for x in args.units.split(",")]
     if len(systems) > 1:
