@@ -624,6 +624,19 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
           }
         }
       } else {
+        // Every operand fragment of the output's column blocks is read from
+        // LDS at once (one wait); X0's fragments serve all of its products.
+        // Each enabled product then runs its K-steps as one straight block.
+        T fa[1 + D][4], fb[1 + D][4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          if (!FK && kk >= a.ksteps) break;
+#pragma unroll
+          for (int m = 0; m <= D; ++m) {
+            fa[m][kk] = xa[m * BS + lane + kk * 64];
+            fb[m][kk] = xb[m * BS + lane + kk * 64];
+          }
+        }
         // W: this column's FP32 products go to temporaries, then to the FP64 sums
         Acc<T> tmp[W ? 1 + D : 1];
         if constexpr (W) {
@@ -633,19 +646,18 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
             for (int r = 0; r < 4; ++r) tmp[m].v[r] = 0.f;
         }
         Acc<T>* dst = W ? tmp : &acc[W ? 0 : o][0];
-        // each enabled product runs its K-steps as one straight block
-        auto product = [&](Acc<T>& c, const T* pa, const T* pb) {
+        auto prod = [&](Acc<T>& cc, const T* ra, const T* rb) {
 #pragma unroll
           for (int kk = 0; kk < 4; ++kk) {
             if (!FK && kk >= a.ksteps) break;
-            mfma(c, pa[lane + kk * 64], pb[lane + kk * 64]);
+            mfma(cc, ra[kk], rb[kk]);
           }
         };
-        if (en & 1u) product(dst[0], xa, xb);
+        if (en & 1u) prod(dst[0], fa[0], fb[0]);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          if ((en >> (1 + d)) & 1u) product(dst[1 + d], xa, xb + (1 + d) * BS);
-          if ((en >> (1 + MAXD + d)) & 1u) product(dst[1 + d], xa + (1 + d) * BS, xb);
+          if ((en >> (1 + d)) & 1u) prod(dst[1 + d], fa[0], fb[1 + d]);
+          if ((en >> (1 + MAXD + d)) & 1u) prod(dst[1 + d], fa[1 + d], fb[0]);
         }
         if constexpr (W) {
           if (en & 1u) {
