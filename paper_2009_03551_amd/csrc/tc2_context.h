@@ -280,6 +280,7 @@ struct tc2_ctx {
   int test_kl_chunk = 0;
   long long test_stage_cap = 0;
   int test_no_zero_skip = 0;      // issue every product (masks not passed to the kernel)
+  int test_waves_per_column = 0;  // 1: one wave per sub-tile column in every numeric kernel
   std::vector<int> h_active;      // host copy of the active flags
   // clusters
   int nc = 0, max_sys_clusters = 0;

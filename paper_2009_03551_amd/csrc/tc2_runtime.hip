@@ -333,6 +333,7 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   if (const char* v = getenv("TC2_TEST_KL_CHUNK")) ctx->test_kl_chunk = std::max(0, atoi(v));
   if (const char* v = getenv("TC2_TEST_STAGE_CAP")) ctx->test_stage_cap = std::max(0LL, atoll(v));
   if (const char* v = getenv("TC2_TEST_NO_ZERO_SKIP")) ctx->test_no_zero_skip = atoi(v) != 0;
+  if (const char* v = getenv("TC2_TEST_WAVES_PER_COLUMN")) ctx->test_waves_per_column = atoi(v);
   tc2_status st = TC2_OK;
   auto fail = [&](tc2_status s) {
     tc2_free(ctx);
@@ -799,6 +800,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     ta.wide = wide_now;
     ta.skip = ctx->skip_now;
     ta.xmask = ctx->test_no_zero_skip ? nullptr : ctx->mask[c].as<unsigned char>();
+    ta.waves_per_column = ctx->test_waves_per_column;
     ta.bn = screen ? ctx->bn.as<float>() : nullptr;
     ta.screened = screen ? ctx->screened.as<unsigned long long>() : nullptr;
     ta.mlp_skipped = screen ? ctx->screened.as<unsigned long long>() + 1 : nullptr;
@@ -1261,6 +1263,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       ta.shape = shape;
       ta.skip = ctx->skip_now;
       ta.xmask = ctx->test_no_zero_skip ? nullptr : ctx->mask[c].as<unsigned char>();
+      ta.waves_per_column = ctx->test_waves_per_column;
       ta.bn = screen ? ctx->bn.as<float>() : nullptr;
       ta.screened = screen ? ctx->screened.as<unsigned long long>() : nullptr;
       ta.mlp_skipped = screen ? ctx->screened.as<unsigned long long>() + 1 : nullptr;

@@ -183,10 +183,10 @@ __global__ __launch_bounds__(PNT) void k_tiles(int pass, PanelArgs a) {
 
 // ------------------------------------------------------------------ tile numeric
 // A block owns a sub-tile of SP rows of cluster P x TQ columns of cluster Q
-// (a tile of 8 x 8 output blocks is split into (8/SP)(8/TQ) blocks).  Wave w
-// owns the "diagonal" outputs (I_s, J_t) with t = (s + w) mod TQ, one per
-// row, so that for any column K every wave has about the same number of
-// present block pairs.  The common columns K of the two panels are walked in
+// (a tile of 8 x 8 output blocks is split into (8/SP)(8/TQ) blocks).  Wave
+// w = h TQ + v owns the "diagonal" outputs (I_s, J_t) with t = (s + v) mod TQ
+// for the SP / WS rows s of part h, so that for any column K every wave has
+// about the same number of present block pairs.  The common columns K of the two panels are walked in
 // groups of KG; for each group the present blocks X_{I_s K} and X_{J_t K} are
 // copied straight from global memory into LDS with global_load_lds (16 B per
 // lane), double-buffered so that the copy of group g+1 overlaps the MFMAs of
@@ -199,15 +199,18 @@ typedef __attribute__((address_space(3))) void lds_void;
 // FK: the block size needs all four K-steps of the padded tile (b > 12), so
 // the K-step loop has no exit test and the compiler can overlap the LDS reads
 // of one step with the MFMAs of the previous one.
-template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK>
-__global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
+// WS waves share each column of the sub-tile (WS = 2: two waves per SIMD, so
+// that one wave's bookkeeping overlaps the other's matrix operations).
+template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK, int WS>
+__global__ __launch_bounds__(TQ * WS * 64) void k_tile_numeric(TileArgs a) {
   constexpr int PER = (1 + D) * BS;                       // elements per entry
   constexpr int EB = PER * (int)sizeof(T);                // bytes per entry
   constexpr int NE = SP + TQ;                             // entries per column K
   constexpr int KG = (65536 / (NE * EB)) > 0 ? (65536 / (NE * EB)) : 1;
-  constexpr int NW = TQ;                                  // waves
+  constexpr int NW = TQ * WS;                             // waves
   constexpr int NT = NW * 64;
-  constexpr int NO = SP;                                  // outputs per wave
+  constexpr int NO = SP / WS;                             // outputs per wave
+  static_assert(SP % WS == 0, "rows of the sub-tile split evenly over the waves of a column");
   constexpr int KLMAX = 2048;
   constexpr int SUBS = (CS / SP) * (CS / TQ);
   __shared__ __attribute__((aligned(16))) T buf[2][KG][NE][PER];
@@ -258,8 +261,8 @@ __global__ __launch_bounds__(TQ * 64) void k_tile_numeric(TileArgs a) {
   bool any_owned = false;
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
-    so[o] = o;
-    to[o] = (o + wave) % TQ;
+    so[o] = (wave / TQ) * NO + o;
+    to[o] = (so[o] + wave % TQ) % TQ;
     Io[o] = sIA[so[o]];
     Jo[o] = sJB[to[o]];
     owned[o] = Io[o] >= 0 && Jo[o] >= 0 && (P != Q || Io[o] <= Jo[o]);
@@ -873,15 +876,15 @@ const char* tile_shape_name(int shape) {
 
 // Blocks of a persistent launch: enough to fill every CU at the kernel's
 // occupancy (computed once per instance).
-template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK>
+template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK, int WS>
 static unsigned resident_blocks() {
   static int per_cu = -1, cus = 0;
   if (per_cu < 0) {
     int dev = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_numeric<T, D, SP, TQ, BF, W, FK>,
-                                                     TQ * 64, 0) != hipSuccess || n < 1) {
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_numeric<T, D, SP, TQ, BF, W, FK, WS>,
+                                                     TQ * WS * 64, 0) != hipSuccess || n < 1) {
       cus = 256;
       n = 1;
     }
@@ -890,14 +893,25 @@ static unsigned resident_blocks() {
   return (unsigned)(per_cu * cus);
 }
 
-template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK>
-static void tile_go_k(hipStream_t st, const TileArgs& a) {
+template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK, int WS>
+static void tile_go_w(hipStream_t st, const TileArgs& a) {
   unsigned G = (unsigned)a.n_tiles * (unsigned)((CS / SP) * (CS / TQ));
   if (a.work) {  // persistent: never more blocks than sub-tiles or than fit at once
-    const unsigned R = resident_blocks<T, D, SP, TQ, BF, W, FK>();
+    const unsigned R = resident_blocks<T, D, SP, TQ, BF, W, FK, WS>();
     G = G < R ? G : R;
   }
-  hipLaunchKernelGGL((k_tile_numeric<T, D, SP, TQ, BF, W, FK>), dim3(G), dim3(TQ * 64), 0, st, a);
+  hipLaunchKernelGGL((k_tile_numeric<T, D, SP, TQ, BF, W, FK, WS>), dim3(G), dim3(TQ * WS * 64), 0,
+                     st, a);
+}
+
+// The 4 x 4 sub-tile of FP64 with two or three directions runs eight waves
+// (two per column, two per SIMD); the other shapes one wave per column.
+template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK>
+static void tile_go_k(hipStream_t st, const TileArgs& a) {
+  if constexpr (sizeof(T) == 8 && D >= 2 && SP == 4 && TQ == 4) {
+    if (a.waves_per_column != 1) return tile_go_w<T, D, SP, TQ, BF, W, FK, 2>(st, a);
+  }
+  tile_go_w<T, D, SP, TQ, BF, W, FK, 1>(st, a);
 }
 
 template <typename T, int D, bool BF, bool W, int S>

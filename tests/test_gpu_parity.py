@@ -278,3 +278,29 @@ def test_zero_block_products_are_not_issued(knob, variant):
         assert np.array_equal(x.col, y.col) and np.array_equal(x.val, y.val)
     if variant.get("kernel") != "block":
         assert a.executed_flops < b.executed_flops
+
+
+@pytest.mark.parametrize("case", [
+    dict(name="cube10", kw=dict(L=5, n_dir=3, eps=1e-5), variant=dict(precision="fp64")),
+    dict(name="cube10", kw=dict(L=5, n_dir=2, eps=1e-5),
+         variant=dict(precision="fp64", skip="bound", graph=True)),
+    dict(name="cube20", kw=dict(L=4, n_dir=3, eps=1e-6), variant=dict(precision="fp64"), chunk=64),
+])
+def test_two_waves_per_column_equal_one(knob, case):
+    # the FP64 4x4 sub-tile with two or three directions runs two waves per
+    # sub-tile column; every output sums the same products in the same order
+    # as with one wave per column, so the iterates are bitwise identical (only
+    # the grouping of the per-workgroup trace sums differs)
+    if "chunk" in case:
+        knob("TC2_TEST_KL_CHUNK", case["chunk"])
+    s = W.config_system(case["name"], **case["kw"])
+    a = T.solve(s, **case["variant"])[0]
+    knob("TC2_TEST_WAVES_PER_COLUMN", 1)
+    b = T.solve(s, **case["variant"])[0]
+    print(f"  {case['name']}: {a.iters} updates {a.branches}", flush=True)
+    assert a.branches == b.branches and a.iters == b.iters
+    for x, y in zip([a.X0] + a.X1, [b.X0] + b.X1):
+        assert np.array_equal(x.row_ptr, y.row_ptr) and np.array_equal(x.col, y.col)
+        assert np.array_equal(x.val, y.val)
+    for p, q in zip(a.alpha, b.alpha):
+        assert p == pytest.approx(q, rel=1e-12)
