@@ -199,8 +199,8 @@ typedef __attribute__((address_space(3))) void lds_void;
 // FK: the block size needs all four K-steps of the padded tile (b > 12), so
 // the K-step loop has no exit test and the compiler can overlap the LDS reads
 // of one step with the MFMAs of the previous one.
-// WS waves share each column of the sub-tile (WS = 2: two waves per SIMD, so
-// that one wave's bookkeeping overlaps the other's matrix operations).
+// WS waves share each column of the sub-tile (WS > 1: several waves per SIMD,
+// so that one wave's bookkeeping overlaps another's matrix operations).
 template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK, int WS>
 __global__ __launch_bounds__(TQ * WS * 64) void k_tile_numeric(TileArgs a) {
   constexpr int PER = (1 + D) * BS;                       // elements per entry
@@ -904,12 +904,13 @@ static void tile_go_w(hipStream_t st, const TileArgs& a) {
                      st, a);
 }
 
-// The 4 x 4 sub-tile of FP64 with two or three directions runs eight waves
-// (two per column, two per SIMD); the other shapes one wave per column.
+// The 4 x 4 sub-tile of FP64 with two or three directions runs sixteen waves
+// (four per column, one output each, four per SIMD); the other shapes one
+// wave per column.
 template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK>
 static void tile_go_k(hipStream_t st, const TileArgs& a) {
   if constexpr (sizeof(T) == 8 && D >= 2 && SP == 4 && TQ == 4) {
-    if (a.waves_per_column != 1) return tile_go_w<T, D, SP, TQ, BF, W, FK, 2>(st, a);
+    if (a.waves_per_column != 1) return tile_go_w<T, D, SP, TQ, BF, W, FK, 4>(st, a);
   }
   tile_go_w<T, D, SP, TQ, BF, W, FK, 1>(st, a);
 }

@@ -286,8 +286,8 @@ def test_zero_block_products_are_not_issued(knob, variant):
          variant=dict(precision="fp64", skip="bound", graph=True)),
     dict(name="cube20", kw=dict(L=4, n_dir=3, eps=1e-6), variant=dict(precision="fp64"), chunk=64),
 ])
-def test_two_waves_per_column_equal_one(knob, case):
-    # the FP64 4x4 sub-tile with two or three directions runs two waves per
+def test_four_waves_per_column_equal_one(knob, case):
+    # the FP64 4x4 sub-tile with two or three directions runs four waves per
     # sub-tile column; every output sums the same products in the same order
     # as with one wave per column, so the iterates are bitwise identical (only
     # the grouping of the per-workgroup trace sums differs)
