@@ -44,8 +44,11 @@ def kernel_name(kernel: str, kind: int, D: int, shape: int, b: int) -> str:
         return f"k_numeric<{T}, {D}>"
     sp, tq = SHAPES[max(shape, 0)]
     full_k = b > 12 and kind != 2
+    # waves per sub-tile column: four for the FP64 4 x 4 sub-tile with D >= 2
+    ws = 4 if (kind == 0 and D >= 2 and (sp, tq) == (4, 4)) else 1
     tf = lambda v: "true" if v else "false"
-    return f"k_tile_numeric<{T}, {D}, {sp}, {tq}, {tf(kind == 2)}, {tf(kind == 3)}, {tf(full_k)}>"
+    return (f"k_tile_numeric<{T}, {D}, {sp}, {tq}, {tf(kind == 2)}, {tf(kind == 3)}, {tf(full_k)}, "
+            f"{ws}>")
 
 KERNEL_SOURCES = ("paper_2009_03551_amd/csrc/tc2_tile.hip", "paper_2009_03551_amd/csrc/tc2_device.h",
                   "paper_2009_03551_amd/csrc/tc2_internal.h", "paper_2009_03551_amd/csrc/tc2_kernels.hip")

@@ -12,31 +12,32 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def test_kernel_names_match_the_kernel_trace():
-    with open(os.path.join(PROFILES, "k_tile_numeric_cube10_fp32w.txt")) as f:
+    with open(os.path.join(PROFILES, "k_tile_numeric_cube30_fp64.txt")) as f:
         text = f.read()
-    # default variant on cube10: b = 13 (full K-steps), one direction, 8 x 8 sub-tiles
-    wide = bench.kernel_name("tile", 3, 1, 0, 13)
-    fp64 = bench.kernel_name("tile", 0, 1, 0, 13)
-    assert f"tc2::{wide}(tc2::TileArgs)" in text
+    # bench default on cube30: FP64, b = 13 (full K-steps), three directions,
+    # 4 x 4 sub-tiles with four waves per sub-tile column
+    fp64 = bench.kernel_name("tile", 0, 3, 3, 13)
     assert f"tc2::{fp64}(tc2::TileArgs)" in text
+    assert fp64.endswith(", 4>")
+    assert bench.kernel_name("tile", 3, 1, 0, 13).endswith(", 1>")
     assert bench.kernel_name("block", 0, 2, -1, 8) == "k_numeric<double, 2>"
 
 
 def test_traffic_summary_belongs_to_the_current_sources():
-    path = os.path.join(PROFILES, "k_tile_numeric_cube10_fp32w_traffic.md")
+    path = os.path.join(PROFILES, "k_tile_numeric_cube30_fp64_traffic.md")
     with open(path) as f:
         recorded = re.search(r"kernel_source_sha256_16: `([0-9a-f]{16})`", f.read()).group(1)
-    traffic = bench.measured_traffic("k_tile_numeric", "cube10", "fp32w")
+    traffic = bench.measured_traffic("k_tile_numeric", "cube30", "fp64")
     if recorded == bench.kernel_source_hash():
-        assert traffic is not None and 1e9 < traffic < 1e12
+        assert traffic is not None and 1e11 < traffic < 1e14
     else:  # the kernels changed since the counters were taken: reported as unknown
         assert traffic is None
 
 
 def test_trace_summary_records_the_same_source_hash_as_the_traffic_summary():
-    with open(os.path.join(PROFILES, "k_tile_numeric_cube10_fp32w.txt")) as f:
+    with open(os.path.join(PROFILES, "k_tile_numeric_cube30_fp64.txt")) as f:
         trace = re.search(r"sha256\[:16\] = ([0-9a-f]{16})", f.read()).group(1)
-    with open(os.path.join(PROFILES, "k_tile_numeric_cube10_fp32w_traffic.md")) as f:
+    with open(os.path.join(PROFILES, "k_tile_numeric_cube30_fp64_traffic.md")) as f:
         traffic = re.search(r"kernel_source_sha256_16: `([0-9a-f]{16})`", f.read()).group(1)
     assert trace == traffic
 
