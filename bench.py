@@ -36,18 +36,20 @@ HBM_PEAK_GBS = 8000.0
 SHAPES = ((8, 8), (4, 8), (8, 4), (4, 4))   # sub-tile shape id -> (rows, columns)
 
 
-def kernel_name(kernel: str, kind: int, D: int, shape: int, b: int) -> str:
+def kernel_name(kernel: str, kind: int, D: int, shape: int, b: int, split: bool = False) -> str:
     """Template instance of the numeric kernel of one kind (FP64, FP32, BF16
-    operands, FP32 with FP64 sums), as rocprofv3 names it."""
+    operands, FP32 with FP64 sums; with `split`, the FP64-sum kind runs the
+    three-way bfloat16 split), as rocprofv3 names it."""
     T = "double" if kind == 0 else "float"
     if kernel == "block":
         return f"k_numeric<{T}, {D}>"
     sp, tq = SHAPES[max(shape, 0)]
-    full_k = b > 12 and kind != 2
+    bf = kind == 2 or (split and kind == 3)
+    full_k = b > 12 and not bf
     # waves per sub-tile column: four for the FP64 4 x 4 sub-tile with D >= 2
     ws = 4 if (kind == 0 and D >= 2 and (sp, tq) == (4, 4)) else 1
     tf = lambda v: "true" if v else "false"
-    return (f"k_tile_numeric<{T}, {D}, {sp}, {tq}, {tf(kind == 2)}, {tf(kind == 3)}, {tf(full_k)}, "
+    return (f"k_tile_numeric<{T}, {D}, {sp}, {tq}, {tf(bf)}, {tf(kind == 3)}, {tf(full_k)}, "
             f"{ws}>")
 
 KERNEL_SOURCES = ("paper_2009_03551_amd/csrc/tc2_tile.hip", "paper_2009_03551_amd/csrc/tc2_device.h",
@@ -651,10 +653,12 @@ def main() -> int:
     dom_launches = sum(res[-1][0].numeric_launches_kind[dom] for res in per)
     dom_flops = sum(x.useful_flops_kind[dom] for res in per for x in res[-1])
     achieved = dom_flops / (ms_kind[dom] * 1e-3) / 1e12 if ms_kind[dom] > 0 else 0.0
-    peak = PEAK_TFLOPS[("fp64", "fp32", "bf16", "fp32")[dom]]
+    split = chosen == "bf16" and variant["wide"]  # FP64-sum kind on bfloat16 MFMAs
+    peak = PEAK_TFLOPS["bf16" if split else ("fp64", "fp32", "bf16", "fp32")[dom]]
     pm = measured_peaks() or {}
-    pk_meas = pm.get({0: "gemm_fp64_tflops", 1: "gemm_fp32_tflops", 3: "gemm_fp32_tflops"}.get(dom, ""))
-    kname = kernel_name(args.kernel, dom, D, r.tile_shape[dom], sysm.H.b)
+    pk_meas = None if split else pm.get({0: "gemm_fp64_tflops", 1: "gemm_fp32_tflops",
+                                         3: "gemm_fp32_tflops"}.get(dom, ""))
+    kname = kernel_name(args.kernel, dom, D, r.tile_shape[dom], sysm.H.b, split)
     traffic = measured_traffic(kname.split("<")[0], args.workload,
                                ("fp64", "fp32", "bf16", "fp32w")[dom])
     plain = refs[0][0] if refs and refs[0][0] == "plain FP64 GPU path" else None

@@ -86,8 +86,11 @@ enum { TC2_FP64 = 0, TC2_FP32 = 1, TC2_BF16 = 2 };
 typedef struct {
   int32_t precision;       /* TC2_FP64 / TC2_FP32 / TC2_BF16 block products.  FP32
                               and BF16 keep X in FP32 with FP32 accumulation;
-                              BF16 rounds the MFMA operands to bfloat16; traces,
-                              branch and stopping tests stay in FP64           */
+                              BF16 rounds the MFMA operands to bfloat16 (a
+                              first stage, handed over to FP32), or, with
+                              wide_accumulate = 1, splits each operand into
+                              three bfloat16 parts for the whole reduced stage;
+                              traces, branch and stopping tests stay in FP64   */
   int32_t closing_fp64;    /* 0, or 2: finish a reduced-precision solve with two
                               FP64 steps of opposite branches                  */
   int32_t skip;            /* 0: every candidate block is computed; 1: exact
@@ -112,7 +115,12 @@ typedef struct {
   int32_t wide_accumulate; /* 0 or 1 (tiled kernel): in FP32 stages, the FP32
                               MFMA product of each column block is added to an
                               FP64 sum over the common columns, instead of one
-                              FP32 sum over all of them                         */
+                              FP32 sum over all of them.  With TC2_BF16: each
+                              FP32 operand is split into three bfloat16 parts
+                              (24 significant bits), the six cross products
+                              above 2^-24 of the leading one run on bfloat16
+                              MFMAs, and each column block's sum is added to
+                              the FP64 sums (an FP32-accurate stage)           */
   int32_t tune;            /* 0: default sub-tile shapes; 1 (tiled kernel):
                               per kernel kind, take the shape from tune_cache
                               or, failing that, time every available shape on

@@ -69,6 +69,23 @@ __device__ __forceinline__ s4 bf16_frag(const float* tile, int lane) {
   return v;
 }
 
+// The same fragment as bf16_frag, each value split into three bfloat16 parts
+// v = h + m + l + r: h = bf16(v), m = bf16(v - h), l = bf16(v - h - m) (the
+// differences are exact in FP32), so that the parts carry 24 significant bits.
+__device__ __forceinline__ void bf16_split3(const float* tile, int lane, s4& h, s4& m, s4& l) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float v = tile[(4 * (lane >> 4) + i) * BP + (lane & 15)];
+    const __bf16 bh = (__bf16)v;
+    const float r1 = v - (float)bh;
+    const __bf16 bm = (__bf16)r1;
+    const __bf16 bl = (__bf16)(r1 - (float)bm);
+    h[i] = __builtin_bit_cast(short, bh);
+    m[i] = __builtin_bit_cast(short, bm);
+    l[i] = __builtin_bit_cast(short, bl);
+  }
+}
+
 __device__ __forceinline__ void mfma_bf16(Acc<float>& c, s4 a, s4 b) {
   c.v = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c.v, 0, 0, 0);
 }

@@ -628,7 +628,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   int n_work = 0;          // work items (atom path) or tile blocks (tiled path)
   long long out_bound = 0; // upper bound of computed output blocks
   const int kind = ctx->cur_prec == P_FP64 ? K_FP64
-                   : (ctx->op_bf16 ? K_BF16 : (ctx->wide ? K_WIDE : K_FP32));
+                   : ((ctx->op_bf16 && !ctx->wide) ? K_BF16 : (ctx->wide ? K_WIDE : K_FP32));
   const int wide_now = kind == K_WIDE ? 1 : 0;
   int mult = tiled ? tile_subs(ctx->shape[kind]) : 1;
   if (tiled) ctx->kind_used[kind] = true;
@@ -1085,7 +1085,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   const int c = ctx->cur, n = c ^ 1;
   const int nb = ctx->nb, D = ctx->D, nc = ctx->nc;
   const int kind = ctx->cur_prec == P_FP64 ? K_FP64
-                   : (ctx->op_bf16 ? K_BF16 : (ctx->wide ? K_WIDE : K_FP32));
+                   : ((ctx->op_bf16 && !ctx->wide) ? K_BF16 : (ctx->wide ? K_WIDE : K_FP32));
   const int shape = ctx->shape[kind];
   const int mult = tile_subs(shape);
   const size_t tile = (size_t)(1 + D) * BS * prec_bytes(ctx->cur_prec);
@@ -1258,7 +1258,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       ta.bad = ctx->bad.as<int>();
       ta.partial = ctx->partial.as<double>();
       ta.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
-      ta.bf16 = kind == K_BF16 ? 1 : 0;
+      ta.bf16 = (ctx->op_bf16 && ctx->cur_prec == P_FP32) ? 1 : 0;
       ta.wide = kind == K_WIDE ? 1 : 0;
       ta.shape = shape;
       ta.skip = ctx->skip_now;
@@ -1474,7 +1474,7 @@ bool solve_finished(const tc2_ctx* ctx) {
   const RunState& R = ctx->run;
   for (int s = 0; s < ctx->nsys; ++s)
     if (R.ss[s].active) return false;
-  if (R.phase == 0 && ctx->op_bf16) return false;
+  if (R.phase == 0 && ctx->op_bf16 && !ctx->wide) return false;
   if (R.phase == 0 && R.reduced && ctx->closing == 2) return false;
   return true;
 }
@@ -1641,7 +1641,7 @@ tc2_status advance_one(tc2_ctx* ctx, bool* done) {
       }
     }
     if (any) break;
-    if (R.phase == 0 && ctx->op_bf16) {
+    if (R.phase == 0 && ctx->op_bf16 && !ctx->wide) {
       // BF16 stage done: continue with FP32 operands from where it stopped
       ctx->op_bf16 = 0;
       R.later_stage = true;
@@ -1681,7 +1681,7 @@ tc2_status advance_one(tc2_ctx* ctx, bool* done) {
   tc2_status r = TC2_OK;
   {
     const int kind_now = ctx->cur_prec == P_FP64 ? K_FP64
-                         : (ctx->op_bf16 ? K_BF16 : (ctx->wide ? K_WIDE : K_FP32));
+                         : ((ctx->op_bf16 && !ctx->wide) ? K_BF16 : (ctx->wide ? K_WIDE : K_FP32));
     // the closing pair runs as direct launches: two updates gain nothing
     // from a captured graph, and sizing their FP64 buffers exactly (not by
     // the graph's bounds) lets them fit in the buffers the reduced stage
@@ -1742,7 +1742,7 @@ tc2_status advance_one(tc2_ctx* ctx, bool* done) {
       continue;
     }
     const double tol = ctx->cur_prec == P_FP64 ? si.tol
-                                               : std::max(si.tol, ctx->op_bf16 ? 1e-3 : 1e-6);
+                                               : std::max(si.tol, (ctx->op_bf16 && !ctx->wide) ? 1e-3 : 1e-6);
     bool stop = false;
     if (!si.replay.empty()) {
       if (S.k == (int)si.replay.size()) {
@@ -1752,7 +1752,7 @@ tc2_status advance_one(tc2_ctx* ctx, bool* done) {
     } else if (S.k >= 2 && dmax < tol) {
       stop = true;
       S.status = TC2_OK;
-    } else if (ctx->op_bf16 && S.k >= 3 && std::fabs(iota) < 1e-2 * (double)si.n_occ) {
+    } else if (ctx->op_bf16 && !ctx->wide && S.k >= 3 && std::fabs(iota) < 1e-2 * (double)si.n_occ) {
       // bfloat16 stage: hand over to FP32 while the spectrum of X0 is still
       // well inside (0, 1), before bfloat16 rounding can push it out
       stop = true;

@@ -611,7 +611,47 @@ __global__ __launch_bounds__(TQ * WS * 64) void k_tile_numeric(TileArgs a) {
       nprod += __popc(en);
       const T* xa = &buf[bb][gi][so[o]][0];
       const T* xb = &buf[bb][gi][SP + to[o]][0];
-      if constexpr (BF) {
+      if constexpr (BF && W) {
+        // bfloat16 three-way split: each operand value v = h + m + l; the six
+        // cross products above 2^-24 of the leading term (l h, h l, m m, m h,
+        // h m, h h, smallest first) run as 16x16x16 bfloat16 MFMAs into an
+        // FP32 temporary per column block, which is added to the FP64 sums
+        s4 ah[1 + D], am[1 + D], al[1 + D], bh[1 + D], bm[1 + D], bl[1 + D];
+#pragma unroll
+        for (int m = 0; m <= D; ++m) {
+          bf16_split3((const float*)xa + m * BS, lane, ah[m], am[m], al[m]);
+          bf16_split3((const float*)xb + m * BS, lane, bh[m], bm[m], bl[m]);
+        }
+        Acc<float> tmp[1 + D];
+#pragma unroll
+        for (int m = 0; m <= D; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) tmp[m].v[r] = 0.f;
+        auto prod3 = [&](Acc<float>& c, int ma, int mb) {
+          mfma_bf16(c, al[ma], bh[mb]);
+          mfma_bf16(c, ah[ma], bl[mb]);
+          mfma_bf16(c, am[ma], bm[mb]);
+          mfma_bf16(c, am[ma], bh[mb]);
+          mfma_bf16(c, ah[ma], bm[mb]);
+          mfma_bf16(c, ah[ma], bh[mb]);
+        };
+        if (en & 1u) prod3(tmp[0], 0, 0);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          if ((en >> (1 + d)) & 1u) prod3(tmp[1 + d], 0, 1 + d);
+          if ((en >> (1 + MAXD + d)) & 1u) prod3(tmp[1 + d], 1 + d, 0);
+        }
+        if (en & 1u) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) wacc[o][0].v[r] += (double)tmp[0].v[r];
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+          if ((en >> (1 + d)) & ((1u << MAXD) | 1u)) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) wacc[o][1 + d].v[r] += (double)tmp[1 + d].v[r];
+          }
+      } else if constexpr (BF) {
         // bfloat16 operands: one 16x16x16 MFMA per block product
         const s4 a0 = bf16_frag((const float*)xa, lane), b0 = bf16_frag((const float*)xb, lane);
         if (en & 1u) mfma_bf16(acc[o][0], a0, b0);
@@ -928,7 +968,8 @@ static void tile_go(hipStream_t st, const TileArgs& a) {
 // false when the shape does not exist for this kind
 template <typename T, int D, bool BF, bool W>
 static bool tile_shape_go(hipStream_t st, const TileArgs& a) {
-  constexpr int KIND = sizeof(T) == 8 ? K_FP64 : (BF ? K_BF16 : (W ? K_WIDE : K_FP32));
+  // the bfloat16 split with FP64 sums has the accumulators of the FP32 kind with FP64 sums
+  constexpr int KIND = sizeof(T) == 8 ? K_FP64 : (W ? K_WIDE : (BF ? K_BF16 : K_FP32));
   switch (a.shape) {
     case TS_8x8:
       if constexpr (shape_ok(KIND, D, TS_8x8)) { tile_go<T, D, BF, W, TS_8x8>(st, a); return true; }
@@ -950,7 +991,7 @@ static bool tile_shape_go(hipStream_t st, const TileArgs& a) {
 template <typename T, int D>
 static bool tile_launch(hipStream_t st, const TileArgs& a) {
   if constexpr (sizeof(T) == 4) {
-    if (a.bf16) return tile_shape_go<T, D, true, false>(st, a);
+    if (a.bf16) return a.wide ? tile_shape_go<T, D, true, true>(st, a) : tile_shape_go<T, D, true, false>(st, a);
     if (a.wide) return tile_shape_go<T, D, false, true>(st, a);
   }
   return tile_shape_go<T, D, false, false>(st, a);

@@ -87,6 +87,41 @@ def test_bf16_closing_pair(D):
     assert dx1 < 1e-1
 
 
+@pytest.mark.parametrize("name,kw", [("cube20", dict(L=3)), ("cube10", dict(L=4))])
+def test_bf16_three_way_split_matches_fp32_with_fp64_sums(name, kw):
+    # bfloat16 operands split three ways (24 significant bits) with FP64 sums
+    # per column block: the accuracy of FP32 products with FP64 sums, against
+    # the oracle, where one bfloat16 rounding per operand is a thousand times
+    # worse
+    s = W.config_system(name, **kw)
+    o = O.solve_system(s)
+    g = T.solve(s, precision="bf16", wide=True, closing_fp64=2, fp64_first=8)[0]
+    f = T.solve(s, precision="fp32", wide=True, closing_fp64=2, fp64_first=8)[0]
+    dx1, dal = errors(s, g, o)
+    dx1f, dalf = errors(s, f, o)
+    assert g.status >= 0 and g.branches[-1] != g.branches[-2]
+    assert abs(g.tr_x0 - s.n_occ) < 1e-6 and abs(g.idem_err) < 1e-6
+    assert dx1 < 1e-6 and dal < 1e-6
+    # the two variants may stop at different updates (stall guard), which
+    # moves alpha by up to ~1e-7 here; X1 stays at the same level
+    assert dx1 < 4 * dx1f + 1e-9 and dal < max(4 * dalf, 2e-7)
+
+
+def test_bf16_three_way_split_products_against_fp64():
+    # the first update alone (replayed branch, no closing pair): the split
+    # product of one update against the FP64 product of the same update
+    s = W.config_system("cube10", L=4, n_dir=3, eps=0.0)
+    rep = O.solve_system(s, max_iter=2).branches
+    a = T.solve(s, precision="bf16", wide=True, closing_fp64=0, fp64_first=0, replay=[rep])[0]
+    b = T.solve(s, precision="fp64", replay=[rep])[0]
+    assert a.branches == b.branches == rep
+    for x, y in zip([a.X0] + a.X1, [b.X0] + b.X1):
+        d = np.abs(T.bsr_dense(x) - T.bsr_dense(y)).max()
+        ref = np.abs(T.bsr_dense(y)).max()
+        print(f"  max|d| {d:.2e} of max {ref:.2e}", flush=True)
+        assert d < 3e-7 * ref
+
+
 def test_reduced_precision_rejected_by_block_kernel():
     s = W.config_system("chain64", n=8)
     with pytest.raises(T.TC2Error):
