@@ -309,6 +309,17 @@ TC2_API int64_t tc2_log_copy(tc2_ctx *ctx, float *x, float *y, float *z, int64_t
 /* Release the context and everything it owns.  NULL-safe. */
 TC2_API void tc2_free(tc2_ctx *ctx);
 
+/* Device memory pool (Sec. 2.3's products grow their buffers every update).
+   Large buffers of every context map physical memory in fixed chunks; the
+   chunks a buffer or a freed context gives back stay in a per-device pool of
+   the process and are mapped again by later buffers and contexts, so that
+   the driver does not clear reclaimed memory before each reuse.  The pool
+   is returned to the driver when an allocation of the library fails for lack
+   of memory (then retried), and by this call: device = HIP ordinal.  Returns
+   TC2_EINVAL for an ordinal without a device.  Call it when other code of the
+   process needs the memory; no context of the library needs to be freed.  */
+TC2_API tc2_status tc2_trim_memory(int32_t device);
+
 /* Static description of a status code. */
 TC2_API const char *tc2_strerror(tc2_status s);
 

@@ -137,9 +137,6 @@ tc2_status select_gfx950(int device, std::string* arch) {
 
 }  // namespace tc2
 
-// contexts alive per device (see tc2_free)
-static std::atomic<int> live_contexts[64];
-
 // ====================================================================== ABI
 extern "C" {
 
@@ -175,9 +172,21 @@ void tc2_free(tc2_ctx* ctx) {
   if (ctx->run.ev0) (void)hipEventDestroy(ctx->run.ev0);
   if (ctx->run.ev1) (void)hipEventDestroy(ctx->run.ev1);
   delete ctx;
-  // the last context of a device gives the pooled chunks back, so that the
-  // process's other allocations find the memory
-  if (--live_contexts[dev] == 0) pool_trim();
+  (void)dev;
+}
+
+tc2_status tc2_trim_memory(int32_t device) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return TC2_EINVAL;
+  }
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return TC2_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return TC2_EDEVICE;
+  tc2::pool_trim();
+  (void)hipSetDevice(cur);
+  return TC2_OK;
 }
 
 // ---- tuned sub-tile shapes.  The cache file holds one JSON object per line,
@@ -301,7 +310,6 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   ctx = new (std::nothrow) tc2_ctx();
   if (!ctx) return TC2_ENOMEM;
   ctx->device = o->device;
-  ++live_contexts[ctx->device];  // tc2_free (also on a failed setup) counts it down
   ctx->nsys = np;
   ctx->D = D;
   ctx->b = b;

@@ -97,6 +97,8 @@ def lib() -> C.CDLL:
         L.tc2_strerror.argtypes = [C.c_int]
         L.tc2_version.restype = C.c_char_p
         L.tc2_version.argtypes = []
+        L.tc2_trim_memory.restype = C.c_int
+        L.tc2_trim_memory.argtypes = [C.c_int32]
         _lib = L
     return _lib
 
@@ -105,7 +107,8 @@ EXPORTED = ("tc2_setup", "tc2_run", "tc2_advance", "tc2_free", "tc2_strerror", "
             "tc2_export_rows", "tc2_iterate_size", "tc2_export_entries", "tc2_compare_entries",
             "tc2_mlp_forward", "tc2_mlp_grad", "tc2_mlp_train", "tc2_log_copy",
             "tc2_dense_response", "tc2_lowdin", "tc2_congruence", "tc2_bsr_release",
-            "tc2_lowdin_response", "tc2_congruence_response", "tc2_mlp_grad_noalloc")
+            "tc2_lowdin_response", "tc2_congruence_response", "tc2_mlp_grad_noalloc",
+            "tc2_trim_memory")
 
 MLP_IN, MLP_PARAMS = 8, 4801
 
@@ -472,6 +475,14 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def trim_memory(device: int = 0) -> None:
+    """Return the library's pooled device memory (chunks kept for reuse by
+    later buffers and contexts) to the driver (tc2_trim_memory)."""
+    st = lib().tc2_trim_memory(int(device))
+    if st != 0:
+        raise TC2Error(st, "tc2_trim_memory")
 
 
 def solve(systems, **kw) -> List[Result]:

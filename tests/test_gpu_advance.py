@@ -177,3 +177,17 @@ def test_entries_export_and_device_compare():
     finally:
         ref.close()
         var.close()
+
+
+def test_pool_kept_across_contexts_and_trimmed_on_request():
+    # a second context reuses the chunks the first one gave back; trimming the
+    # pool in between changes nothing in the results
+    s = W.config_system("cube10", L=5, n_dir=3, eps=1e-5)
+    a = T.solve(s, precision="fp64", skip="bound", graph=True)[0]
+    b = T.solve(s, precision="fp64", skip="bound", graph=True)[0]
+    T.trim_memory(0)
+    c = T.solve(s, precision="fp64", skip="bound", graph=True)[0]
+    same_result(a, b)
+    same_result(a, c)
+    with pytest.raises(T.TC2Error):
+        T.trim_memory(4096)
