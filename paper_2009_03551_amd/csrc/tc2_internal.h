@@ -170,7 +170,7 @@ struct TileArgs {
   long long log_cap;      // 0: no logging
   int kl_chunk;           // 0: default panel pass length
   int ksteps;
-  int waves_per_column;   // 1: one wave per column of the 4 x 4 FP64 sub-tile (tests compare)
+  int waves_per_column;   // 1: one wave per column of the 4 x 4 sub-tile (tests compare)
   int n_tiles;
   const int* rp;
   const int* ci;
