@@ -944,12 +944,13 @@ static void tile_go_w(hipStream_t st, const TileArgs& a) {
                      st, a);
 }
 
-// The 4 x 4 sub-tile with two or three directions (FP64, and FP32 with FP64
-// sums) runs sixteen waves (four per column, one output each, four per SIMD);
-// the other kinds and shapes one wave per column.
+// The 4 x 4 sub-tile with two or three directions (FP64, and the kinds with
+// FP64 sums: FP32 products and the bfloat16 split) runs sixteen waves (four
+// per column, one output each, four per SIMD); the other kinds and shapes one
+// wave per column.
 template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK>
 static void tile_go_k(hipStream_t st, const TileArgs& a) {
-  if constexpr (D >= 2 && SP == 4 && TQ == 4 && (sizeof(T) == 8 || (W && !BF))) {
+  if constexpr (D >= 2 && SP == 4 && TQ == 4 && (sizeof(T) == 8 || W)) {
     if (a.waves_per_column != 1) return tile_go_w<T, D, SP, TQ, BF, W, FK, 4>(st, a);
   }
   tile_go_w<T, D, SP, TQ, BF, W, FK, 1>(st, a);

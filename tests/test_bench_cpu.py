@@ -21,7 +21,7 @@ def test_kernel_names_match_the_kernel_trace():
     assert fp64.endswith(", 4>")
     assert bench.kernel_name("tile", 3, 1, 0, 13).endswith(", 1>")
     assert bench.kernel_name("tile", 3, 3, 3, 13).endswith(", 4>")          # FP32 with FP64 sums
-    assert bench.kernel_name("tile", 3, 3, 3, 13, split=True).endswith(", 1>")  # BF16 split
+    assert bench.kernel_name("tile", 3, 3, 3, 13, split=True).endswith("true, true, false, 4>")  # BF16 split
     assert bench.kernel_name("block", 0, 2, -1, 8) == "k_numeric<double, 2>"
 
 

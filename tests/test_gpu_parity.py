@@ -288,6 +288,8 @@ def test_zero_block_products_are_not_issued(knob, variant):
     dict(name="cube10", kw=dict(L=5, n_dir=3, eps=1e-5),
          variant=dict(precision="fp32", wide=True, fp64_first=2, closing_fp64=2, skip="bound",
                       graph=True)),
+    dict(name="cube10", kw=dict(L=5, n_dir=3, eps=1e-5),
+         variant=dict(precision="bf16", wide=True, fp64_first=2, closing_fp64=2, skip="bound")),
 ])
 def test_four_waves_per_column_equal_one(knob, case):
     # the 4x4 sub-tile with two or three directions (FP64, and FP32 with FP64
