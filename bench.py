@@ -47,8 +47,13 @@ def kernel_name(kernel: str, kind: int, D: int, shape: int, b: int, split: bool 
     bf = kind == 2 or (split and kind == 3)
     full_k = b > 12 and not bf
     # waves per sub-tile column: four for the 4 x 4 sub-tile with D >= 2 (FP64,
-    # and the kinds with FP64 sums)
-    ws = 4 if (kind in (0, 3) and D >= 2 and (sp, tq) == (4, 4)) else 1
+    # and the kinds with FP64 sums), two for the 8 x 8 sub-tile with D <= 1
+    # (FP64, FP32 with FP64 sums)
+    ws = 1
+    if kind in (0, 3) and D >= 2 and (sp, tq) == (4, 4):
+        ws = 4
+    elif (kind == 0 or (kind == 3 and not split)) and D <= 1 and (sp, tq) == (8, 8):
+        ws = 2
     tf = lambda v: "true" if v else "false"
     return (f"k_tile_numeric<{T}, {D}, {sp}, {tq}, {tf(bf)}, {tf(kind == 3)}, {tf(full_k)}, "
             f"{ws}>")

@@ -944,14 +944,19 @@ static void tile_go_w(hipStream_t st, const TileArgs& a) {
                      st, a);
 }
 
-// The 4 x 4 sub-tile with two or three directions (FP64, and the kinds with
-// FP64 sums: FP32 products and the bfloat16 split) runs sixteen waves (four
-// per column, one output each, four per SIMD); the other kinds and shapes one
-// wave per column.
+// Waves per sub-tile column.  The 4 x 4 sub-tile with two or three
+// directions (FP64, and the kinds with FP64 sums: FP32 products and the
+// bfloat16 split) runs sixteen waves (four per column, one output each, four
+// per SIMD); the 8 x 8 sub-tile with at most one direction (FP64, FP32 with
+// FP64 sums) sixteen (two per column, four outputs each); the other kinds and
+// shapes one wave per column.
 template <typename T, int D, int SP, int TQ, bool BF, bool W, bool FK>
 static void tile_go_k(hipStream_t st, const TileArgs& a) {
   if constexpr (D >= 2 && SP == 4 && TQ == 4 && (sizeof(T) == 8 || W)) {
     if (a.waves_per_column != 1) return tile_go_w<T, D, SP, TQ, BF, W, FK, 4>(st, a);
+  }
+  if constexpr (D <= 1 && SP == 8 && TQ == 8 && (sizeof(T) == 8 || (W && !BF))) {
+    if (a.waves_per_column != 1) return tile_go_w<T, D, SP, TQ, BF, W, FK, 2>(st, a);
   }
   tile_go_w<T, D, SP, TQ, BF, W, FK, 1>(st, a);
 }

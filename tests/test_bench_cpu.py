@@ -19,7 +19,8 @@ def test_kernel_names_match_the_kernel_trace():
     fp64 = bench.kernel_name("tile", 0, 3, 3, 13)
     assert f"tc2::{fp64}(tc2::TileArgs)" in text
     assert fp64.endswith(", 4>")
-    assert bench.kernel_name("tile", 3, 1, 0, 13).endswith(", 1>")
+    assert bench.kernel_name("tile", 3, 1, 0, 13).endswith(", 2>")          # D = 1, 8 x 8
+    assert bench.kernel_name("tile", 1, 1, 0, 13).endswith(", 1>")          # plain FP32
     assert bench.kernel_name("tile", 3, 3, 3, 13).endswith(", 4>")          # FP32 with FP64 sums
     assert bench.kernel_name("tile", 3, 3, 3, 13, split=True).endswith("true, true, false, 4>")  # BF16 split
     assert bench.kernel_name("block", 0, 2, -1, 8) == "k_numeric<double, 2>"

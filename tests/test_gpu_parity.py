@@ -290,11 +290,14 @@ def test_zero_block_products_are_not_issued(knob, variant):
                       graph=True)),
     dict(name="cube10", kw=dict(L=5, n_dir=3, eps=1e-5),
          variant=dict(precision="bf16", wide=True, fp64_first=2, closing_fp64=2, skip="bound")),
+    dict(name="cube10", kw=dict(L=5), variant=dict(precision="fp64", skip="bound", graph=True)),
+    dict(name="cube10", kw=dict(L=5),
+         variant=dict(precision="fp32", wide=True, fp64_first=2, closing_fp64=2, skip="bound")),
 ])
-def test_four_waves_per_column_equal_one(knob, case):
-    # the 4x4 sub-tile with two or three directions (FP64, and FP32 with FP64
-    # sums) runs four waves per
-    # sub-tile column; every output sums the same products in the same order
+def test_more_waves_per_column_equal_one(knob, case):
+    # the 4x4 sub-tile with two or three directions runs four waves per
+    # sub-tile column, the 8x8 sub-tile with one direction two (FP64 and the
+    # kinds with FP64 sums); every output sums the same products in the same order
     # as with one wave per column, so the iterates are bitwise identical (only
     # the grouping of the per-workgroup trace sums differs)
     if "chunk" in case:
