@@ -280,6 +280,56 @@ def crossover(args) -> int:
     return 0
 
 
+def decision_latency(args) -> int:
+    """Seconds per solve and per update of small, latency-bound FP64 solves
+    with the branch and stopping decisions taken on the host after every
+    update (graph = 1) and on the device (device_loop = k: the host replays
+    k update graphs between two polls of a flag word).  One JSON line per
+    workload, with whether every variant took the same branches and reached
+    bit-identical traces."""
+    import torch
+    from paper_2009_03551_amd import tc2 as T
+    from paper_2009_03551_amd import workloads as W
+
+    stream = torch.cuda.current_stream().cuda_stream
+    cases = {"chain64": lambda: W.config_system("chain64"),
+             "chain256": lambda: W.config_system("chain64", n=256),
+             "cube4": lambda: W.config_system("cube10", L=4),
+             "batch8_chain64": lambda: [W.config_system("chain64", seed=100 + k) for k in range(8)]}
+    if args.workload in cases:
+        cases = {args.workload: cases[args.workload]}
+    ks = [int(x) for x in (args.sizes or "1,4,16").split(",")]
+    variants = {"host": {}}
+    variants.update({f"device_k{k}": dict(device_loop=k) for k in ks})
+    for name, make in cases.items():
+        sysm = make()
+        first = sysm[0] if isinstance(sysm, list) else sysm
+        line = {"mode": "decision_latency", "workload": name, "atoms": first.H.nb, "b": first.H.b,
+                "dirs": len(first.H1), "systems": len(sysm) if isinstance(sysm, list) else 1}
+        outs = {}
+        for vname, kw in variants.items():
+            solver = T.Solver(sysm, export=False, graph=True, skip="bound", tune=args.tune,
+                              tune_cache=args.tune_cache, **kw)
+            for _ in range(args.warmup):
+                solver.run(stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                res = solver.run(stream=stream)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / args.steps
+            solver.close()
+            upd = max(r.iters for r in res)
+            outs[vname] = [(r.branches, r.status, r.alpha, r.e0) for r in res]
+            line[vname] = {"s_per_solve": sec, "ms_per_update": 1e3 * sec / max(upd, 1),
+                           "updates": upd, "device_updates": res[0].device_loop_updates}
+        ref = outs["host"]
+        line["identical"] = all(o == ref for o in outs.values())
+        line["branches"] = ref[0][0]
+        print(json.dumps(line), flush=True)
+    return 0
+
+
 def lowdin_pipeline(args) -> int:
     """Seconds of each stage of the non-orthogonal pipeline (Sec. 2.2): S^-1/2
     and the orthogonal forms, the TC2 / TC2-CPSCF solve on them (the default
@@ -454,6 +504,9 @@ def main() -> int:
                     help="with --lowdin: the perturbation is a displacement of the central atom, "
                          "which moves the overlap too (derivative of S^-1/2, three-term "
                          "back-transform)")
+    ap.add_argument("--latency", action="store_true",
+                    help="only time small FP64 solves with the branch and stopping decisions on "
+                         "the host and on the device (--sizes: poll intervals k, default 1,4,16)")
     ap.add_argument("--no-dense", action="store_true",
                     help="crossover: time the linear-scaling path only")
     ap.add_argument("--sizes", default=None,
@@ -482,6 +535,8 @@ def main() -> int:
         return crossover(args)
     if args.lowdin:
         return lowdin_pipeline(args)
+    if args.latency:
+        return decision_latency(args)
     stream = torch.cuda.current_stream().cuda_stream
 
     # workload -> units: lists of systems solved in one context (one merged

@@ -157,7 +157,33 @@ typedef struct {
                               candidates the network skipped in a solve add up
                               to more than this, the rest of the solve runs with
                               the exact screen alone (skip = 1); 0: no limit   */
+  int32_t device_loop;     /* 0: after every update the host reads the per-system
+                              scalars and takes the branch (Eq. TC2: SQUARE
+                              when Tr X0 >= Nocc) and stopping decisions (the
+                              band-energy tolerance of Sec. 2.3, the stall
+                              guard, max_iter).  k in 1..TC2_MAX_ITER: a kernel
+                              at the end of each captured update takes them on
+                              the device and writes the per-system flags that
+                              the next update reads; the host replays the update
+                              graph k times between two reads of a flag word.
+                              Taken by tc2_run for graph = 1, precision =
+                              TC2_FP64 solves with skip 0 or 1 and no replay,
+                              metrics_log, log_capacity, count_useful, profile
+                              or FP64 shape still to be tuned, when the dense
+                              bound of the stage (every
+                              upper block of every system kept) is at most
+                              TC2_DEVICE_LOOP_MAX_BYTES; otherwise (and in
+                              tc2_advance) the host decides.  A batch ends at
+                              the update count of the context's last such
+                              solve, and past it the word is polled after
+                              every update; otherwise up to k - 1 updates
+                              after the last system stops copy the iterate
+                              unchanged.  Results are identical              */
 } tc2_options;
+
+/* Largest stage (kept upper blocks x (1 + n_dir) padded 16 x 16 FP64 blocks)
+ * that device_loop sizes for the dense bound. */
+#define TC2_DEVICE_LOOP_MAX_BYTES ((int64_t)1 << 30)
 
 typedef struct {
   tc2_status status;
@@ -199,6 +225,8 @@ typedef struct {
   int32_t numeric_launches_kind[4];
   int32_t graph_updates;   /* updates run as a captured graph                   */
   int32_t graph_captures;  /* update graphs captured (the others were replays)  */
+  int32_t device_loop_updates; /* updates whose branch and stopping decisions
+                              were taken on the device (device_loop)           */
   double nominal_flops;    /* 2 b^3 (1 + 2D) per block triple of the full products
                               on each update's input pattern (sum over rows K of
                               m_K^2): the work of full sparse products, as the

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtc2.so")
 SOURCES = ["tc2_kernels.hip", "tc2_tile.hip", "tc2_mlp.hip", "tc2_runtime.hip", "tc2_dense.hip",
-           "tc2_lowdin.hip", "tc2_measure.hip", "tc2_memory.hip"]
+           "tc2_lowdin.hip", "tc2_measure.hip", "tc2_memory.hip", "tc2_decide.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # the dense O(N^3) path: eigenpairs (rocSOLVER) and products (rocBLAS)
 LIBS = ["-lrocsolver", "-lrocblas"]

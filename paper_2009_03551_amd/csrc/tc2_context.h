@@ -295,6 +295,14 @@ struct tc2_ctx {
   std::vector<unsigned long long> gkey[2];
   long long kept_prev = 0, kept_prev2 = 0;  // kept upper blocks of the last updates
   int graph_updates = 0, graph_captures = 0;
+  // branch and stopping decisions on the device (device_loop): per-system
+  // records, parameters and the flag word the host polls
+  int device_loop = 0;            // option: updates replayed between two polls
+  int dl_updates = 0;             // updates of this solve decided on the device
+  int dl_last = 0;                // updates of the last device-loop solve (batch sizing)
+  long long dl_cap = 0;           // dense bound of the kept upper blocks
+  tc2::DBuf dl_state, dl_param, dl_word;
+  tc2::HostPin pin_dl;            // the word and the records, read back
   tc2::DBuf panel_cnt, panel_rp, panel_k, panel_e, tile_cnt, tile_rp, tile_pairs, tile_p, tile_q;
   tc2::DBuf tile_bits;            // cluster bitmaps kept between the two tile passes
   // the solve in progress

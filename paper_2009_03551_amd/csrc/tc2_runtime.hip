@@ -7,6 +7,7 @@
 // Sec. 2.3 (band-energy change below the tolerance) per system.
 #include "tc2_internal.h"
 #include "tc2_context.h"
+#include "tc2_decide.h"
 #include "tc2_host.h"
 #include "../../include/tc2.h"
 
@@ -273,6 +274,7 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   if (o->precision == P_BF16 && o->numeric_kernel != 0) return TC2_EINVAL;
   if (o->fp64_first < 0 || o->fp64_first > TC2_MAX_ITER) return TC2_EINVAL;
   if (o->count_useful < 0 || o->count_useful > 1) return TC2_EINVAL;
+  if (o->device_loop < 0 || o->device_loop > TC2_MAX_ITER) return TC2_EINVAL;
   const int b = probs[0].H.b, D = probs[0].n_dir;
   if (b < 1 || b > BP || D < 0 || D > MAXD) return TC2_EINVAL;
   int64_t nb_tot = 0;
@@ -333,6 +335,7 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
   ctx->tune = o->tune;
   if (o->tune_cache) ctx->tune_cache = o->tune_cache;
   ctx->graph = o->graph;
+  ctx->device_loop = o->device_loop;
   ctx->count_useful = o->count_useful;
   if (o->metrics_log) ctx->metrics_log = o->metrics_log;
   ctx->arch = arch;
@@ -498,6 +501,19 @@ static tc2_status setup_impl(const tc2_problem* probs, int32_t np, const tc2_opt
       const long long m = csys_end[s] - csys_start[s];
       ctx->tile_bound += m * (m + 1) / 2;
     }
+    // with fewer cluster pairs than compute units, one workgroup per pair
+    // leaves most units idle and each runs the whole column loop of its
+    // pair: the FP64 kind, 8x8 by default, then takes the 4x8 sub-tile (two
+    // workgroups per pair; on a 64-atom chain the products took 0.155 ms per
+    // update instead of 0.216), unless a tuned shape was loaded
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) {
+      (void)hipGetLastError();
+      n_cu = 0;
+    }
+    if (!ctx->tuned[K_FP64] && ctx->shape[K_FP64] == TS_8x8 && ctx->tile_bound < n_cu &&
+        tile_shape_available(K_FP64, D, TS_4x8))
+      ctx->shape[K_FP64] = TS_4x8;
     if ((st = upload(ctx, ctx->clus_atom, clus_atom)) != TC2_OK) return fail(st);
     if ((st = upload(ctx, ctx->clus_sys, clus_sys)) != TC2_OK) return fail(st);
     if ((st = upload(ctx, ctx->atom_clus, atom_clus)) != TC2_OK) return fail(st);
@@ -1089,7 +1105,7 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   } while (0)
 
 int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
-               unsigned long long& exec_pairs_total) {
+               unsigned long long& exec_pairs_total, bool dl = false) {
   const int c = ctx->cur, n = c ^ 1;
   const int nb = ctx->nb, D = ctx->D, nc = ctx->nc;
   const int kind = ctx->cur_prec == P_FP64 ? K_FP64
@@ -1098,15 +1114,22 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   const int mult = tile_subs(shape);
   const size_t tile = (size_t)(1 + D) * BS * prec_bytes(ctx->cur_prec);
   const bool screen = ctx->skip_now != 0;
-  bool any_stopped = false;
-  for (int s = 0; s < ctx->nsys; ++s) any_stopped |= !ctx->h_active[s];
+  // with the decisions on the device the host does not know which systems
+  // have stopped: the copy-through is always part of the update
+  bool any_stopped = dl;
+  if (!dl)
+    for (int s = 0; s < ctx->nsys; ++s) any_stopped |= !ctx->h_active[s];
   ctx->kind_used[kind] = true;
   ctx->last_kind = kind;
   const long long nnz_c = ctx->nnz[c];
 
-  // kept-block estimate: the last count grown by the last growth factor
+  // kept-block estimate: the last count grown by the last growth factor;
+  // with the decisions on the device, the dense bound (no update can
+  // overflow it, so none needs a size from the host)
   long long est;
-  if (ctx->kept_prev == 0) {
+  if (dl) {
+    est = ctx->dl_cap;
+  } else if (ctx->kept_prev == 0) {
     est = 2 * nnz_c + 1024;
   } else {
     double g = ctx->kept_prev2 > 0 ? (double)ctx->kept_prev / (double)ctx->kept_prev2 : 2.0;
@@ -1115,13 +1138,16 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   }
   // geometric buckets (steps of 2^(1/4)): the capacity is part of the graph
   // key, so updates whose estimates share a bucket replay the same graph
-  {
+  if (!dl) {
     double v = 1024.0;
     while (v < (double)est) v *= 1.189207115002721;
     est = (long long)v;
+    if (ctx->test_stage_cap > 0) est = ctx->test_stage_cap;
   }
-  if (ctx->test_stage_cap > 0) est = ctx->test_stage_cap;
   est = std::min<long long>(est, INT32_MAX / 2);
+  // entries of the current pattern the panel buffers must hold: the
+  // host's count, or the bound of any pattern under the dense stage bound
+  const long long ent_c = dl ? 2 * est : nnz_c;
 
   int hcnt[8];
   unsigned long long pairs = 0, sc[2] = {0, 0};
@@ -1137,8 +1163,8 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     GRESERVE(ctx->tile_pairs.reserve((size_t)nc * 8));
     const int tile_words = (ctx->max_sys_clusters + 31) / 32;
     GRESERVE(ctx->tile_bits.reserve((size_t)std::max(nc, 1) * tile_words * 4));
-    GRESERVE(ctx->panel_k.reserve((size_t)std::max<long long>(nnz_c, 1) * 4));
-    GRESERVE(ctx->panel_e.reserve((size_t)std::max<long long>(nnz_c, 1) * CS * 4));
+    GRESERVE(ctx->panel_k.reserve((size_t)std::max<long long>(ent_c, 1) * 4));
+    GRESERVE(ctx->panel_e.reserve((size_t)std::max<long long>(ent_c, 1) * CS * 4));
     GRESERVE(ctx->tile_p.reserve((size_t)std::max<long long>(ctx->tile_bound, 1) * 4));
     GRESERVE(ctx->tile_q.reserve((size_t)std::max<long long>(ctx->tile_bound, 1) * 4));
     GRESERVE(ctx->partial.reserve((size_t)std::max(ctx->tile_bound * 4, (long long)nb) * NQ * 8));
@@ -1174,7 +1200,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     const std::vector<unsigned long long> key = {
         (unsigned long long)kind, (unsigned long long)shape, (unsigned long long)screen,
         (unsigned long long)any_stopped, (unsigned long long)cap, (unsigned long long)cap_c,
-        (unsigned long long)ctx->profile, (unsigned long long)(uintptr_t)st,
+        (unsigned long long)ctx->profile, (unsigned long long)(uintptr_t)st, (unsigned long long)dl,
         (uintptr_t)ctx->xv[c].p, (uintptr_t)ctx->rp[c].p, (uintptr_t)ctx->ci[c].p,
         (uintptr_t)ctx->rp[n].p, (uintptr_t)ctx->ci[n].p,
         (uintptr_t)ctx->panel_k.p, (uintptr_t)ctx->panel_e.p, (uintptr_t)ctx->tile_p.p,
@@ -1325,6 +1351,25 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
                          ctx->mask[n].as<unsigned char>(), ctx->rp[n].as<int>() + nb);
       launch_reduce(st, ctx->nsys, ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>(),
                     ctx->partial.as<double>(), ctx->scal.as<double>());
+      if (dl) {
+        // branch and stopping decisions for the next update, on the device
+        DecideArgs da{};
+        da.nsys = ctx->nsys;
+        da.D = D;
+        da.init = 0;
+        da.scal = ctx->scal.as<double>();
+        da.bad = ctx->bad.as<int>();
+        da.nominal = ctx->nominal.as<unsigned long long>();
+        da.exec_pairs = ctx->exec_pairs.as<unsigned long long>();
+        da.screened = screen ? ctx->screened.as<unsigned long long>() : nullptr;
+        da.overflow = cnt + 2;
+        da.param = ctx->dl_param.as<DecideParam>();
+        da.state = ctx->dl_state.as<DecideSys>();
+        da.active = ctx->active.as<int>();
+        da.branch = ctx->branch.as<int>();
+        da.word = ctx->dl_word.as<DecideWord>();
+        launch_decide(st, da);
+      }
     };
     // capture of a part sequence into an executable graph; false if refused
     auto capture = [&](hipGraphExec_t* out, bool with_pre, bool with_num, bool with_post) {
@@ -1383,6 +1428,13 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       HIPCHK(hipEventRecord(ctx->pev[5], st));
     } else {
       HIPCHK(hipGraphLaunch(ctx->gexec[c], st));
+    }
+    if (dl) {
+      // nothing is read back: the device has taken the decisions, and the
+      // host polls their flag word every device_loop updates
+      ctx->xv[c].swap(ctx->xv[n]);
+      ctx->cur = n;
+      return TC2_OK;
     }
     // counters, pairs, new entries, screen counts and scalars, read back
     // through page-locked memory: [hcnt 32 B | pairs 8 | nnz_new 8 | sc 16 | scal]
@@ -1503,6 +1555,7 @@ tc2_status begin_solve(tc2_ctx* ctx, hipStream_t st) {
   ctx->ms_tune = 0.0;
   ctx->prev_out_bound = -1;
   ctx->kept_prev = ctx->kept_prev2 = 0;
+  ctx->dl_updates = 0;
   ctx->graph_updates = 0;
   ctx->graph_captures = 0;
   for (bool& u : ctx->kind_used) u = false;
@@ -1869,6 +1922,7 @@ tc2_status finish_solve(tc2_ctx* ctx, tc2_result* res) {
     }
     Rs.graph_updates = ctx->graph_updates;
     Rs.graph_captures = ctx->graph_captures;
+    Rs.device_loop_updates = ctx->dl_updates;
     Rs.ms_compact = ctx->ms_cmp;
     Rs.numeric_launches = ctx->num_launches;
     for (int k = 0; k < 4; ++k) Rs.tile_shape[k] = ctx->kind_used[k] ? ctx->shape[k] : -1;
@@ -1891,12 +1945,182 @@ tc2_status finish_solve(tc2_ctx* ctx, tc2_result* res) {
   return worst;
 }
 
+// Whether the solve just begun can take its branch and stopping decisions
+// on the device (device_loop): FP64 updates in captured graphs with nothing
+// that needs the host between two updates, and a dense stage bound within
+// TC2_DEVICE_LOOP_MAX_BYTES.  Sets ctx->dl_cap.
+bool device_loop_eligible(tc2_ctx* ctx) {
+  const RunState& R = ctx->run;
+  if (ctx->device_loop <= 0 || !ctx->graph || !ctx->graph_ok || ctx->kernel != 0) return false;
+  if (ctx->prec != P_FP64 || R.reduced || ctx->cur_prec != P_FP64 || ctx->skip_now == 2) return false;
+  // a shape still to be tuned times its first update outside a graph
+  if (!ctx->metrics_log.empty() || ctx->log_cap > 0 || (ctx->tune && !ctx->tuned[K_FP64]) ||
+      ctx->count_useful || ctx->profile)
+    return false;
+  long long cap = 0;
+  for (const SysInfo& si : ctx->sys) {
+    if (!si.replay.empty()) return false;
+    cap += (long long)si.nb * (si.nb + 1) / 2;
+  }
+  const double tile = (double)(1 + ctx->D) * BS * 8;
+  if ((double)cap * tile > (double)TC2_DEVICE_LOOP_MAX_BYTES) return false;
+  ctx->dl_cap = cap;
+  return true;
+}
+
+// The updates of a solve with the decisions on the device: the update graphs
+// (each ending with k_decide) are replayed device_loop times between two
+// polls of the flag word, until no system is active.  The device records are
+// then copied into the host state, which finish_solve reports.  *used is
+// false when the solve is not eligible (the host loop runs it); a capture the
+// runtime refuses hands the rest of the solve to the host loop.
+tc2_status run_device_loop(tc2_ctx* ctx, bool* used) {
+  RunState& R = ctx->run;
+  hipStream_t st = R.st;
+  const int nsys = ctx->nsys, D = ctx->D, nb = ctx->nb;
+  *used = false;
+  if (!device_loop_eligible(ctx)) return TC2_OK;
+  const int c0 = ctx->cur;
+  const size_t nnz = (size_t)ctx->nnz[c0], cap2 = (size_t)2 * ctx->dl_cap;
+  const size_t tile = (size_t)(1 + D) * BS * 8;
+  // the current pattern's buffers at the bound, contents kept: no update
+  // replayed between two polls grows (and so frees) a buffer in use
+  {
+    hipError_t e = ctx->ci[c0].grow_keep(cap2 * 4, nnz * 4, st);
+    if (e == hipSuccess) e = ctx->mask[c0].grow_keep(cap2, nnz, st);
+    if (e == hipSuccess) e = ctx->xv[c0].grow_keep(cap2 * tile, nnz * tile, st);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      return TC2_OK;
+    }
+    HIPCHK(e);
+  }
+  const size_t rec = (size_t)nsys * sizeof(DecideSys);
+  const size_t off_rec = 64, off_act = off_rec + rec, off_br = off_act + (size_t)nsys * 4,
+               off_nnz = (off_br + (size_t)nsys * 4 + 7) / 8 * 8, off_prm = off_nnz + 8;
+  HIPCHK(ctx->dl_param.reserve((size_t)nsys * sizeof(DecideParam)));
+  HIPCHK(ctx->dl_state.reserve(rec));
+  HIPCHK(ctx->dl_word.reserve(sizeof(DecideWord)));
+  HIPCHK(ctx->pin_dl.reserve(off_prm + (size_t)nsys * sizeof(DecideParam)));
+  char* pin = (char*)ctx->pin_dl.p;
+  DecideParam* prm = (DecideParam*)(pin + off_prm);
+  int* act = (int*)(pin + off_act);
+  int max_it = 0;
+  for (int s = 0; s < nsys; ++s) {
+    prm[s].n_occ = (double)ctx->sys[s].n_occ;
+    prm[s].tol = ctx->sys[s].tol;
+    prm[s].max_iter = ctx->sys[s].max_iter;
+    prm[s].pad = 0;
+    R.active[s] = R.ss[s].active ? 1 : 0;
+    act[s] = R.active[s];
+    max_it = std::max(max_it, ctx->sys[s].max_iter);
+  }
+  HIPCHK(hipMemcpyAsync(ctx->dl_param.p, prm, (size_t)nsys * sizeof(DecideParam),
+                        hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->active.p, act, (size_t)nsys * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(ctx->dl_state.p, 0, rec, st));
+  HIPCHK(hipMemsetAsync(ctx->dl_word.p, 0, sizeof(DecideWord), st));
+  {
+    // the first update's branch, from the initial scalars
+    DecideArgs da{};
+    da.nsys = nsys;
+    da.D = D;
+    da.init = 1;
+    da.scal = ctx->scal.as<double>();
+    da.param = ctx->dl_param.as<DecideParam>();
+    da.state = ctx->dl_state.as<DecideSys>();
+    da.active = ctx->active.as<int>();
+    da.branch = ctx->branch.as<int>();
+    da.word = ctx->dl_word.as<DecideWord>();
+    launch_decide(st, da);
+    HIPCHK(hipGetLastError());
+  }
+  *used = true;
+  ctx->h_active = R.active;
+  DecideWord w{};
+  auto poll = [&]() -> tc2_status {
+    HIPCHK(hipMemcpyAsync(pin, ctx->dl_word.p, sizeof(DecideWord), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    memcpy(&w, pin, sizeof(DecideWord));
+    return TC2_OK;
+  };
+  // batches of device_loop updates; within the update count of the last
+  // device-loop solve of this context, a batch ends there, and past it the
+  // flag word is polled after every update, so that a solve like the last
+  // one launches no update after its last stop
+  const int expect = ctx->dl_last;
+  bool handed_over = false;
+  int launched = 0;
+  for (;;) {
+    int batch = ctx->device_loop;
+    if (expect > 0) batch = launched < expect ? std::min(batch, expect - launched) : 1;
+    for (int k = 0; k < batch && launched < max_it; ++k, ++launched) {
+      const int g = step_graph(ctx, st, R.scal, R.exec_pairs, true);
+      if (g == 1) {
+        ctx->graph_ok = false;
+        handed_over = true;
+        break;
+      }
+      if (g != TC2_OK) return (tc2_status)g;
+    }
+    if (tc2_status r = poll(); r != TC2_OK) return r;
+    if (w.overflow) return TC2_ENOMEM;
+    if (handed_over || !w.any_active || launched >= max_it) break;
+  }
+  // the device records into the host state
+  HIPCHK(hipMemcpyAsync(pin + off_rec, ctx->dl_state.p, rec, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(pin + off_act, ctx->active.p, (size_t)nsys * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(pin + off_br, ctx->branch.p, (size_t)nsys * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(pin + off_nnz, ctx->rp[ctx->cur].as<int>() + nb, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const DecideSys* recs = (const DecideSys*)(pin + off_rec);
+  const int* br = (const int*)(pin + off_br);
+  for (int s = 0; s < nsys; ++s) {
+    SysState& S = R.ss[s];
+    if (!S.active) continue;  // trivial or degenerate: never iterated
+    const DecideSys& d = recs[s];
+    S.k = d.k;
+    S.status = (tc2_status)d.status;
+    S.active = act[s] != 0;
+    S.branches.assign(d.branches, (size_t)d.k);
+    S.trip = d.trip;
+    S.nominal = (double)d.nominal;
+    std::copy(d.prev, d.prev + 1 + 2 * D, S.prev);
+    // the last two iotas, in order: enough for the stall guard's k - 2
+    S.iota.clear();
+    if (d.k >= 2) S.iota.push_back(d.iota2);
+    if (d.k >= 1) S.iota.push_back(d.iota1);
+    R.active[s] = act[s];
+    R.branch[s] = br[s];
+  }
+  ctx->h_active = R.active;
+  int nnz_now = 0;
+  memcpy(&nnz_now, pin + off_nnz, 4);
+  ctx->nnz[ctx->cur] = nnz_now;
+  ctx->kept_prev = ctx->kept_prev2 = 0;
+  R.updates += w.updates;
+  R.exec_pairs += w.exec_pairs;
+  ctx->screened_total += w.screened[0];
+  ctx->mlp_total += w.screened[1];
+  ctx->graph_updates += w.updates;
+  ctx->dl_updates += w.updates;
+  if (!handed_over) ctx->dl_last = w.updates;
+  return TC2_OK;
+}
+
 tc2_status run_impl(tc2_ctx* ctx, void* stream, tc2_result* res) {
   if (!ctx || !res) return TC2_EINVAL;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = stream ? (hipStream_t)stream : ctx->own;
   tc2_status r = begin_solve(ctx, st);
   if (r != TC2_OK) return r;
+  if (ctx->device_loop > 0) {
+    bool used = false;
+    if ((r = run_device_loop(ctx, &used)) != TC2_OK) {
+      ctx->run.open = false;
+      return r;
+    }
+  }
   for (;;) {
     bool done = false;
     if ((r = advance_one(ctx, &done)) != TC2_OK) {

@@ -46,7 +46,8 @@ class tc2_options(C.Structure):
                 ("mlp_threshold", C.c_float), ("log_capacity", C.c_int64),
                 ("wide_accumulate", C.c_int32), ("tune", C.c_int32), ("tune_cache", C.c_char_p),
                 ("graph", C.c_int32), ("metrics_log", C.c_char_p), ("count_useful", C.c_int32),
-                ("mlp_bound_cap", C.c_float), ("mlp_budget", C.c_double)]
+                ("mlp_bound_cap", C.c_float), ("mlp_budget", C.c_double),
+                ("device_loop", C.c_int32)]
 
 
 class tc2_result(C.Structure):
@@ -62,7 +63,8 @@ class tc2_result(C.Structure):
                 ("tile_shape", C.c_int32 * 4), ("ms_tune", C.c_double),
                 ("useful_flops_kind", C.c_double * 4), ("ms_numeric_kind", C.c_double * 4),
                 ("numeric_launches_kind", C.c_int32 * 4), ("graph_updates", C.c_int32),
-                ("graph_captures", C.c_int32), ("nominal_flops", C.c_double),
+                ("graph_captures", C.c_int32), ("device_loop_updates", C.c_int32),
+                ("nominal_flops", C.c_double),
                 ("branches", C.c_char * (TC2_MAX_ITER + 4)),
                 ("X0", tc2_bsr), ("X1", tc2_bsr * 3)]
 
@@ -239,6 +241,7 @@ class Result:
     union_flops: float = 0.0
     graph_captures: int = 0
     mlp_updates: int = 0
+    device_loop_updates: int = 0
 
     @property
     def status_name(self) -> str:
@@ -275,7 +278,7 @@ class Solver:
                  mlp_threshold: float = 0.99, log_capacity: int = 0, wide: bool = False,
                  tune: bool = False, tune_cache: Optional[str] = None, graph: bool = False,
                  count_useful: bool = False, metrics_log: Optional[str] = None,
-                 mlp_bound_cap: float = 0.0, mlp_budget: float = 0.0):
+                 mlp_bound_cap: float = 0.0, mlp_budget: float = 0.0, device_loop: int = 0):
         if isinstance(systems, System):
             systems = [systems]
         self.systems = list(systems)
@@ -315,7 +318,8 @@ class Solver:
                            int(log_capacity), 1 if wide else 0, 1 if tune else 0,
                            tune_cache.encode() if tune_cache else None, 1 if graph else 0,
                            metrics_log.encode() if metrics_log else None,
-                           1 if count_useful else 0, float(mlp_bound_cap), float(mlp_budget))
+                           1 if count_useful else 0, float(mlp_bound_cap), float(mlp_budget),
+                           int(device_loop))
         self.log_capacity = int(log_capacity)
         self._ctx = C.c_void_p()
         st = lib().tc2_setup(probs, n, C.byref(opts), C.byref(self._ctx))
@@ -337,7 +341,7 @@ class Solver:
                               list(r.useful_flops_kind), list(r.ms_numeric_kind),
                               list(r.numeric_launches_kind), r.graph_updates, x0, x1,
                               r.nominal_flops, r.union_flops, r.graph_captures,
-                              r.mlp_updates))
+                              r.mlp_updates, r.device_loop_updates))
         return out
 
     def run(self, stream: Optional[int] = None, check: bool = True) -> List[Result]:

@@ -114,6 +114,9 @@ def test_rejects_bad_options():
     assert _setup_status(small(), replay=["SX"]) == -1
     # FP64 sums of the per-block FP32 products exist in the tiled kernel only
     assert _setup_status(small(), precision="fp32", wide=True, kernel="block") == -1
+    # updates between two polls of the device-side decisions: 0..TC2_MAX_ITER
+    assert _setup_status(small(), device_loop=-1) == -1
+    assert _setup_status(small(), device_loop=T.TC2_MAX_ITER + 1) == -1
 
 
 def test_valid_problem_needs_a_device():

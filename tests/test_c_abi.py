@@ -65,3 +65,32 @@ def test_c_caller_matches_the_oracle(tmp_path):
     assert branches == o.branches and int(iters) == o.iters
     assert abs(float(alpha) - o.alpha[0]) <= 1e-10 * abs(o.alpha[0])
     assert abs(float(tr) - na) < 1e-8
+
+
+def test_ctypes_structs_match_the_c_layout(tmp_path):
+    # the binding's structures against gcc's layout of include/tc2.h: sizes
+    # and the offset of every field of the option, problem and result structs
+    import ctypes as C
+    structs = {"tc2_options": T.tc2_options, "tc2_problem": T.tc2_problem,
+               "tc2_result": T.tc2_result, "tc2_bsr": T.tc2_bsr}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "tc2.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'  printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = str(tmp_path / "layout")
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        "-o", exe, str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, out):
+        name, field, val = line.split()
+        cls = structs[name]
+        want = C.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert int(val) == want, (name, field, int(val), want)
+        seen += 1
+    assert seen == sum(len(c._fields_) + 1 for c in structs.values())
