@@ -98,3 +98,20 @@ def test_device_decisions_fall_back_to_the_host(variant):
     got = T.solve(s, graph=True, device_loop=4, **variant)[0]
     same(got, ref)
     assert got.device_loop_updates == 0
+
+
+@pytest.mark.parametrize("case", ["chain", "cube_three_directions"])
+def test_device_decisions_against_the_oracle(case):
+    # the device's branches, update count and status against the oracle's
+    # own rule, and X1 and alpha against the oracle's iterate
+    from oracle import tc2_oracle as O
+    s = (W.config_system("chain64", n=24) if case == "chain"
+         else W.config_system("cube10", L=3, n_dir=3))
+    g = T.solve(s, graph=True, skip="bound", device_loop=3)[0]
+    o = O.solve_system(s)
+    print(f"  {case}: {g.status_name} it={g.iters} {g.branches} (oracle {o.branches})", flush=True)
+    assert g.device_loop_updates == g.iters
+    assert g.branches == o.branches and g.iters == len(o.branches) and g.status == o.status
+    for d in range(len(s.H1)):
+        assert np.abs(T.bsr_dense(g.X1[d]) - o.X1[d]).max() < 1e-9
+        assert abs(g.alpha[d] - o.alpha[d]) <= 1e-10 * abs(o.alpha[d])
