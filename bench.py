@@ -567,9 +567,10 @@ def main() -> int:
     tile_kw = (dict(tune=args.tune, tune_cache=args.tune_cache, graph=bool(args.graph))
                if args.kernel == "tile" else {})
     # plain FP64 path (every candidate block computed): the reference of the
-    # gate and of the speed-up.  Both sides run with profile = 1 (kernel
-    # timing by events), so that they are timed the same way.
-    ref_kw = dict(precision="fp64", kernel=args.kernel, profile=True, **tile_kw)
+    # gate and of the speed-up.  Both sides are timed the same way, without
+    # kernel events or the useful-product count; those come from a separate,
+    # untimed run of the chosen variant over the same (deterministic) updates.
+    ref_kw = dict(precision="fp64", kernel=args.kernel, **tile_kw)
     chosen = args.precision
     closing = 0 if chosen == "fp64" else 2
     theta = None
@@ -584,12 +585,14 @@ def main() -> int:
             f"{losses[0]:.4f} -> {losses[-1]:.4f}, {time.perf_counter() - t0:.1f} s")
     variant = dict(precision=chosen, closing_fp64=closing, kernel=args.kernel, skip=args.skip,
                    fp64_first=args.fp64_first if chosen != "fp64" else 0,
-                   wide=bool(args.wide and chosen != "fp64"), profile=True, count_useful=True)
+                   wide=bool(args.wide and chosen != "fp64"))
     if args.kernel == "tile":
         variant.update(tile_kw)
     if theta is not None:
         variant.update(mlp_weights=theta, mlp_threshold=args.mlp_threshold,
                        mlp_bound_cap=args.mlp_cap, mlp_budget=args.mlp_budget)
+    # the measurement run: kernel times by events and the exact useful count
+    meas_kw = dict(variant, profile=True, count_useful=True)
     # references solved once per unit, their X1 kept on the host for the gate
     refs = []
     if not args.no_reference:
@@ -651,7 +654,6 @@ def main() -> int:
         elapsed = time.perf_counter() - t0
         if r:
             done.append(r)
-        timed_useful = p["useful_flops"]
         timed_exec = p["executed_flops"]
         assert p["updates"] == args.steps
         # finish the solve in progress (untimed): its iterate is the one gated
@@ -663,12 +665,30 @@ def main() -> int:
         for name, res, snap in per_unit:
             add_gate(name, gate(sv, snap, results, res, name, sysm.eps))
         sv.close()
+        # the same updates again, untimed, with the useful-product count and
+        # kernel events: the useful flops of the timed updates, kernel times
+        mv = T.Solver(u, export=False, **meas_kw)
+        mdone = []
+        pm, r = mv.advance(args.warmup, stream=stream)
+        if r:
+            mdone.append(r)
+        pm, r = mv.advance(args.steps, stream=stream)
+        if r:
+            mdone.append(r)
+        timed_useful = pm["useful_flops"]
+        while pm["solve_open"] or not mdone:
+            pm, r = mv.advance(1, stream=stream)
+            if r:
+                mdone.append(r)
+        mv.close()
+        assert mdone[-1][0].branches == results[0].branches
         ms_per_step = elapsed / args.steps * 1e3
         value = timed_useful / elapsed / 1e9
         s_solve = sum(x.seconds for x in results[:1])
         log(f"{chosen}: {args.steps} updates in {elapsed:.3f} s ({ms_per_step:.1f} ms/update), "
             f"useful {timed_useful / 1e12:.3f} TF -> {value:.1f} GFLOP/s; solve "
             f"{results[0].iters} updates {results[0].branches} in {s_solve:.2f} s")
+        results = mdone[-1]
         per = [[results]]
     else:
         # ---- batches: steps are solves of every unit, one unit at a time
@@ -687,15 +707,19 @@ def main() -> int:
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / args.steps
             total_s += dt
-            timed_useful += sum(x.useful_flops for x in res[-1])
             timed_exec += sum(x.executed_flops for x in res[-1])
             for name, rres, snap, wall in rdone:
                 add_gate(name, gate(sv, snap, res[-1], rres, name, sysm.eps))
             sv.close()
+            # one untimed solve with the useful-product count and kernel events
+            mv = T.Solver(u, export=False, **meas_kw)
+            mres = mv.run(stream=stream)
+            mv.close()
+            timed_useful += sum(x.useful_flops for x in mres)
             log(f"  unit of {len(u)} systems / {sum(x.H.nb for x in u)} atoms: {dt:.2f} s/solve; "
                 f"gate so far {gates}")
-            results += res[-1]
-            per.append(res)
+            results += mres
+            per.append([mres])
         elapsed = total_s * args.steps
         ms_per_step = total_s * 1e3
         s_solve = total_s
