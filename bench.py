@@ -412,6 +412,17 @@ def snapshot(solver, D: int, chunk: int = 1 << 20):
     return rows, cols, vals
 
 
+def export_time(solver, D: int, chunk: int = 1 << 20) -> float:
+    """Seconds to copy every entry of X0 and of each X1_d of the current
+    iterate (rows, columns, b x b values) to host memory, in chunks."""
+    n = solver.iterate_size()
+    t0 = time.perf_counter()
+    for m in range(1 + D):
+        for f in range(0, n, chunk):
+            solver.export_entries(m, f, min(chunk, n - f))
+    return time.perf_counter() - t0
+
+
 def gate(solver, snap, res, ref_res, name: str, eps: float) -> dict:
     """max |dX1| over the union of the patterns (on the device) and relative
     |d alpha| of the chosen variant's last solve against a reference.  The
@@ -642,7 +653,9 @@ def main() -> int:
             ref_s[name] = res[0].seconds
             refs_done = (name, res, snap)
             per_unit.append(refs_done)
+        t0 = time.perf_counter()
         sv = T.Solver(u, export=False, metrics_log=args.metrics_log, **variant)
+        setup_s = time.perf_counter() - t0  # validation, host set-up, upload
         done = []
         p, r = sv.advance(args.warmup, stream=stream)
         if r:
@@ -662,6 +675,7 @@ def main() -> int:
             if r:
                 done.append(r)
         results = done[-1]
+        export_s = export_time(sv, D)
         for name, res, snap in per_unit:
             add_gate(name, gate(sv, snap, results, res, name, sysm.eps))
         sv.close()
@@ -694,6 +708,7 @@ def main() -> int:
         # ---- batches: steps are solves of every unit, one unit at a time
         total_s, per = 0.0, []
         timed_useful = timed_exec = 0.0
+        setup_s = export_s = None
         for u in units:
             rdone = solve_refs(u)
             for name, res, snap, wall in rdone:
@@ -805,6 +820,13 @@ def main() -> int:
                      "useful_tflop_per_solve": round(dom_flops / 1e12, 4),
                      "all_numeric_ms_per_kind": [round(x, 3) for x in ms_kind]},
     }
+    if setup_s is not None:
+        # from host buffers to host results: tc2_setup (validation, host
+        # set-up, upload), one solve, and every entry of X0 and X1 copied back
+        tot = setup_s + s_solve + export_s
+        out["pcie_inclusive"] = {"setup_s": round(setup_s, 3), "solve_s": round(s_solve, 3),
+                                 "export_s": round(export_s, 3), "total_s": round(tot, 3),
+                                 "useful_gflops": round(useful / tot / 1e9, 3)}
     if not args.no_cpu_baseline:
         if len(systems) == 1 and sysm.H.n <= 20000:
             log("cpu baseline (dense oracle) ...")
