@@ -57,10 +57,21 @@ def test_device_decisions_batch_with_systems_stopping_apart():
     assert all(g.device_loop_updates == max(r.iters for r in ref) for g in got)
 
 
-@pytest.mark.parametrize("case", ["single_atom", "max_iter", "ragged_chain", "mixed_batch"])
+@pytest.mark.parametrize("case", ["single_atom", "max_iter", "ragged_chain", "mixed_batch",
+                                  "no_direction", "first_update_stop", "many_systems"])
 def test_device_decisions_edge_cases(case):
     if case == "single_atom":
         systems = W.config_system("chain64", n=1)
+    elif case == "no_direction":
+        systems = W.config_system("chain64", n=20, n_dir=0)
+    elif case == "first_update_stop":
+        # max_iter = 1 stops one system after its first update, beside others
+        a = W.config_system("chain64", n=12)
+        a.max_iter = 1
+        systems = [a, W.config_system("chain64", n=9), W.config_system("chain64", n=16, seed=9)]
+    elif case == "many_systems":
+        # more systems than the decision kernel's 256 threads (its stride loop)
+        systems = [W.config_system("chain64", n=2 + k % 3, seed=100 + k) for k in range(300)]
     elif case == "max_iter":
         systems = W.config_system("chain64", n=16)
         systems.max_iter = 3
@@ -74,6 +85,10 @@ def test_device_decisions_edge_cases(case):
     ref, got = both(systems, 2)
     if case == "max_iter":
         assert ref[0].status_name == "NOT_CONVERGED" and ref[0].iters == 3
+    if case == "first_update_stop":
+        assert ref[0].iters == 1 and ref[1].iters > 1
+    if case != "single_atom":
+        assert max(g.device_loop_updates for g in got) == max(r.iters for r in ref) > 0
 
 
 def test_device_decisions_repeated_runs_replay_their_graphs():
