@@ -293,7 +293,7 @@ struct tc2_ctx {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipGraphExec_t gexec_post[2] = {nullptr, nullptr};  // profiling: the part after the products
   std::vector<unsigned long long> gkey[2];
-  long long kept_prev = 0, kept_prev2 = 0;  // kept upper blocks of the last updates
+  long long kept_prev = 0, kept_prev2 = 0, kept_prev3 = 0;  // kept upper blocks, last updates
   int graph_updates = 0, graph_captures = 0;
   // branch and stopping decisions on the device (device_loop): per-system
   // records, parameters and the flag word the host polls

@@ -1123,8 +1123,8 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   ctx->last_kind = kind;
   const long long nnz_c = ctx->nnz[c];
 
-  // kept-block estimate: the last count grown by the last growth factor;
-  // with the decisions on the device, the dense bound (no update can
+  // kept-block estimate: the last count grown by the larger of the last two
+  // growth factors; with the decisions on the device, the dense bound (no update can
   // overflow it, so none needs a size from the host)
   long long est;
   if (dl) {
@@ -1132,8 +1132,16 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   } else if (ctx->kept_prev == 0) {
     est = 2 * nnz_c + 1024;
   } else {
-    double g = ctx->kept_prev2 > 0 ? (double)ctx->kept_prev / (double)ctx->kept_prev2 : 2.0;
-    g = std::min(2.0, std::max(1.0, g));
+    // the larger of the last two growth factors: the growth of the kept
+    // count varies from one update to the next (cube30: 2.45, 1.98, 1.07,
+    // 1.53, 1.10, 1.43, ...), and an update that overflows its stage runs
+    // its products again; 2.5 after the first update
+    double g = 2.5;
+    if (ctx->kept_prev2 > 0) {
+      g = (double)ctx->kept_prev / (double)ctx->kept_prev2;
+      if (ctx->kept_prev3 > 0) g = std::max(g, (double)ctx->kept_prev2 / (double)ctx->kept_prev3);
+    }
+    g = std::min(2.5, std::max(1.0, g));
     est = (long long)(ctx->kept_prev * g * 1.1) + 1024;
   }
   // geometric buckets (steps of 2^(1/4)): the capacity is part of the graph
@@ -1473,6 +1481,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     ctx->screened_total += sc[0];
     ctx->mlp_total += sc[1];
   }
+  ctx->kept_prev3 = ctx->kept_prev2;
   ctx->kept_prev2 = ctx->kept_prev;
   ctx->kept_prev = hcnt[1];
   ctx->stage_cap = std::max<long long>(ctx->stage_cap, (long long)hcnt[1] * 5 / 4 + 1024);
@@ -1554,7 +1563,7 @@ tc2_status begin_solve(tc2_ctx* ctx, hipStream_t st) {
   }
   ctx->ms_tune = 0.0;
   ctx->prev_out_bound = -1;
-  ctx->kept_prev = ctx->kept_prev2 = 0;
+  ctx->kept_prev = ctx->kept_prev2 = ctx->kept_prev3 = 0;
   ctx->dl_updates = 0;
   ctx->graph_updates = 0;
   ctx->graph_captures = 0;
@@ -2097,7 +2106,7 @@ tc2_status run_device_loop(tc2_ctx* ctx, bool* used) {
   int nnz_now = 0;
   memcpy(&nnz_now, pin + off_nnz, 4);
   ctx->nnz[ctx->cur] = nnz_now;
-  ctx->kept_prev = ctx->kept_prev2 = 0;
+  ctx->kept_prev = ctx->kept_prev2 = ctx->kept_prev3 = 0;
   R.updates += w.updates;
   R.exec_pairs += w.exec_pairs;
   ctx->screened_total += w.screened[0];
