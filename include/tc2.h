@@ -341,8 +341,8 @@ TC2_API void tc2_free(tc2_ctx *ctx);
    Large buffers of every context map physical memory in fixed chunks; the
    chunks a buffer or a freed context gives back stay in a per-device pool of
    the process and are mapped again by later buffers and contexts, so that
-   the driver does not clear reclaimed memory before each reuse.  The pool
-   is returned to the driver when an allocation of the library fails for lack
+   the GPU driver does not clear reclaimed memory before each reuse.  The pool
+   is returned to the GPU driver when an allocation of the library fails for lack
    of memory (then retried), and by this call: device = HIP ordinal.  Returns
    TC2_EINVAL for an ordinal without a device.  Call it when other code of the
    process needs the memory; no context of the library needs to be freed.  */

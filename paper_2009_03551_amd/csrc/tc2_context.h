@@ -23,7 +23,7 @@ constexpr size_t VM_MIN = (size_t)64 << 20;
 hipError_t vm_grow(DBuf& b, size_t n);     // map up to >= n bytes, contents kept
 void vm_release(DBuf& b);                  // chunks back to the pool, range freed
 hipError_t dev_malloc(void** p, size_t n); // hipMalloc, retried after pool_trim
-void pool_trim();                          // pooled chunks of the device to the driver
+void pool_trim();                          // pooled chunks of the device to the GPU driver
 
 struct DBuf {
   void* p = nullptr;

@@ -3,7 +3,7 @@
 // A solve grows its large buffers (the iterate's values, the stage of kept
 // blocks, the work arrays) over many updates, and a precision switch or a
 // new context releases and re-requests tens of gigabytes.  Freeing a large
-// allocation and asking for a larger one makes the driver clear memory it has
+// allocation and asking for a larger one makes the GPU driver clear memory it has
 // just reclaimed, at a few tens of GB/s, which stalls the device for seconds
 // at the largest sizes.  Large buffers here therefore live in a virtual
 // address range reserved once per buffer; physical memory is mapped into it
@@ -12,7 +12,7 @@
 // device and are mapped again by the next buffer that grows, within the same
 // solve or in a later context (a later context would otherwise wait for the
 // driver to clear the memory again: up to 2.6 s for one chunk at 256 MB after
-// a large context was freed).  The pool is returned to the driver when an
+// a large context was freed).  The pool is returned to the GPU driver when an
 // allocation of the library fails for lack of memory (and then retried), and
 // by tc2_trim_memory, for callers whose other allocations need the memory.
 #include "tc2_context.h"
@@ -73,7 +73,7 @@ Pool* pool_of(int* dev_out) {
 
 }  // namespace
 
-// Return every pooled chunk of the current device to the driver.
+// Return every pooled chunk of the current device to the GPU driver.
 void pool_trim() {
   int dev = 0;
   Pool* P = pool_of(&dev);
