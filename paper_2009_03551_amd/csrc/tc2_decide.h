@@ -19,6 +19,9 @@
 #include "tc2_internal.h"
 #include "../../include/tc2.h"
 
+#define TC2_HD __host__ __device__
+#include "tc2_decide_rule.h"
+
 namespace tc2 {
 
 struct DecideSys {

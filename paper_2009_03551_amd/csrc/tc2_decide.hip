@@ -38,36 +38,12 @@ __global__ void __launch_bounds__(256) k_decide(DecideArgs a) {
       S.branches[S.k] = a.branch[s] ? 'S' : 'D';
       S.branches[S.k + 1] = 0;
     }
-    const int k = ++S.k;
     S.trip += q[Q_TRIP];
     S.nominal += a.nominal[s];
-    double dmax = 0.0;
-    for (int m = 0; m < 1 + 2 * D; ++m) {
-      const double v = fabs(cur[m] - S.prev[m]);
-      dmax = dmax < v ? v : dmax;
-      S.prev[m] = cur[m];
-    }
-    const double iota = q[Q_TR0] - q[Q_FRO0];
-    const double iota_km2 = S.iota2;  // iota two updates back (k >= 3)
-    S.iota2 = S.iota1;
-    S.iota1 = iota;
-    int stop = 0;
-    if (a.bad[s]) {
-      S.status = TC2_ENAN;
-      stop = 1;
-    } else {
-      if (k >= 2 && dmax < P.tol) {
-        S.status = TC2_OK;
-        stop = 1;
-      } else if (k >= 3 && fabs(iota) < 1.0 && fabs(iota) >= fabs(iota_km2)) {
-        S.status = TC2_FLOOR_REACHED;
-        stop = 1;
-      } else if (k >= P.max_iter) {
-        S.status = TC2_NOT_CONVERGED;
-        stop = 1;
-      }
-      a.branch[s] = q[Q_TR0] >= P.n_occ ? 1 : 0;
-    }
+    const int bad = a.bad[s];
+    const int stop = tc2_decide_rule(D, cur, q[Q_TR0] - q[Q_FRO0], bad, P.tol, P.max_iter, S.prev,
+                                     &S.iota1, &S.iota2, &S.k, &S.status);
+    if (!bad) a.branch[s] = q[Q_TR0] >= P.n_occ ? 1 : 0;
     if (stop) a.active[s] = 0;
     else atomicOr(&any, 1);
   }
