@@ -176,9 +176,10 @@ typedef struct {
                               tc2_advance) the host decides.  A batch ends at
                               the update count of the context's last such
                               solve, and past it the word is polled after
-                              every update; otherwise up to k - 1 updates
-                              after the last system stops copy the iterate
-                              unchanged.  Results are identical              */
+                              every update; the first such solve of a context
+                              polls at least every 4 updates.  Updates
+                              launched after the last system stops copy the
+                              iterate unchanged.  Results are identical      */
 } tc2_options;
 
 /* Largest stage (kept upper blocks x (1 + n_dir) padded 16 x 16 FP64 blocks)

@@ -2056,13 +2056,15 @@ tc2_status run_device_loop(tc2_ctx* ctx, bool* used) {
   // batches of device_loop updates; within the update count of the last
   // device-loop solve of this context, a batch ends there, and past it the
   // flag word is polled after every update, so that a solve like the last
-  // one launches no update after its last stop
+  // one launches no update after its last stop.  Without such a solve,
+  // batches of at most 4 bound the updates launched after the last stop.
   const int expect = ctx->dl_last;
   bool handed_over = false;
   int launched = 0;
   for (;;) {
     int batch = ctx->device_loop;
     if (expect > 0) batch = launched < expect ? std::min(batch, expect - launched) : 1;
+    else batch = std::min(batch, 4);
     for (int k = 0; k < batch && launched < max_it; ++k, ++launched) {
       const int g = step_graph(ctx, st, R.scal, R.exec_pairs, true);
       if (g == 1) {
