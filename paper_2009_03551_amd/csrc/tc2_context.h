@@ -328,5 +328,11 @@ tc2_status mask_iterate(tc2_ctx* ctx, hipStream_t st);
 // The same for nnz entries of xv (at most *nnz_dev when given), as stream work.
 void launch_block_masks(hipStream_t st, int prec, long long nnz, int D, const void* xv,
                         unsigned char* mask, const int* nnz_dev);
+// The gather of the new values from the stage (at most nnz entries, *nnz_dev
+// when given) together with their masks, in one pass; nothing is written
+// when *skip_flag is set (an overflowed stage: the update runs again).
+void launch_gather_masks(hipStream_t st, int prec, long long nnz, int D, const int* new_src,
+                         const void* stage, void* xv, unsigned char* mask, const int* nnz_dev,
+                         const int* skip_flag);
 
 }  // namespace tc2

@@ -1053,11 +1053,14 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   ca.new_src = ctx->new_src.as<int>();
   launch_compact_scatter(st, ca, n_kept);
   launch_row_sort(st, ca);
-  launch_gather(st, ctx->cur_prec, nnz_new, D, ctx->new_src.as<int>(), ctx->stage.p, ctx->xv[c].p);
+  // the new values and the masks of their nonzero matrices, in one pass
+  HIPCHK(ctx->mask[n].reserve((size_t)std::max(nnz_new, 1)));
+  launch_gather_masks(st, ctx->cur_prec, nnz_new, D, ctx->new_src.as<int>(), ctx->stage.p,
+                      ctx->xv[c].p, ctx->mask[n].as<unsigned char>(), nullptr, nullptr);
+  HIPCHK(hipGetLastError());
   ctx->xv[c].swap(ctx->xv[n]);
   ctx->nnz[n] = nnz_new;
   ctx->cur = n;
-  if (tc2_status r = mask_iterate(ctx, st); r != TC2_OK) return r;
   if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[1], st));
 
   // ---- per-system scalars of the new iterate
@@ -1351,12 +1354,12 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       launch_scan(st, nb, ctx->rowcnt.as<int>(), ctx->rp[n].as<int>(), cnt);
       launch_compact_scatter(st, cm, cap);
       launch_row_sort(st, cm);
-      // the gather writes over the current values: skipped when the stage
-      // overflowed (the update is then run again from those values)
-      launch_gather(st, ctx->cur_prec, (int)cap2, D, ctx->new_src.as<int>(), ctx->stage.p,
-                    ctx->xv[c].p, ctx->rp[n].as<int>() + nb, cnt + 2);
-      launch_block_masks(st, ctx->cur_prec, (long long)cap2, D, ctx->xv[c].p,
-                         ctx->mask[n].as<unsigned char>(), ctx->rp[n].as<int>() + nb);
+      // the gather (with the masks of the new values) writes over the current
+      // values: skipped when the stage overflowed (the update is then run
+      // again from those values)
+      launch_gather_masks(st, ctx->cur_prec, (long long)cap2, D, ctx->new_src.as<int>(),
+                          ctx->stage.p, ctx->xv[c].p, ctx->mask[n].as<unsigned char>(),
+                          ctx->rp[n].as<int>() + nb, cnt + 2);
       launch_reduce(st, ctx->nsys, ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>(),
                     ctx->partial.as<double>(), ctx->scal.as<double>());
       if (dl) {
