@@ -258,6 +258,8 @@ struct tc2_ctx {
   tc2::DBuf mlp_bsum;             // per system: that sum so far in this solve
   int mlp_updates = 0;            // updates run with the network in this solve
   tc2::DBuf bn, screened;         // block norms, skip counters [exact, network]
+  bool bn_valid = false;          // bn holds the norms of the current iterate
+                                  // (written by the last captured update's gather)
   tc2::DBuf nominal;              // per system: sum over rows K of m_K^2, this update
   unsigned long long screened_total = 0, mlp_total = 0;
   tc2::DBuf mlp;                  // skip network parameters
@@ -329,10 +331,11 @@ tc2_status mask_iterate(tc2_ctx* ctx, hipStream_t st);
 void launch_block_masks(hipStream_t st, int prec, long long nnz, int D, const void* xv,
                         unsigned char* mask, const int* nnz_dev);
 // The gather of the new values from the stage (at most nnz entries, *nnz_dev
-// when given) together with their masks, in one pass; nothing is written
-// when *skip_flag is set (an overflowed stage: the update runs again).
+// when given) together with their masks and, bn given, their block norms (as
+// k_block_norms computes them), in one pass; nothing is written when
+// *skip_flag is set (an overflowed stage: the update runs again).
 void launch_gather_masks(hipStream_t st, int prec, long long nnz, int D, const int* new_src,
-                         const void* stage, void* xv, unsigned char* mask, const int* nnz_dev,
-                         const int* skip_flag);
+                         const void* stage, void* xv, unsigned char* mask, float* bn,
+                         const int* nnz_dev, const int* skip_flag);
 
 }  // namespace tc2

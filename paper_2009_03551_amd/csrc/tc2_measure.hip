@@ -54,41 +54,47 @@ __global__ void k_block_masks(long long nnz, int D, const T* __restrict__ xv,
   }
 }
 
-// New entry e <- its staged block, with the mask of its nonzero matrices, in
-// one pass, one wave per entry.  The stage holds C_IJ row-major: entry (I, J)
-// needs it column-major (a transpose), the mirrored entry (J, I) needs C_IJ^T
-// column-major, i.e. the stage as it is (bit 0 of new_src).  Lane l copies
-// elements 4l .. 4l + 3 of each tile (one column segment, a 4-vector store)
-// and tests them for nonzeros, as k_block_masks does on the copied values.
-// An update whose stage overflowed is run again: then nothing is written.
+// New entry e <- its staged block, with the mask of its nonzero matrices and
+// (bn given) the Frobenius norm of each of its blocks, in one pass, one wave
+// per entry.  The stage holds C_IJ row-major: entry (I, J) needs it
+// column-major (a transpose), the mirrored entry (J, I) needs C_IJ^T
+// column-major, i.e. the stage as it is (bit 0 of new_src).  Lane l handles
+// elements l + 64 j of each tile, as k_block_masks and k_block_norms do, and
+// sums their squares in the same order with the same wave reduction, so the
+// norms equal theirs bit for bit.  An update whose stage overflowed is run
+// again: then nothing is written.
 template <typename T>
 __global__ void k_gather_masks(long long nnz, int D, const int* __restrict__ new_src,
                                const T* __restrict__ stage, T* __restrict__ xv,
-                               unsigned char* __restrict__ mask, const int* nnz_dev,
-                               const int* skip_flag) {
+                               unsigned char* __restrict__ mask, float* __restrict__ bn,
+                               const int* nnz_dev, const int* skip_flag) {
   if (skip_flag && *skip_flag) return;
-  typedef T T4 __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
   if (nnz_dev) nnz = min(nnz, (long long)*nnz_dev);
   const int per = (1 + D) * BS;
-  const int qd = lane * 4;  // c * 16 + r, r % 4 == 0
-  const int c = qd >> 4, r = qd & 15;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
   for (long long e = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < nnz; e += nwaves) {
     const int src = new_src[e];
     unsigned bits = 0u;
     for (int m = 0; m <= D; ++m) {
       const T* sb = stage + (size_t)(src >> 1) * per + m * BS;
-      T4 v;
-      if (src & 1) {
-        v = *(const T4*)(sb + qd);
-      } else {
+      T* xb = xv + (size_t)e * per + m * BS;
+      bool nz = false;
+      double ss = 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = sb[(r + i) * BP + c];
+      for (int j = 0; j < 4; ++j) {
+        const int q = lane + 64 * j;  // c * 16 + r of the column-major tile
+        const T v = (src & 1) ? sb[q] : sb[(q & 15) * BP + (q >> 4)];
+        xb[q] = v;
+        nz |= v != (T)0;
+        const double dv = (double)v;
+        ss += dv * dv;
       }
-      *(T4*)(xv + (size_t)e * per + m * BS + qd) = v;
-      const bool nz = v[0] != (T)0 || v[1] != (T)0 || v[2] != (T)0 || v[3] != (T)0;
       if (__ballot(nz) != 0ull) bits |= 1u << m;
+      if (bn) {
+        ss = wave_sum(ss);
+        if (lane == 0) bn[(size_t)e * (1 + D) + m] = (float)sqrt(ss);
+      }
     }
     if (lane == 0) mask[e] = (unsigned char)bits;
   }
@@ -301,16 +307,16 @@ void launch_block_masks(hipStream_t st, int prec, long long nnz, int D, const vo
 }
 
 void launch_gather_masks(hipStream_t st, int prec, long long nnz, int D, const int* new_src,
-                         const void* stage, void* xv, unsigned char* mask, const int* nnz_dev,
-                         const int* skip_flag) {
+                         const void* stage, void* xv, unsigned char* mask, float* bn,
+                         const int* nnz_dev, const int* skip_flag) {
   if (nnz == 0) return;
   const unsigned g = grid_waves(nnz, 4);
   if (prec == P_FP64)
     hipLaunchKernelGGL(k_gather_masks<double>, dim3(g), dim3(256), 0, st, nnz, D, new_src,
-                       (const double*)stage, (double*)xv, mask, nnz_dev, skip_flag);
+                       (const double*)stage, (double*)xv, mask, bn, nnz_dev, skip_flag);
   else
     hipLaunchKernelGGL(k_gather_masks<float>, dim3(g), dim3(256), 0, st, nnz, D, new_src,
-                       (const float*)stage, (float*)xv, mask, nnz_dev, skip_flag);
+                       (const float*)stage, (float*)xv, mask, bn, nnz_dev, skip_flag);
 }
 
 tc2_status mask_iterate(tc2_ctx* ctx, hipStream_t st) {

@@ -568,6 +568,7 @@ namespace {
 
 // Copy the current iterate into fresh buffers of another precision.
 tc2_status convert_iterate(tc2_ctx* ctx, hipStream_t st, int to_prec) {
+  ctx->bn_valid = false;  // the norms of the converted values are taken anew
   int c = ctx->cur;
   long long n = (long long)ctx->nnz[c] * (1 + ctx->D) * BS;
   DBuf& dst = ctx->xv[c ^ 1];
@@ -1056,11 +1057,12 @@ tc2_status step(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   // the new values and the masks of their nonzero matrices, in one pass
   HIPCHK(ctx->mask[n].reserve((size_t)std::max(nnz_new, 1)));
   launch_gather_masks(st, ctx->cur_prec, nnz_new, D, ctx->new_src.as<int>(), ctx->stage.p,
-                      ctx->xv[c].p, ctx->mask[n].as<unsigned char>(), nullptr, nullptr);
+                      ctx->xv[c].p, ctx->mask[n].as<unsigned char>(), nullptr, nullptr, nullptr);
   HIPCHK(hipGetLastError());
   ctx->xv[c].swap(ctx->xv[n]);
   ctx->nnz[n] = nnz_new;
   ctx->cur = n;
+  ctx->bn_valid = false;
   if (ctx->profile) HIPCHK(hipEventRecord(ctx->pev[1], st));
 
   // ---- per-system scalars of the new iterate
@@ -1199,8 +1201,12 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
     // entries the value buffer can hold: a bound of the current entries for
     // the kernels that read their count from the device
     const long long cap_c = std::max<long long>((long long)(ctx->xv[c].cap / tile), 1);
+    // the gather of the last captured update wrote the block norms of the
+    // current iterate into bn, unless bn must grow now (growing drops them)
+    const size_t bn_need = (size_t)cap_c * (1 + D) * 4;
+    const bool norms_ready = screen && ctx->bn_valid && ctx->bn.p && ctx->bn.cap >= bn_need;
     if (screen) {
-      GRESERVE(ctx->bn.reserve((size_t)cap_c * (1 + D) * 4));
+      GRESERVE(ctx->bn.reserve(bn_need));
       GRESERVE(ctx->screened.reserve(16));
     }
     GRESERVE(ctx->scal.reserve((size_t)ctx->nsys * NQ * 8));
@@ -1212,6 +1218,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
         (unsigned long long)kind, (unsigned long long)shape, (unsigned long long)screen,
         (unsigned long long)any_stopped, (unsigned long long)cap, (unsigned long long)cap_c,
         (unsigned long long)ctx->profile, (unsigned long long)(uintptr_t)st, (unsigned long long)dl,
+        (unsigned long long)norms_ready,
         (uintptr_t)ctx->xv[c].p, (uintptr_t)ctx->rp[c].p, (uintptr_t)ctx->ci[c].p,
         (uintptr_t)ctx->rp[n].p, (uintptr_t)ctx->ci[n].p,
         (uintptr_t)ctx->panel_k.p, (uintptr_t)ctx->panel_e.p, (uintptr_t)ctx->tile_p.p,
@@ -1262,8 +1269,9 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
                        ctx->tile_rp.as<int>(), ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>());
       if (screen) {
         launch_fill_int(st, ctx->screened.as<int>(), 0, 4);
-        launch_block_norms(st, ctx->cur_prec, cap_c, D, ctx->xv[c].p, ctx->bn.as<float>(),
-                           ctx->rp[c].as<int>() + nb);
+        if (!norms_ready)
+          launch_block_norms(st, ctx->cur_prec, cap_c, D, ctx->xv[c].p, ctx->bn.as<float>(),
+                             ctx->rp[c].as<int>() + nb);
       }
       launch_fill_int(st, cnt, 0, 8);
       launch_fill_int(st, ctx->exec_pairs.as<int>(), 0, 2);
@@ -1359,7 +1367,8 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       // again from those values)
       launch_gather_masks(st, ctx->cur_prec, (long long)cap2, D, ctx->new_src.as<int>(),
                           ctx->stage.p, ctx->xv[c].p, ctx->mask[n].as<unsigned char>(),
-                          ctx->rp[n].as<int>() + nb, cnt + 2);
+                          screen ? ctx->bn.as<float>() : nullptr, ctx->rp[n].as<int>() + nb,
+                          cnt + 2);
       launch_reduce(st, ctx->nsys, ctx->sys_lo.as<int>(), ctx->sys_hi.as<int>(),
                     ctx->partial.as<double>(), ctx->scal.as<double>());
       if (dl) {
@@ -1445,6 +1454,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
       // host polls their flag word every device_loop updates
       ctx->xv[c].swap(ctx->xv[n]);
       ctx->cur = n;
+      ctx->bn_valid = screen;
       return TC2_OK;
     }
     // counters, pairs, new entries, screen counts and scalars, read back
@@ -1491,6 +1501,7 @@ int step_graph(tc2_ctx* ctx, hipStream_t st, std::vector<double>& scal,
   ctx->xv[c].swap(ctx->xv[n]);
   ctx->nnz[n] = nnz_new;
   ctx->cur = n;
+  ctx->bn_valid = screen;  // the gather wrote the new iterate's block norms
   ctx->graph_updates++;
   if (ctx->verbose)
     fprintf(stderr, "tc2 step (graph): kept=%d pairs=%llu new entries=%d captures=%d\n", hcnt[1],
@@ -1568,6 +1579,7 @@ tc2_status begin_solve(tc2_ctx* ctx, hipStream_t st) {
   ctx->prev_out_bound = -1;
   ctx->kept_prev = ctx->kept_prev2 = ctx->kept_prev3 = 0;
   ctx->dl_updates = 0;
+  ctx->bn_valid = false;
   ctx->graph_updates = 0;
   ctx->graph_captures = 0;
   for (bool& u : ctx->kind_used) u = false;
